@@ -1,0 +1,165 @@
+/*
+ * pbpqlp.h -- C ABI of the MI355X (gfx950) PbP-QLP library, libpbpqlp.so.
+ *
+ * Projection-based Partial QLP (Kaloorazi & Chen, IEEE TSP 2021,
+ * arXiv 2103.07245).  Given an m x n matrix A and 1 <= k <= l = k + p, the
+ * method (Section III, Algorithm 1, here applied to A^T so that Omega has n
+ * rows) computes
+ *     Omega = randn(n, l)            Y = A Omega            Q = orth(Y)
+ *     q times:  Z = A^T Q,  P^ = orth(Z),  Y = A P^,  Q = orth(Y)
+ *     B^T = A^T Q = P R              (unpivoted QR, eqs. (D), (DQR))
+ *     R^T = Qt L^T                   (unpivoted QR, eq. (R^T = Pt Rt))
+ * and returns Q Qt (m x l), the lower-triangular L (l x l) and P (n x l) with
+ *     A ~= (Q Qt) L^T P^T                                 (eq. (Ahat) for A^T)
+ * where diag(L) approximates the leading singular values of A.  orth() and
+ * both QRs are upper-triangular (nested-span) factorizations with a
+ * non-negative diagonal, so every output is unique whenever the sketch has
+ * full rank.
+ *
+ * Conventions for every entry point:
+ *   - All matrix arguments are DEVICE pointers, row-major, with a leading
+ *     dimension (elements between consecutive rows) >= the row length.
+ *   - The caller owns every buffer; the library never frees caller memory
+ *     and keeps no pointer after the call returns.
+ *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
+ *     the default stream) and the call returns without synchronizing.
+ *     Argument errors are reported synchronously by the return code before
+ *     anything is enqueued; numerical conditions (dependent columns that had
+ *     to be completed, non-finite input) are reported asynchronously in the
+ *     device-resident pbpqlp_info, which is valid once the stream reaches the
+ *     end of the call.
+ *   - Outputs must not alias inputs.  No C++ exception crosses this ABI.
+ */
+#ifndef PBPQLP_H
+#define PBPQLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PBPQLP_OK = 0,
+  PBPQLP_EINVAL = 1,       /* an argument breaks the rules stated below            */
+  PBPQLP_ENOMEM = 2,       /* caller workspace too small, or device allocation failed */
+  PBPQLP_EHIP = 3,         /* a HIP runtime call or kernel launch failed           */
+  PBPQLP_EUNSUPPORTED = 4  /* valid input outside this build's limits (l > 256, ...) */
+} pbpqlp_status;
+
+/* Storage type of A and of the tall outputs Q and P. */
+typedef enum { PBPQLP_F64 = 0, PBPQLP_F32 = 1 } pbpqlp_dtype;
+
+/* Arithmetic of one A-streaming pass (products with A or A^T).
+ *   NATIVE : the storage type (FP64 or FP32 matrix cores).
+ *   BF16   : A and the l-column operand rounded to bfloat16 (RNE), FP32 accumulate.
+ *   FP16   : the same in IEEE half; A is multiplied by opts.fp16_scale_a (a power
+ *            of two) before rounding, so the caller keeps |A| inside half range.
+ *   BF16X3 : split products hi*hi + hi*lo + lo*hi of bfloat16 pieces
+ *            (hi = bf16(x), lo = bf16(x - hi)), FP32 accumulate: close to FP32.
+ * The reduced precisions apply to PBPQLP_F32 storage only.  Grams, Cholesky
+ * factors, triangular solves and the l x l QR always run in FP64 / FP32. */
+typedef enum {
+  PBPQLP_PREC_NATIVE = 0,
+  PBPQLP_PREC_BF16 = 1,
+  PBPQLP_PREC_FP16 = 2,
+  PBPQLP_PREC_BF16X3 = 3
+} pbpqlp_prec;
+
+typedef struct {
+  int sketch_prec;          /* pass Y = A Omega                                   */
+  int power_prec;           /* the 2q passes of the power iterations              */
+  int proj_prec;            /* pass B^T = A^T Q                                   */
+  int split_k;              /* 0 = automatic; else forced split count of each pass */
+  double fp16_scale_a;      /* power of two applied to A in FP16 passes (0 -> 1)  */
+  void* workspace;          /* device memory owned by the caller, or NULL: then the
+                               library allocates stream-ordered and frees it after */
+  size_t workspace_bytes;
+} pbpqlp_opts;
+
+/* Device-resident result record of one factorization. */
+typedef struct {
+  int status_flags;         /* PBPQLP_FLAG_* bits                                  */
+  int n_dependent;          /* columns completed over all orthonormalizations     */
+  int l;                    /* sketch width used                                   */
+  int q;                    /* power iterations used                               */
+  double norm_a_fro2;       /* ||A||_F^2, FP64, accumulated during the first pass */
+  double norm_l_fro2;       /* ||L||_F^2                                           */
+  double resid_rel_est;     /* sqrt(max(||A||^2 - ||L||^2, 0)) / ||A||_F: equals
+                               ||A - Q L^T P^T||_F / ||A||_F when Q, P are orthonormal */
+  double reserved[2];
+} pbpqlp_info;
+
+#define PBPQLP_FLAG_DEPENDENT 1  /* a Cholesky pivot fell below the dependence threshold:
+                                    that column was replaced by a seeded random vector,
+                                    its R row/diagonal is 0 (rank-deficient sketch)   */
+#define PBPQLP_FLAG_NONFINITE 2  /* a Gram matrix held NaN or Inf (non-finite input)   */
+
+/* Human-readable name of a status code (static storage). */
+const char* pbpqlp_status_string(pbpqlp_status s);
+
+/* Version of this ABI, 100 * major + minor. */
+int pbpqlp_version(void);
+
+/* Default options: every pass NATIVE, automatic split, library-owned workspace. */
+void pbpqlp_default_opts(pbpqlp_opts* opts);
+
+/* Bytes of device workspace pbpqlp_factor needs for this problem.
+ * Errors: EINVAL for arguments pbpqlp_factor would reject; EUNSUPPORTED for l > 256. */
+pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_dtype dt,
+                                    const pbpqlp_opts* opts, size_t* bytes);
+
+/* Full factorization (Algorithm 1 for A^T; Section III-A when q = 0).
+ *   A     : m x n, dtype dt, lda >= n.  Read only.
+ *   k, p  : 1 <= k, 0 <= p, l = k + p <= min(m, n), l <= 256.
+ *   q     : number of power iterations, 0 <= q <= 16.
+ *   seed  : selects Omega (Philox4x32-10 + Box-Muller, rounded to bfloat16),
+ *           identical for every precision choice.
+ *   Q     : m x l, dtype dt, ldq >= l: written with Q Qt (orthonormal columns).
+ *   L     : l x l FP64, ldl >= l: lower triangular, upper part written 0,
+ *           diagonal >= 0 (approximate singular values).
+ *   P     : n x l, dtype dt, ldp >= l: orthonormal columns.
+ *   opts  : may be NULL (defaults).  d_info: device pointer or NULL.
+ * A == 0 returns OK with L = 0 and orthonormal (seeded) Q and P. */
+pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                            int k, int p, int q, uint64_t seed,
+                            void* Q, int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
+                            const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream);
+
+/* ---- single steps of the method, for validation against the oracle ---- */
+
+/* The sketch matrix of eq. (c) / Algorithm 1 (randn): Omega (n x l, row-major,
+ * ldo >= l) in dtype dt; element (i, j) is the Box-Muller normal of flat index
+ * i*l + j under `seed`, rounded to bfloat16 with |x| < 2^-14 flushed to 0. */
+pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt,
+                           void* Omega, int64_t ldo, void* stream);
+
+/* One A-streaming pass (eq. (c) or (D) and the power-iteration products):
+ *   trans == 0:  Y (m x l) = A X,   X is n x l;
+ *   trans == 1:  Y (n x l) = A^T X, X is m x l.
+ * All row-major in dtype dt; prec as in pbpqlp_prec (reduced precisions need
+ * PBPQLP_F32).  fp16_scale_a as in pbpqlp_opts.  l <= 256. */
+pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int64_t lda,
+                            pbpqlp_dtype dt, const void* X, int64_t ldx, int l, int prec,
+                            double fp16_scale_a, void* Y, int64_t ldy, void* stream);
+
+/* orth()/qr() of a tall matrix (eqs. (Pbar), (DQR)): Y (rows x l, dtype dt,
+ * row-major) = Q R with Q orthonormal (rows x l, dtype dt) and R upper
+ * triangular l x l FP64 (ldr >= l, lower part written 0, diag >= 0), by
+ * `passes` (1 or 2) CholeskyQR sweeps with FP64 Grams; passes = 2 gives an
+ * orthonormal Q to working precision.  R may be NULL.  l <= rows, l <= 256. */
+pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpqlp_dtype dt,
+                          int passes, void* Q, int64_t ldq, double* R, int64_t ldr,
+                          pbpqlp_info* d_info, void* stream);
+
+/* The l x l stage (eq. (R^T = Pt Rt)): R^T = Qt L^T for an upper-triangular
+ * FP64 R (l x l, ldr >= l): writes Qt (l x l, orthogonal, FP64, ldqt >= l)
+ * and L (l x l lower triangular, diag >= 0, FP64, ldl >= l). */
+pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, int64_t ldqt,
+                              double* L, int64_t ldl, pbpqlp_info* d_info, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PBPQLP_H */

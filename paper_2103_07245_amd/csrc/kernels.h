@@ -1,0 +1,81 @@
+// Host-side launchers of the PbP-QLP kernels (implemented in the .hip files).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+struct pbpqlp_info_dev;  // layout-compatible with pbpqlp_info (include/pbpqlp.h)
+
+namespace pbq {
+
+// Arguments of one A-streaming pass (K1: out = A X, K2: out = A^T X).
+struct StreamArgs {
+  const void* A;
+  int64_t lda, m, n;
+  const void* X;        // compute-type operand, column-major lp32 x ldx
+  const void* Xlo;      // low bfloat16 part (BF16X3 only)
+  int64_t ldx;
+  int lp;               // l rounded up to 16
+  void* out;            // split partials, column-major lp x ldo each
+  int64_t ldo;
+  int64_t split_stride; // elements between consecutive split partials
+  int splits;
+  int64_t chunk;        // contraction indices per split (multiple of 64)
+  double* normA;        // per-block partial ||A||_F^2 (K1 only), or null
+  float a_scale, out_scale;
+  int vec_ok;           // A rows are 16-byte aligned
+};
+
+hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s);
+int stream_rows_per_block(int mode);
+int stream_kc(int mode);
+
+// sketch: Omega^T (column-major lp32 x ld) in FP32 or FP64; zero padding
+hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot,
+                           int64_t ld, hipStream_t s);
+// Omega row-major n x l (ldo)
+hipError_t launch_omega_rm(bool f64, int64_t n, int l, uint64_t seed, void* O, int64_t ldo,
+                           hipStream_t s);
+// FP32 column-major operand -> compute type (mode BF16/FP16/BF16X3), zero padded
+hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int l, int lp32,
+                          float scale, void* hi, void* lo, hipStream_t s);
+// out[c*ldo + i] = sum_s part[s*stride + c*ld + i]   (i < ldo; zero for i >= len)
+hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
+                                int lp, int64_t len, void* out, int64_t ldo, hipStream_t s);
+// Gram partials and reduction: G (lp x lp, FP64, row-major, ldg) = X X^T over len
+int gram_splits(int64_t len, int lp);
+size_t gram_partial_elems(int64_t len, int lp);
+hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
+                       double* G, int64_t ldg, hipStream_t s);
+// Cholesky of the Gram with dependent-column detection (single workgroup)
+hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
+                       double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
+                       hipStream_t s);
+// Q = Y Ra^-1 by blocked substitution (column-major in/out), optional row-major copy
+hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
+                        const void* Ra, const void* Dinv, const int* dep, uint64_t seed,
+                        void* Qcm, int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s);
+// Out = In M with M dense l x l given column-major (Mt[j*ldm + k] = M[k][j])
+hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
+                            const void* Mt, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
+                            int64_t ldor, hipStream_t s);
+// layout conversions
+hipError_t launch_rm_to_cm(bool f64, const void* X, int64_t ldx, int64_t len, int l, int lp32,
+                           void* Xt, int64_t ldt, hipStream_t s);
+hipError_t launch_cm_to_rm(bool f64, const void* Xt, int64_t ldt, int64_t len, int l, void* X,
+                           int64_t ldx, hipStream_t s);
+// small FP64 products: C = op(A) op(B) (lp x lp), optional transposed store
+hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, int ta,
+                             const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
+                             hipStream_t s);
+hipError_t launch_cast_f64_to_f32(const double* in, int64_t n, float* out, hipStream_t s);
+// write L = U^T (lower) from upper U, zero elsewhere
+hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, int64_t ldl,
+                                hipStream_t s);
+hipError_t launch_info_init(void* info, int l, int q, hipStream_t s);
+hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts, const double* L,
+                                int64_t ldl, int l, hipStream_t s);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_copy_mat(const double* in, int64_t ldi, int rows, int cols, double* out,
+                           int64_t ldo, int upper_only, hipStream_t s);
+
+}  // namespace pbq

@@ -1,0 +1,562 @@
+// Host orchestration and C ABI of libpbpqlp.so (declared in include/pbpqlp.h).
+//
+// One call enqueues the whole method on the caller's stream with no host
+// synchronization:  sketch -> (orth, A^T pass, orth, A pass) x q -> orth ->
+// projection B^T = A^T Q -> QR of B^T -> QR of R^T -> Q Qt, following
+// Algorithm 1 of the paper applied to A^T.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "../../include/pbpqlp.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace pbq;
+
+namespace {
+
+inline int64_t rup(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over one workspace block; with base == nullptr it only sizes.
+struct Bump {
+  char* base = nullptr;
+  size_t off = 0;
+  void* take(size_t bytes) {
+    off = (size_t)rup((int64_t)off, 256);
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+#define PBQ_CHECK(expr)                       \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return PBPQLP_EHIP; \
+  } while (0)
+
+int resolve_mode(pbpqlp_dtype dt, int prec, bool* ok) {
+  *ok = true;
+  if (dt == PBPQLP_F64) {
+    if (prec != PBPQLP_PREC_NATIVE) *ok = false;
+    return M_F64;
+  }
+  switch (prec) {
+    case PBPQLP_PREC_NATIVE: return M_F32;
+    case PBPQLP_PREC_BF16: return M_BF16;
+    case PBPQLP_PREC_FP16: return M_F16;
+    case PBPQLP_PREC_BF16X3: return M_BF16X3;
+  }
+  *ok = false;
+  return M_F32;
+}
+
+// Relative pivot threshold below which a Cholesky column counts as
+// dependent: the larger of (32 u_data)^2 (a residual below 32 rounding units
+// of the data is noise) and 4 l u_64 (the Gram's own rounding level).
+double dep_eps(bool f64, int l) {
+  const double u64 = 1.1102230246251565e-16, u32 = 5.9604644775390625e-08;
+  const double ud = f64 ? u64 : u32;
+  const double a = (32.0 * ud) * (32.0 * ud), b = 4.0 * l * u64;
+  return a > b ? a : b;
+}
+
+struct Split {
+  int S;
+  int64_t chunk;
+};
+
+// Contraction split of one streaming pass: aim at ~512 workgroups (two per
+// CU), keep at least 4 stages of 64 per split.
+Split plan_split(int64_t blocks, int64_t klen, int forced) {
+  int64_t S = forced > 0 ? forced : (512 + blocks - 1) / blocks;
+  const int64_t maxS = klen / 256 > 0 ? klen / 256 : 1;
+  if (S > maxS) S = maxS;
+  if (S > 64) S = 64;
+  if (S < 1) S = 1;
+  int64_t chunk = rup((klen + S - 1) / S, 64);
+  S = (klen + chunk - 1) / chunk;
+  if (S < 1) S = 1;
+  return {(int)S, chunk};
+}
+
+// Everything one factorization needs, carved from one workspace block.
+struct Ctx {
+  // problem
+  int64_t m = 0, n = 0, lda = 0;
+  int l = 0, lp = 0, lp32 = 0, q = 0;
+  bool f64 = false;
+  size_t el = 4;           // bytes of one data element
+  int64_t ldm = 0, ldn = 0, ldS = 0;
+  int mode_sketch = 0, mode_power = 0, mode_proj = 0;
+  float fp16_scale = 1.0f;
+  int forced_split = 0;
+  uint64_t seed = 0;
+  // splits
+  Split k1s{1, 0}, k2s{1, 0};
+  int k1_blocks = 0;
+  // buffers
+  void *Om = nullptr, *Y = nullptr, *Qm = nullptr, *W1m = nullptr, *Zn = nullptr, *Pn = nullptr,
+       *W1n = nullptr;
+  void *Xhi = nullptr, *Xlo = nullptr, *part = nullptr;
+  double *normA = nullptr, *gpart = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr,
+         *Rfin = nullptr, *M1 = nullptr, *Qt64 = nullptr, *U = nullptr;
+  void *Ra = nullptr, *Dinv = nullptr, *Ra64 = nullptr, *Dinv64 = nullptr, *Qt32 = nullptr;
+  int* dep = nullptr;
+  uint64_t ncall = 0;
+
+  void carve(Bump& b, bool need16) {
+    const int64_t ldmax = ldm > ldn ? ldm : ldn;
+    Om = b.take((size_t)lp32 * ldn * el);
+    Y = b.take((size_t)lp32 * ldm * el);
+    Qm = b.take((size_t)lp32 * ldm * el);
+    W1m = b.take((size_t)lp32 * ldm * el);
+    Zn = b.take((size_t)lp32 * ldn * el);
+    Pn = b.take((size_t)lp32 * ldn * el);
+    W1n = b.take((size_t)lp32 * ldn * el);
+    if (need16) {
+      Xhi = b.take((size_t)lp32 * ldmax * 2);
+      Xlo = b.take((size_t)lp32 * ldmax * 2);
+    }
+    const size_t p1 = (size_t)k1s.S * lp * ldm * el;
+    const size_t p2 = (size_t)k2s.S * lp * ldn * el;
+    part = b.take(p1 > p2 ? p1 : p2);
+    normA = (double*)b.take((size_t)k1_blocks * k1s.S * sizeof(double));
+    size_t gp = gram_partial_elems(m, lp);
+    const size_t gpn = gram_partial_elems(n, lp), gps = gram_partial_elems(l, lp);
+    if (gpn > gp) gp = gpn;
+    if (gps > gp) gp = gps;
+    gpart = (double*)b.take(gp * sizeof(double));
+    G = (double*)b.take((size_t)lp * lp * 8);
+    R1 = (double*)b.take((size_t)lp * lp * 8);
+    R2 = (double*)b.take((size_t)lp * lp * 8);
+    U = (double*)b.take((size_t)lp * lp * 8);
+    Rfin = (double*)b.take((size_t)lp32 * ldS * 8);
+    M1 = (double*)b.take((size_t)lp32 * ldS * 8);
+    Qt64 = (double*)b.take((size_t)lp32 * ldS * 8);
+    Qt32 = b.take((size_t)lp32 * ldS * 4);
+    Ra = b.take((size_t)lp * lp * el);
+    Dinv = b.take((size_t)(lp / 16) * 256 * el);
+    Ra64 = b.take((size_t)lp * lp * 8);
+    Dinv64 = b.take((size_t)(lp / 16) * 256 * 8);
+    dep = (int*)b.take((size_t)lp * sizeof(int));
+  }
+};
+
+bool valid_args(int64_t m, int64_t n, int k, int p, int q) {
+  if (m < 1 || n < 1 || k < 1 || p < 0 || q < 0 || q > 16) return false;
+  const int64_t l = (int64_t)k + p;
+  return l <= m && l <= n;
+}
+
+pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, int k, int p,
+                    int q, const pbpqlp_opts* opts) {
+  if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
+  if (!valid_args(m, n, k, p, q) || lda < n) return PBPQLP_EINVAL;
+  const int l = k + p;
+  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  pbpqlp_opts o;
+  pbpqlp_default_opts(&o);
+  if (opts) o = *opts;
+  c.m = m; c.n = n; c.lda = lda; c.q = q;
+  c.l = l; c.lp = (int)rup(l, 16); c.lp32 = (int)rup(l, 32);
+  c.f64 = dt == PBPQLP_F64;
+  c.el = c.f64 ? 8 : 4;
+  c.ldm = rup(m, 64); c.ldn = rup(n, 64); c.ldS = rup(c.lp, 64);
+  bool ok1, ok2, ok3;
+  c.mode_sketch = resolve_mode(dt, o.sketch_prec, &ok1);
+  c.mode_power = resolve_mode(dt, o.power_prec, &ok2);
+  c.mode_proj = resolve_mode(dt, o.proj_prec, &ok3);
+  if (!ok1 || !ok2 || !ok3) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
+  c.fp16_scale = (float)(o.fp16_scale_a > 0 ? o.fp16_scale_a : 1.0);
+  c.forced_split = o.split_k;
+  const int rb = stream_rows_per_block(c.f64 ? M_F64 : M_F32);
+  c.k1_blocks = (int)((m + rb - 1) / rb);
+  c.k1s = plan_split(c.k1_blocks, n, c.forced_split);
+  c.k2s = plan_split((n + rb - 1) / rb, m, c.forced_split);
+  return PBPQLP_OK;
+}
+
+bool needs16(const Ctx& c) {
+  return c.mode_sketch >= M_BF16 || c.mode_power >= M_BF16 || c.mode_proj >= M_BF16;
+}
+
+// One A-streaming pass: out (column-major, ld) = A X (trans=0) or A^T X.
+pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const void* X,
+                          int64_t ldx, int64_t xlen, bool unit_columns, void* out, int64_t ldo,
+                          double* normA, hipStream_t st) {
+  StreamArgs a;
+  a.A = A; a.lda = c.lda; a.m = c.m; a.n = c.n;
+  a.lp = c.lp;
+  a.a_scale = 1.0f;
+  a.out_scale = 1.0f;
+  if (mode >= M_BF16) {
+    float xs = 1.0f;
+    if (mode == M_F16) {
+      a.a_scale = c.fp16_scale;
+      // unit-norm columns have entries ~ len^-1/2: lift them to ~1 (exact power of two)
+      if (unit_columns) xs = std::ldexp(1.0f, (int)std::floor(0.5 * std::log2((double)xlen)));
+      a.out_scale = 1.0f / (a.a_scale * xs);
+    }
+    PBQ_CHECK(launch_convert(mode, (const float*)X, ldx, xlen, c.l, c.lp32, xs, c.Xhi, c.Xlo, st));
+    a.X = c.Xhi;
+    a.Xlo = c.Xlo;
+  } else {
+    a.X = X;
+    a.Xlo = nullptr;
+  }
+  a.ldx = ldx;
+  a.vec_ok = (((uintptr_t)A & 15) == 0 && ((c.lda * (int64_t)c.el) & 15) == 0) ? 1 : 0;
+  const Split sp = trans ? c.k2s : c.k1s;
+  a.splits = sp.S;
+  a.chunk = sp.chunk;
+  a.normA = normA;
+  const int64_t olen = trans ? c.n : c.m;
+  if (sp.S == 1) {
+    a.out = out;
+    a.ldo = ldo;
+    a.split_stride = 0;
+  } else {
+    a.out = c.part;
+    a.ldo = ldo;
+    a.split_stride = (int64_t)c.lp * ldo;
+  }
+  PBQ_CHECK(launch_stream(trans, mode, a, st));
+  if (sp.S > 1)
+    PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, a.split_stride, sp.S, ldo, c.lp, olen, out, ldo, st));
+  return PBPQLP_OK;
+}
+
+// orth()/qr() of a column-major tall matrix X (lp32 x ld, len rows of the
+// tall matrix) by `passes` CholeskyQR sweeps.  Result in `out` (column-major)
+// and optionally row-major `rm` (ld_rm).  Rkeep (lp x lp, FP64) receives the
+// accumulated triangular factor when non-null.
+pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes,
+                   void* out, void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm,
+                   void* info, hipStream_t st) {
+  const double eps = dep_eps(f64, c.l);
+  void* Ra = f64 ? c.Ra64 : c.Ra;
+  void* Dv = f64 ? c.Dinv64 : c.Dinv;
+  const void* src = X;
+  for (int ps = 0; ps < passes; ++ps) {
+    const bool last = ps == passes - 1;
+    void* dst = last ? out : tmp;
+    double* Rt = ps == 0 ? c.R1 : c.R2;
+    const uint64_t cseed = c.seed ^ (0x9E3779B97F4A7C15ull * (++c.ncall));
+    PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, st));
+    PBQ_CHECK(launch_chol(f64, c.G, c.lp, c.l, c.lp, eps, Rt, c.lp, Ra, Dv, c.dep, info, st));
+    PBQ_CHECK(launch_apply(f64, src, ld, len, c.lp, c.l, Ra, Dv, c.dep, cseed, dst, ld,
+                           last ? rm : nullptr, ldrm, st));
+    src = dst;
+  }
+  if (Rkeep) {
+    if (passes == 1)
+      PBQ_CHECK(launch_copy_mat(c.R1, c.lp, c.lp, c.lp, Rkeep, ldrk, 1, st));
+    else
+      PBQ_CHECK(launch_small_gemm(c.lp, c.lp, c.lp, c.R2, c.lp, 0, c.R1, c.lp, 0, Rkeep, ldrk, 0, st));
+  }
+  return PBPQLP_OK;
+}
+
+// The l x l stage: R^T = Qt U (U = L^T) by two FP64 CholeskyQR sweeps of the
+// l x l matrix R^T, whose column-major storage is R itself (row-major).
+pbpqlp_status small_qr(Ctx& c, const double* Rrow, int64_t ldr, void* info, hipStream_t st) {
+  return orth(c, true, Rrow, ldr, c.l, 2, c.Qt64, c.M1, c.U, c.lp, nullptr, 0, info, st);
+}
+
+pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L, int64_t ldl,
+                         void* P, int64_t ldp, pbpqlp_info* info, hipStream_t st) {
+  PBQ_CHECK(launch_info_init(info, c.l, c.q, st));
+  // S0: sketch matrix, column-major (lp32 x ldn)
+  PBQ_CHECK(launch_omega_cm(c.f64, c.n, c.l, c.lp32, c.seed, c.Om, c.ldn, st));
+  // S1: Y = A Omega (+ ||A||_F^2)
+  pbpqlp_status s;
+  s = stream_pass(c, false, c.mode_sketch, A, c.Om, c.ldn, c.n, false, c.Y, c.ldm, c.normA, st);
+  if (s) return s;
+  s = orth(c, c.f64, c.Y, c.ldm, c.m, c.q == 0 ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
+  if (s) return s;
+  // S3: power iterations with re-orthonormalization after each product
+  for (int i = 1; i <= c.q; ++i) {
+    s = stream_pass(c, true, c.mode_power, A, c.Qm, c.ldm, c.m, true, c.Zn, c.ldn, nullptr, st);
+    if (s) return s;
+    s = orth(c, c.f64, c.Zn, c.ldn, c.n, 1, c.Pn, c.W1n, nullptr, 0, nullptr, 0, info, st);
+    if (s) return s;
+    s = stream_pass(c, false, c.mode_power, A, c.Pn, c.ldn, c.n, true, c.Y, c.ldm, nullptr, st);
+    if (s) return s;
+    s = orth(c, c.f64, c.Y, c.ldm, c.m, i == c.q ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
+    if (s) return s;
+  }
+  // S4: projection B^T = A^T Q;  S5: B^T = P R (P written row-major to the caller)
+  s = stream_pass(c, true, c.mode_proj, A, c.Qm, c.ldm, c.m, true, c.Zn, c.ldn, nullptr, st);
+  if (s) return s;
+  s = orth(c, c.f64, c.Zn, c.ldn, c.n, 2, c.Pn, c.W1n, c.Rfin, c.ldS, P, ldp, info, st);
+  if (s) return s;
+  // S6: R^T = Qt L^T
+  s = small_qr(c, c.Rfin, c.ldS, info, st);
+  if (s) return s;
+  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, c.l, L, ldl, st));
+  // S7: Q Qt, written row-major to the caller
+  const void* Mt = c.Qt64;
+  if (!c.f64) {
+    PBQ_CHECK(launch_cast_f64_to_f32(c.Qt64, (int64_t)c.lp32 * c.ldS, (float*)c.Qt32, st));
+    Mt = c.Qt32;
+  }
+  PBQ_CHECK(launch_right_mul(c.f64, c.Qm, c.ldm, c.m, c.lp, c.l, Mt, c.ldS, nullptr, 0, Q, ldq, st));
+  // S8: result record
+  PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1s.S, L, ldl, c.l, st));
+  return PBPQLP_OK;
+}
+
+struct ScratchGuard {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  ~ScratchGuard() {
+    if (p) (void)hipFreeAsync(p, s);
+  }
+};
+
+pbpqlp_status alloc_scratch(ScratchGuard& g, size_t bytes, hipStream_t st) {
+  g.s = st;
+  if (hipMallocAsync(&g.p, bytes > 0 ? bytes : 256, st) != hipSuccess) {
+    g.p = nullptr;
+    return PBPQLP_ENOMEM;
+  }
+  return PBPQLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pbpqlp_status_string(pbpqlp_status s) {
+  switch (s) {
+    case PBPQLP_OK: return "PBPQLP_OK";
+    case PBPQLP_EINVAL: return "PBPQLP_EINVAL: invalid argument";
+    case PBPQLP_ENOMEM: return "PBPQLP_ENOMEM: workspace too small or allocation failed";
+    case PBPQLP_EHIP: return "PBPQLP_EHIP: HIP runtime error";
+    case PBPQLP_EUNSUPPORTED: return "PBPQLP_EUNSUPPORTED: outside this build's limits";
+  }
+  return "PBPQLP: unknown status";
+}
+
+int pbpqlp_version(void) { return 100; }
+
+void pbpqlp_default_opts(pbpqlp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->sketch_prec = o->power_prec = o->proj_prec = PBPQLP_PREC_NATIVE;
+  o->fp16_scale_a = 1.0;
+}
+
+pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_dtype dt,
+                                    const pbpqlp_opts* opts, size_t* bytes) {
+  if (!bytes) return PBPQLP_EINVAL;
+  Ctx c;
+  pbpqlp_status s = setup(c, m, n, n, dt, k, p, 0, opts);
+  if (s) return s;
+  Bump b;
+  c.carve(b, needs16(c));
+  *bytes = b.off + 256;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                            int k, int p, int q, uint64_t seed, void* Q, int64_t ldq, double* L,
+                            int64_t ldl, void* P, int64_t ldp, const pbpqlp_opts* opts,
+                            pbpqlp_info* d_info, void* stream) {
+  if (!A || !Q || !L || !P) return PBPQLP_EINVAL;
+  Ctx c;
+  pbpqlp_status s = setup(c, m, n, lda, dt, k, p, q, opts);
+  if (s) return s;
+  if (ldq < c.l || ldl < c.l || ldp < c.l) return PBPQLP_EINVAL;
+  if (Q == A || P == A || (const void*)L == A || Q == P) return PBPQLP_EINVAL;
+  c.seed = seed;
+  hipStream_t st = (hipStream_t)stream;
+  Bump sizer;
+  c.carve(sizer, needs16(c));
+  const size_t need = sizer.off + 256;
+  ScratchGuard g;
+  char* base;
+  if (opts && opts->workspace) {
+    if (opts->workspace_bytes < need) return PBPQLP_ENOMEM;
+    base = (char*)opts->workspace;
+  } else {
+    s = alloc_scratch(g, need + sizeof(pbpqlp_info), st);
+    if (s) return s;
+    base = (char*)g.p;
+  }
+  Bump b;
+  b.base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
+  c.carve(b, needs16(c));
+  pbpqlp_info* info = d_info;
+  if (!info) info = (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  if (!info) return PBPQLP_ENOMEM;
+  if (opts && opts->workspace && b.off > opts->workspace_bytes) return PBPQLP_ENOMEM;
+  return run_factor(c, A, Q, ldq, L, ldl, P, ldp, info, st);
+}
+
+pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt, void* Omega,
+                           int64_t ldo, void* stream) {
+  if (!Omega || n < 1 || l < 1 || ldo < l) return PBPQLP_EINVAL;
+  if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
+  PBQ_CHECK(launch_omega_rm(dt == PBPQLP_F64, n, l, seed, Omega, ldo, (hipStream_t)stream));
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int64_t lda,
+                            pbpqlp_dtype dt, const void* X, int64_t ldx, int l, int prec,
+                            double fp16_scale_a, void* Y, int64_t ldy, void* stream) {
+  if (!A || !X || !Y || l < 1 || m < 1 || n < 1 || lda < n || ldx < l || ldy < l)
+    return PBPQLP_EINVAL;
+  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  pbpqlp_opts o;
+  pbpqlp_default_opts(&o);
+  o.sketch_prec = o.power_prec = o.proj_prec = prec;
+  o.fp16_scale_a = fp16_scale_a;
+  Ctx c;
+  // setup() checks l <= min(m, n); a bare product only needs l <= 256
+  c.m = m; c.n = n; c.lda = lda; c.l = l; c.lp = (int)rup(l, 16); c.lp32 = (int)rup(l, 32);
+  c.f64 = dt == PBPQLP_F64;
+  if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
+  c.el = c.f64 ? 8 : 4;
+  c.ldm = rup(m, 64); c.ldn = rup(n, 64); c.ldS = rup(c.lp, 64);
+  bool ok;
+  const int mode = resolve_mode(dt, prec, &ok);
+  if (!ok) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
+  c.mode_sketch = c.mode_power = c.mode_proj = mode;
+  c.fp16_scale = (float)(fp16_scale_a > 0 ? fp16_scale_a : 1.0);
+  const int rb = stream_rows_per_block(c.f64 ? M_F64 : M_F32);
+  c.k1_blocks = (int)((m + rb - 1) / rb);
+  c.k1s = plan_split(c.k1_blocks, n, 0);
+  c.k2s = plan_split((n + rb - 1) / rb, m, 0);
+  hipStream_t st = (hipStream_t)stream;
+  const int64_t xlen = trans ? m : n, ylen = trans ? n : m;
+  const int64_t ldxi = trans ? c.ldm : c.ldn, ldyo = trans ? c.ldn : c.ldm;
+  // scratch: Xt, Yt, 16-bit copies, split partials
+  const int64_t ldmax = c.ldm > c.ldn ? c.ldm : c.ldn;
+  Bump sz;
+  sz.take((size_t)c.lp32 * ldxi * c.el);
+  sz.take((size_t)c.lp32 * ldyo * c.el);
+  sz.take((size_t)c.lp32 * ldmax * 2);
+  sz.take((size_t)c.lp32 * ldmax * 2);
+  const size_t p1 = (size_t)c.k1s.S * c.lp * c.ldm * c.el, p2 = (size_t)c.k2s.S * c.lp * c.ldn * c.el;
+  sz.take(p1 > p2 ? p1 : p2);
+  sz.take((size_t)c.k1_blocks * c.k1s.S * 8);
+  ScratchGuard g;
+  pbpqlp_status s = alloc_scratch(g, sz.off + 256, st);
+  if (s) return s;
+  Bump b;
+  b.base = (char*)g.p;
+  void* Xt = b.take((size_t)c.lp32 * ldxi * c.el);
+  void* Yt = b.take((size_t)c.lp32 * ldyo * c.el);
+  c.Xhi = b.take((size_t)c.lp32 * ldmax * 2);
+  c.Xlo = b.take((size_t)c.lp32 * ldmax * 2);
+  c.part = b.take(p1 > p2 ? p1 : p2);
+  c.normA = (double*)b.take((size_t)c.k1_blocks * c.k1s.S * 8);
+  PBQ_CHECK(launch_rm_to_cm(c.f64, X, ldx, xlen, l, c.lp32, Xt, ldxi, st));
+  s = stream_pass(c, trans != 0, mode, A, Xt, ldxi, xlen, false, Yt, ldyo, nullptr, st);
+  if (s) return s;
+  PBQ_CHECK(launch_cm_to_rm(c.f64, Yt, ldyo, ylen, l, Y, ldy, st));
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpqlp_dtype dt,
+                          int passes, void* Q, int64_t ldq, double* R, int64_t ldr,
+                          pbpqlp_info* d_info, void* stream) {
+  if (!Y || !Q || l < 1 || rows < l || ldy < l || ldq < l || (R && ldr < l)) return PBPQLP_EINVAL;
+  if (passes < 1 || passes > 2) return PBPQLP_EINVAL;
+  if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
+  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  Ctx c;
+  c.m = rows; c.n = rows; c.l = l; c.lp = (int)rup(l, 16); c.lp32 = (int)rup(l, 32);
+  c.f64 = dt == PBPQLP_F64;
+  c.el = c.f64 ? 8 : 4;
+  c.ldm = rup(rows, 64);
+  c.seed = 0x5EEDull;
+  hipStream_t st = (hipStream_t)stream;
+  Bump sz;
+  sz.take((size_t)c.lp32 * c.ldm * c.el);
+  sz.take((size_t)c.lp32 * c.ldm * c.el);
+  sz.take((size_t)c.lp32 * c.ldm * c.el);
+  sz.take(gram_partial_elems(rows, c.lp) * 8);
+  for (int i = 0; i < 4; ++i) sz.take((size_t)c.lp * c.lp * 8);
+  sz.take((size_t)c.lp * c.lp * 8);
+  sz.take((size_t)(c.lp / 16) * 256 * 8);
+  sz.take((size_t)c.lp * c.lp * 8);
+  sz.take((size_t)(c.lp / 16) * 256 * 8);
+  sz.take((size_t)c.lp * 4);
+  sz.take(sizeof(pbpqlp_info));
+  ScratchGuard g;
+  pbpqlp_status s = alloc_scratch(g, sz.off + 256, st);
+  if (s) return s;
+  Bump b;
+  b.base = (char*)g.p;
+  void* Xt = b.take((size_t)c.lp32 * c.ldm * c.el);
+  void* Out = b.take((size_t)c.lp32 * c.ldm * c.el);
+  void* Tmp = b.take((size_t)c.lp32 * c.ldm * c.el);
+  c.gpart = (double*)b.take(gram_partial_elems(rows, c.lp) * 8);
+  c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
+  double* Rk = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.Ra = b.take((size_t)c.lp * c.lp * 8);
+  c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
+  c.Ra64 = b.take((size_t)c.lp * c.lp * 8);
+  c.Dinv64 = b.take((size_t)(c.lp / 16) * 256 * 8);
+  c.dep = (int*)b.take((size_t)c.lp * 4);
+  pbpqlp_info* info = d_info ? d_info : (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  if (!d_info) PBQ_CHECK(launch_info_init(info, l, 0, st));
+  PBQ_CHECK(launch_rm_to_cm(c.f64, Y, ldy, rows, l, c.lp32, Xt, c.ldm, st));
+  s = orth(c, c.f64, Xt, c.ldm, rows, passes, Out, Tmp, R ? Rk : nullptr, c.lp, Q, ldq, info, st);
+  if (s) return s;
+  if (R) PBQ_CHECK(launch_copy_mat(Rk, c.lp, l, l, R, ldr, 1, st));
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, int64_t ldqt,
+                              double* L, int64_t ldl, pbpqlp_info* d_info, void* stream) {
+  if (!R || !Qt || !L || l < 1 || ldr < l || ldqt < l || ldl < l) return PBPQLP_EINVAL;
+  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  Ctx c;
+  c.l = l; c.lp = (int)rup(l, 16); c.lp32 = (int)rup(l, 32);
+  c.f64 = true; c.el = 8;
+  c.ldS = rup(c.lp, 64);
+  c.seed = 0x5A11ull;
+  hipStream_t st = (hipStream_t)stream;
+  Bump sz;
+  for (int i = 0; i < 3; ++i) sz.take((size_t)c.lp32 * c.ldS * 8);
+  sz.take(gram_partial_elems(l, c.lp) * 8);
+  for (int i = 0; i < 4; ++i) sz.take((size_t)c.lp * c.lp * 8);
+  sz.take((size_t)(c.lp / 16) * 256 * 8);
+  sz.take((size_t)c.lp * 4);
+  sz.take(sizeof(pbpqlp_info));
+  ScratchGuard g;
+  pbpqlp_status s = alloc_scratch(g, sz.off + 256, st);
+  if (s) return s;
+  Bump b;
+  b.base = (char*)g.p;
+  c.Rfin = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
+  c.M1 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
+  c.Qt64 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
+  c.gpart = (double*)b.take(gram_partial_elems(l, c.lp) * 8);
+  c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.U = (double*)b.take((size_t)c.lp * c.lp * 8);
+  c.Ra64 = c.Ra = b.take((size_t)c.lp * c.lp * 8);
+  c.Dinv64 = c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
+  c.dep = (int*)b.take((size_t)c.lp * 4);
+  pbpqlp_info* info = d_info ? d_info : (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  if (!d_info) PBQ_CHECK(launch_info_init(info, l, 0, st));
+  PBQ_CHECK(launch_fill_zero(c.Rfin, (size_t)c.lp32 * c.ldS * 8, st));
+  PBQ_CHECK(launch_copy_mat(R, ldr, l, l, c.Rfin, c.ldS, 1, st));
+  s = small_qr(c, c.Rfin, c.ldS, info, st);
+  if (s) return s;
+  PBQ_CHECK(launch_cm_to_rm(true, c.Qt64, c.ldS, l, l, Qt, ldqt, st));
+  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, l, L, ldl, st));
+  return PBPQLP_OK;
+}
+
+}  // extern "C"

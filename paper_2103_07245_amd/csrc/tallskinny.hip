@@ -1,0 +1,501 @@
+// Tall-skinny kernels of PbP-QLP: the sketch generator, operand conversion,
+// split-K reduction, and the two halves of a CholeskyQR sweep that touch the
+// tall matrix (Gram accumulation and the triangular apply), plus the final
+// right-multiplication Q Qt (Algorithm 1, last step: P := Pbar Pt).
+//
+// Column-major tall buffers: row c of a lp32 x ld buffer is column c of the
+// tall matrix; every producer writes zeros in rows [l, lp) and in columns
+// [len, ld) so consumers can read whole 64-element groups without checks.
+#include "common.h"
+#include "kernels.h"
+#include "../../include/pbpqlp.h"
+
+namespace pbq {
+
+// ---------------------------------------------------------------------------
+// Sketch Omega (randn(n, l) of Algorithm 1, for A^T): element (i, c) is the
+// normal of flat index t = i*l + c from Philox block t/4, slot t%4, rounded to
+// bfloat16 and flushed below 2^-14.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double omega_elem(int64_t i, int c, int l, uint64_t seed) {
+  const uint64_t t = (uint64_t)i * (uint64_t)l + (uint64_t)c;
+  return sketch_value(normal_at(t, 0u, 0u, seed));
+}
+
+template <typename T>
+__global__ void omega_cm_kernel(int64_t n, int l, int lp32, uint64_t seed, T* __restrict__ Ot,
+                                int64_t ld) {
+  const int c = blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= ld) return;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + e;
+    T v = 0;
+    if (c < l && i < n) v = (T)omega_elem(i, c, l, seed);
+    if (i < ld) Ot[(int64_t)c * ld + i] = v;
+  }
+}
+
+template <typename T>
+__global__ void omega_rm_kernel(int64_t n, int l, uint64_t seed, T* __restrict__ O, int64_t ldo) {
+  const int64_t i = blockIdx.y;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= l || i >= n) return;
+  O[i * ldo + c] = (T)omega_elem(i, c, l, seed);
+}
+
+hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot,
+                           int64_t ld, hipStream_t s) {
+  dim3 grid((unsigned)((ld / 4 + 255) / 256), (unsigned)lp32);
+  if (f64)
+    hipLaunchKernelGGL(omega_cm_kernel<double>, grid, dim3(256), 0, s, n, l, lp32, seed,
+                       (double*)Ot, ld);
+  else
+    hipLaunchKernelGGL(omega_cm_kernel<float>, grid, dim3(256), 0, s, n, l, lp32, seed,
+                       (float*)Ot, ld);
+  return hipGetLastError();
+}
+
+hipError_t launch_omega_rm(bool f64, int64_t n, int l, uint64_t seed, void* O, int64_t ldo,
+                           hipStream_t s) {
+  dim3 grid((unsigned)((l + 63) / 64), (unsigned)n);
+  if (f64)
+    hipLaunchKernelGGL(omega_rm_kernel<double>, grid, dim3(64), 0, s, n, l, seed, (double*)O, ldo);
+  else
+    hipLaunchKernelGGL(omega_rm_kernel<float>, grid, dim3(64), 0, s, n, l, seed, (float*)O, ldo);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// FP32 operand -> 16-bit compute type (hi, and lo = x - hi for BF16X3).
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ void convert_kernel(const float* __restrict__ X, int64_t ld, int64_t len, int l,
+                               float scale, void* __restrict__ hi_, void* __restrict__ lo_) {
+  const int c = blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= ld) return;
+  float v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + e;
+    v[e] = (c < l && i < len) ? X[(int64_t)c * ld + i] * scale : 0.0f;
+  }
+  if constexpr (MODE == M_F16) {
+    _Float16* hi = (_Float16*)hi_;
+    f16x4 h = {(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
+    *(f16x4*)(hi + (int64_t)c * ld + i0) = h;
+  } else {
+    __bf16* hi = (__bf16*)hi_;
+    bf16x4 h = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
+    *(bf16x4*)(hi + (int64_t)c * ld + i0) = h;
+    if constexpr (MODE == M_BF16X3) {
+      __bf16* lo = (__bf16*)lo_;
+      bf16x4 w = {(__bf16)(v[0] - (float)h[0]), (__bf16)(v[1] - (float)h[1]),
+                  (__bf16)(v[2] - (float)h[2]), (__bf16)(v[3] - (float)h[3])};
+      *(bf16x4*)(lo + (int64_t)c * ld + i0) = w;
+    }
+  }
+}
+
+hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int l, int lp32,
+                          float scale, void* hi, void* lo, hipStream_t s) {
+  dim3 grid((unsigned)((ld / 4 + 255) / 256), (unsigned)lp32);
+  switch (mode) {
+    case M_BF16:
+      hipLaunchKernelGGL(convert_kernel<M_BF16>, grid, dim3(256), 0, s, X, ld, len, l, scale, hi, lo);
+      break;
+    case M_F16:
+      hipLaunchKernelGGL(convert_kernel<M_F16>, grid, dim3(256), 0, s, X, ld, len, l, scale, hi, lo);
+      break;
+    case M_BF16X3:
+      hipLaunchKernelGGL(convert_kernel<M_BF16X3>, grid, dim3(256), 0, s, X, ld, len, l, scale, hi, lo);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reduction in a fixed order (bitwise reproducible).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void splitk_reduce_kernel(const T* __restrict__ part, int64_t stride, int S,
+                                     int64_t ld, int64_t len, T* __restrict__ out, int64_t ldo) {
+  const int c = blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (i0 >= ldo) return;
+  T acc[4] = {0, 0, 0, 0};
+  if (i0 + 3 < len) {
+    for (int sp = 0; sp < S; ++sp) {
+      const T* p = part + (int64_t)sp * stride + (int64_t)c * ld + i0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] += p[e];
+    }
+  } else {
+    for (int sp = 0; sp < S; ++sp) {
+      const T* p = part + (int64_t)sp * stride + (int64_t)c * ld + i0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (i0 + e < len) acc[e] += p[e];
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (i0 + e < ldo) out[(int64_t)c * ldo + i0 + e] = acc[e];
+}
+
+hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
+                                int lp, int64_t len, void* out, int64_t ldo, hipStream_t s) {
+  dim3 grid((unsigned)((ldo / 4 + 255) / 256), (unsigned)lp);
+  if (f64)
+    hipLaunchKernelGGL(splitk_reduce_kernel<double>, grid, dim3(256), 0, s, (const double*)part,
+                       stride, S, ld, len, (double*)out, ldo);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<float>, grid, dim3(256), 0, s, (const float*)part,
+                       stride, S, ld, len, (float*)out, ldo);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Gram G = X X^T of a column-major lp x len operand, accumulated in FP64 on
+// the FP64 matrix cores (FP32 inputs are exact in FP64).  Grid: (upper
+// triangle of 32x32 blocks) x (contraction splits); each wave owns one 16x16
+// tile; partials are summed by gram_reduce in a fixed order.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int npairs_of(int nb) { return nb * (nb + 1) / 2; }
+
+int gram_splits(int64_t len, int lp) {
+  const int nb = (lp + 31) / 32;
+  const int np = npairs_of(nb);
+  int64_t S = (2048 + np - 1) / np;              // aim at ~2048 workgroups
+  const int64_t maxS = (len + 255) / 256;        // at least 256 rows per split
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  return (int)S;
+}
+
+size_t gram_partial_elems(int64_t len, int lp) {
+  const int nb = (lp + 31) / 32;
+  return (size_t)gram_splits(len, lp) * npairs_of(nb) * 1024;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ X, int64_t ld,
+                                                           int64_t len, int lp, int64_t kchunk,
+                                                           double* __restrict__ part) {
+  constexpr int VV = 16 / sizeof(T);
+  const int p = blockIdx.x;
+  int bj = 0;
+  while ((bj + 1) * (bj + 2) / 2 <= p) ++bj;
+  const int bi = p - bj * (bj + 1) / 2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int ti = wave >> 1, tj = wave & 1;
+  const int rI = 32 * bi + 16 * ti + li, rJ = 32 * bj + 16 * tj + li;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk, ke = min(len, kb + kchunk);
+  const T* pI = X + (int64_t)rI * ld;
+  const T* pJ = X + (int64_t)rJ * ld;
+  const bool okI = rI < lp, okJ = rJ < lp;
+  f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
+  auto ld_slice = [&](const T* base, bool ok, int64_t k, T out[VV]) {
+    if (ok && k + VV <= ke) {
+      union { u32x4 v; T e[VV]; } u;
+      u.v = ld16(base + k);
+#pragma unroll
+      for (int e = 0; e < VV; ++e) out[e] = u.e[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < VV; ++e) out[e] = (ok && k + e < ke) ? base[k + e] : T(0);
+    }
+  };
+  constexpr int STEP = 4 * VV;
+  // wave-uniform trip count: lanes past the end load zeros
+  for (int64_t base = kb; base < ke; base += 2 * STEP) {
+    const int64_t k = base + lg * VV;
+    T a0[VV], b0[VV], a1[VV], b1[VV];
+    ld_slice(pI, okI, k, a0);
+    ld_slice(pJ, okJ, k, b0);
+    ld_slice(pI, okI, k + STEP, a1);
+    ld_slice(pJ, okJ, k + STEP, b1);
+#pragma unroll
+    for (int e = 0; e < VV; ++e) acc0 = mma_f64((double)a0[e], (double)b0[e], acc0);
+#pragma unroll
+    for (int e = 0; e < VV; ++e) acc1 = mma_f64((double)a1[e], (double)b1[e], acc1);
+  }
+  double* out = part + ((int64_t)blockIdx.y * gridDim.x + p) * 1024;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[(16 * ti + 4 * lg + r) * 32 + 16 * tj + li] = acc0[r] + acc1[r];
+}
+
+__global__ void gram_reduce_kernel(const double* __restrict__ part, int S, int np, int lp,
+                                   double* __restrict__ G, int64_t ldg) {
+  const int i = blockIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= lp) return;
+  int bi = i >> 5, bj = j >> 5, ii = i & 31, jj = j & 31;
+  if (bi > bj) {
+    int t = bi; bi = bj; bj = t;
+    t = ii; ii = jj; jj = t;
+  }
+  const int p = bj * (bj + 1) / 2 + bi;
+  double s = 0.0;
+  for (int sp = 0; sp < S; ++sp) s += part[((int64_t)sp * np + p) * 1024 + ii * 32 + jj];
+  G[(int64_t)i * ldg + j] = s;
+}
+
+hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
+                       double* G, int64_t ldg, hipStream_t s) {
+  const int nb = (lp + 31) / 32;
+  const int np = npairs_of(nb);
+  const int S = gram_splits(len, lp);
+  int64_t kchunk = (len + S - 1) / S;
+  kchunk = (kchunk + 15) / 16 * 16;
+  dim3 grid((unsigned)np, (unsigned)S);
+  if (f64)
+    hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, s, (const double*)X, ld,
+                       len, lp, kchunk, part);
+  else
+    hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(256), 0, s, (const float*)X, ld, len,
+                       lp, kchunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 g2((unsigned)((lp + 63) / 64), (unsigned)lp);
+  hipLaunchKernelGGL(gram_reduce_kernel, g2, dim3(64), 0, s, part, S, np, lp, G, ldg);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Triangular apply Q = Y Ra^-1 by blocked forward substitution over 16-wide
+// column blocks, computed in the transposed space (rows of Q^T on the tile's
+// M side) so each step's previous blocks feed the matrix cores from registers:
+//   Q_J = (Y_J - sum_{I<J} Q_I Ra_IJ) Dinv_J.
+// A dependent column c (flagged by the Cholesky) is replaced by the seeded
+// unit-variance vector w_c / sqrt(len); Ra has an identity row/column there.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T completion_value(int c, int64_t a, int64_t len, uint64_t seed) {
+  return (T)(normal_at((uint64_t)a, 1u, (uint32_t)c, seed) / sqrt((double)len));
+}
+
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int64_t ldy,
+                                                    int64_t len, int lp, int l,
+                                                    const T* __restrict__ Ra,
+                                                    const T* __restrict__ Dinv,
+                                                    const int* __restrict__ dep, uint64_t seed,
+                                                    T* __restrict__ Qcm, int64_t ldq,
+                                                    T* __restrict__ Qrm, int64_t ldqr) {
+  typedef typename Vec4<T>::type ACC;
+  // column block J of Ra (rows 0..16J+15) and Dinv_J, staged once per block for all waves
+  __shared__ T rcol[16 * NT][17];
+  __shared__ T dcol[16][17];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int64_t arow = (int64_t)blockIdx.x * 64 + wave * 16 + li;
+  const int Tn = lp >> 4;
+  const bool in = arow < len;
+  ACC qt[NT];
+#pragma unroll
+  for (int J = 0; J < NT; ++J) {
+    if (J < Tn) {
+      __syncthreads();
+      for (int e = tid; e < 16 * J * 16; e += 256) {
+        const int r = e >> 4, c = e & 15;
+        rcol[r][c] = Ra[(int64_t)r * lp + 16 * J + c];
+      }
+      dcol[tid >> 4][tid & 15] = Dinv[J * 256 + tid];
+      __syncthreads();
+      ACC acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * J + 4 * lg + r;
+        T v = in ? Y[(int64_t)c * ldy + arow] : T(0);
+        if (in && c < l && dep[c]) v = completion_value<T>(c, arow, len, seed);
+        acc[r] = v;
+      }
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {   // constant trip count so the loop unrolls; I < J live
+        if (I < J) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) acc = mma_native(-rcol[16 * I + 4 * lg + s4][li], qt[I][s4], acc);
+        }
+      }
+      ACC res = {0, 0, 0, 0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) res = mma_native(dcol[4 * lg + s4][li], acc[s4], res);
+      qt[J] = res;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * J + 4 * lg + r;
+        if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = res[r];
+        if (Qrm && in && c < l) Qrm[arow * ldqr + c] = res[r];
+      }
+    }
+  }
+}
+
+template <typename T, int NT>
+static void apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
+                         const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
+                         void* Qrm, int64_t ldqr, hipStream_t s) {
+  const int64_t rows = Qcm ? (ldq > len ? ldq : len) : len;
+  dim3 grid((unsigned)((rows + 63) / 64));
+  hipLaunchKernelGGL((apply_kernel<T, NT>), grid, dim3(256), 0, s, (const T*)Y, ldy, len, lp, l,
+                     (const T*)Ra, (const T*)Dinv, dep, seed, (T*)Qcm, ldq, (T*)Qrm, ldqr);
+}
+
+hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
+                        const void* Ra, const void* Dinv, const int* dep, uint64_t seed, void* Qcm,
+                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s) {
+  const int T = lp / 16;
+#define PBQ_APPLY(NTV)                                                                           \
+  if (f64) apply_launch<double, NTV>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s); \
+  else apply_launch<float, NTV>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s);
+  if (T <= 2) { PBQ_APPLY(2) }
+  else if (T <= 4) { PBQ_APPLY(4) }
+  else if (T <= 8) { PBQ_APPLY(8) }
+  else if (T <= 16) { PBQ_APPLY(16) }
+  else return hipErrorInvalidValue;
+#undef PBQ_APPLY
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Out = In M for a dense l x l M given column-major (Mt[j*ldm + k] = M[k][j]).
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In, int64_t ldi,
+                                                        int64_t len, int lp, int l,
+                                                        const T* __restrict__ Mt, int64_t ldm,
+                                                        T* __restrict__ Ocm, int64_t ldo,
+                                                        T* __restrict__ Orm, int64_t ldor) {
+  typedef typename Vec4<T>::type ACC;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int64_t arow = (int64_t)blockIdx.x * 64 + wave * 16 + li;
+  const int Tn = lp >> 4;
+  const bool in = arow < len;
+  ACC x[NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 16 * I + 4 * lg + r;
+      x[I][r] = (I < Tn && in) ? In[(int64_t)c * ldi + arow] : T(0);
+    }
+  }
+#pragma unroll
+  for (int J = 0; J < NT; ++J) {
+    if (J < Tn) {
+      ACC acc = {0, 0, 0, 0};
+#pragma unroll
+      for (int I = 0; I < NT; ++I) {
+        if (I < Tn) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const T a = Mt[(int64_t)(16 * J + li) * ldm + 16 * I + 4 * lg + s4];
+            acc = mma_native(a, x[I][s4], acc);
+          }
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * J + 4 * lg + r;
+        if (Ocm && arow < ldo) Ocm[(int64_t)c * ldo + arow] = acc[r];
+        if (Orm && in && c < l) Orm[arow * ldor + c] = acc[r];
+      }
+    }
+  }
+}
+
+hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
+                            const void* Mt, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
+                            int64_t ldor, hipStream_t s) {
+  const int T = lp / 16;
+  const int64_t rows = Ocm ? (ldo > len ? ldo : len) : len;
+  dim3 grid((unsigned)((rows + 63) / 64));
+#define PBQ_RM(NTV)                                                                               \
+  if (f64) hipLaunchKernelGGL((right_mul_kernel<double, NTV>), grid, dim3(256), 0, s,             \
+                              (const double*)In, ldi, len, lp, l, (const double*)Mt, ldm,         \
+                              (double*)Ocm, ldo, (double*)Orm, ldor);                             \
+  else hipLaunchKernelGGL((right_mul_kernel<float, NTV>), grid, dim3(256), 0, s,                  \
+                          (const float*)In, ldi, len, lp, l, (const float*)Mt, ldm, (float*)Ocm,  \
+                          ldo, (float*)Orm, ldor);
+  if (T <= 2) { PBQ_RM(2) }
+  else if (T <= 4) { PBQ_RM(4) }
+  else if (T <= 8) { PBQ_RM(8) }
+  else if (T <= 16) { PBQ_RM(16) }
+  else return hipErrorInvalidValue;
+#undef PBQ_RM
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversions between the caller's row-major tall matrices and the
+// internal column-major buffers (32 x 32 tiles through LDS).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void rm_to_cm_kernel(const T* __restrict__ X, int64_t ldx, int64_t len, int l,
+                                int lp32, T* __restrict__ Xt, int64_t ldt) {
+  __shared__ T tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;   // tall index
+  const int c0 = blockIdx.y * 32;                 // column index
+  const int tx = threadIdx.x, ty = threadIdx.y;   // 32 x 8
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r;
+    const int c = c0 + tx;
+    tile[r][tx] = (i < len && c < l) ? X[i * ldx + c] : T(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r;
+    const int64_t i = i0 + tx;
+    if (c < lp32 && i < ldt) Xt[(int64_t)c * ldt + i] = tile[tx][r];
+  }
+}
+
+template <typename T>
+__global__ void cm_to_rm_kernel(const T* __restrict__ Xt, int64_t ldt, int64_t len, int l,
+                                T* __restrict__ X, int64_t ldx) {
+  __shared__ T tile[32][33];
+  const int64_t i0 = (int64_t)blockIdx.x * 32;
+  const int c0 = blockIdx.y * 32;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  for (int r = ty; r < 32; r += 8) {
+    const int c = c0 + r;
+    const int64_t i = i0 + tx;
+    tile[r][tx] = (c < l && i < len) ? Xt[(int64_t)c * ldt + i] : T(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = i0 + r;
+    const int c = c0 + tx;
+    if (i < len && c < l) X[i * ldx + c] = tile[tx][r];
+  }
+}
+
+hipError_t launch_rm_to_cm(bool f64, const void* X, int64_t ldx, int64_t len, int l, int lp32,
+                           void* Xt, int64_t ldt, hipStream_t s) {
+  dim3 grid((unsigned)((ldt + 31) / 32), (unsigned)((lp32 + 31) / 32));
+  if (f64)
+    hipLaunchKernelGGL(rm_to_cm_kernel<double>, grid, dim3(32, 8), 0, s, (const double*)X, ldx,
+                       len, l, lp32, (double*)Xt, ldt);
+  else
+    hipLaunchKernelGGL(rm_to_cm_kernel<float>, grid, dim3(32, 8), 0, s, (const float*)X, ldx, len,
+                       l, lp32, (float*)Xt, ldt);
+  return hipGetLastError();
+}
+
+hipError_t launch_cm_to_rm(bool f64, const void* Xt, int64_t ldt, int64_t len, int l, void* X,
+                           int64_t ldx, hipStream_t s) {
+  dim3 grid((unsigned)((len + 31) / 32), (unsigned)((l + 31) / 32));
+  if (f64)
+    hipLaunchKernelGGL(cm_to_rm_kernel<double>, grid, dim3(32, 8), 0, s, (const double*)Xt, ldt,
+                       len, l, (double*)X, ldx);
+  else
+    hipLaunchKernelGGL(cm_to_rm_kernel<float>, grid, dim3(32, 8), 0, s, (const float*)Xt, ldt, len,
+                       l, (float*)X, ldx);
+  return hipGetLastError();
+}
+
+}  // namespace pbq

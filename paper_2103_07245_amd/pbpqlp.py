@@ -1,0 +1,263 @@
+"""Python binding of libpbpqlp.so (ctypes; argument marshalling only).
+
+Every computation runs in the library's HIP kernels on the tensor's device;
+this module only checks shapes, allocates outputs and workspace through
+PyTorch's caching allocator, and passes raw device pointers and the current
+HIP stream across the C ABI declared in include/pbpqlp.h.  There is no CPU
+fallback: if the library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpbpqlp.so")
+
+# enums of include/pbpqlp.h
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
+F64, F32 = 0, 1
+PREC = {"native": 0, "bf16": 1, "fp16": 2, "bf16x3": 3}
+FLAG_DEPENDENT, FLAG_NONFINITE = 1, 2
+
+# named precision plans: (sketch pass, power-iteration passes, projection pass)
+PLANS = {
+    "native": ("native", "native", "native"),
+    "bf16": ("bf16", "bf16", "bf16"),
+    "fp16": ("fp16", "fp16", "fp16"),
+    "mixed": ("bf16", "bf16", "bf16x3"),
+    "bf16x3": ("bf16x3", "bf16x3", "bf16x3"),
+}
+
+
+class PbpqlpError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib().pbpqlp_status_string(status).decode()
+        super().__init__(f"{where}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("sketch_prec", ctypes.c_int), ("power_prec", ctypes.c_int),
+                ("proj_prec", ctypes.c_int), ("split_k", ctypes.c_int),
+                ("fp16_scale_a", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+class InfoStruct(ctypes.Structure):
+    _fields_ = [("status_flags", ctypes.c_int), ("n_dependent", ctypes.c_int),
+                ("l", ctypes.c_int), ("q", ctypes.c_int), ("norm_a_fro2", ctypes.c_double),
+                ("norm_l_fro2", ctypes.c_double), ("resid_rel_est", ctypes.c_double),
+                ("reserved", ctypes.c_double * 2)]
+
+
+INFO_BYTES = ctypes.sizeof(InfoStruct)
+
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no fallback path")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, u64, dp = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
+                                 ctypes.c_void_p)
+        lib.pbpqlp_status_string.restype = ctypes.c_char_p
+        lib.pbpqlp_status_string.argtypes = [i32]
+        lib.pbpqlp_version.restype = i32
+        lib.pbpqlp_default_opts.argtypes = [ctypes.POINTER(Opts)]
+        lib.pbpqlp_workspace_size.restype = i32
+        lib.pbpqlp_workspace_size.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(Opts),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+        lib.pbpqlp_factor.restype = i32
+        lib.pbpqlp_factor.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, u64, vp, i64, dp, i64,
+                                      vp, i64, ctypes.POINTER(Opts), vp, vp]
+        lib.pbpqlp_omega.restype = i32
+        lib.pbpqlp_omega.argtypes = [i64, i32, u64, i32, vp, i64, vp]
+        lib.pbpqlp_matmul.restype = i32
+        lib.pbpqlp_matmul.argtypes = [i32, vp, i64, i64, i64, i32, vp, i64, i32, i32,
+                                      ctypes.c_double, vp, i64, vp]
+        lib.pbpqlp_orth.restype = i32
+        lib.pbpqlp_orth.argtypes = [vp, i64, i32, i64, i32, i32, vp, i64, dp, i64, vp, vp]
+        lib.pbpqlp_small_qr.restype = i32
+        lib.pbpqlp_small_qr.argtypes = [dp, i32, i64, dp, i64, dp, i64, vp, vp]
+        _LIB = lib
+    return _LIB
+
+
+def library():
+    """The loaded ctypes handle (loads it on first use)."""
+    return _lib()
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise PbpqlpError(status, where)
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {t.dtype}: use float32 or float64")
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _rowmajor(t: torch.Tensor, name: str) -> torch.Tensor:
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        t = t.contiguous()
+    return t
+
+
+def make_opts(plan="native", split_k: int = 0, fp16_scale_a: float = 1.0) -> Opts:
+    if isinstance(plan, str):
+        plan = PLANS[plan]
+    o = Opts()
+    _lib().pbpqlp_default_opts(ctypes.byref(o))
+    o.sketch_prec, o.power_prec, o.proj_prec = (PREC[x] for x in plan)
+    o.split_k = split_k
+    o.fp16_scale_a = fp16_scale_a
+    return o
+
+
+@dataclass
+class Info:
+    status_flags: int
+    n_dependent: int
+    l: int
+    q: int
+    norm_a_fro2: float
+    norm_l_fro2: float
+    resid_rel_est: float
+
+    @staticmethod
+    def from_device(buf: torch.Tensor) -> "Info":
+        raw = bytes(buf.cpu().numpy().tobytes())
+        s = InfoStruct.from_buffer_copy(raw[:INFO_BYTES])
+        return Info(s.status_flags, s.n_dependent, s.l, s.q, s.norm_a_fro2, s.norm_l_fro2,
+                    s.resid_rel_est)
+
+
+def workspace_size(m: int, n: int, k: int, p: int, dtype=torch.float32, plan="native") -> int:
+    sz = ctypes.c_size_t(0)
+    o = make_opts(plan)
+    _check(_lib().pbpqlp_workspace_size(m, n, k, p, F64 if dtype == torch.float64 else F32,
+                                        ctypes.byref(o), ctypes.byref(sz)), "pbpqlp_workspace_size")
+    return int(sz.value)
+
+
+class Factorizer:
+    """Reusable factorization of one problem shape: holds the workspace, the
+    outputs and the device info record so repeated calls allocate nothing."""
+
+    def __init__(self, m: int, n: int, k: int, p: int, q: int, dtype=torch.float32,
+                 plan="native", device="cuda", split_k: int = 0, fp16_scale_a: float = 1.0):
+        self.m, self.n, self.k, self.p, self.q = m, n, k, p, q
+        self.l = k + p
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.opts = make_opts(plan, split_k, fp16_scale_a)
+        ws = workspace_size(m, n, k, p, dtype, plan)
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        self.opts.workspace = self.workspace.data_ptr()
+        self.opts.workspace_bytes = self.workspace.numel()
+        self.Q = torch.empty((m, self.l), dtype=dtype, device=self.device)
+        self.P = torch.empty((n, self.l), dtype=dtype, device=self.device)
+        self.L = torch.empty((self.l, self.l), dtype=torch.float64, device=self.device)
+        self.info_buf = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=self.device)
+
+    def __call__(self, A: torch.Tensor, seed: int):
+        A = _rowmajor(A, "A")
+        if A.shape != (self.m, self.n) or A.dtype != self.dtype or A.device != self.device:
+            raise ValueError("A does not match this factorizer's shape/dtype/device")
+        st = _lib().pbpqlp_factor(
+            ctypes.c_void_p(A.data_ptr()), self.m, self.n, A.stride(0), _dt(A), self.k, self.p,
+            self.q, ctypes.c_uint64(seed), ctypes.c_void_p(self.Q.data_ptr()), self.l,
+            ctypes.c_void_p(self.L.data_ptr()), self.l, ctypes.c_void_p(self.P.data_ptr()),
+            self.l, ctypes.byref(self.opts), ctypes.c_void_p(self.info_buf.data_ptr()),
+            _stream(self.device))
+        _check(st, "pbpqlp_factor")
+        return self.Q, self.L, self.P
+
+    def info(self) -> Info:
+        return Info.from_device(self.info_buf)
+
+
+def factor(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", split_k: int = 0,
+           fp16_scale_a: float = 1.0) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor, Info]:
+    """PbP-QLP of a device matrix A (m x n, float32/float64): returns
+    (Q, L, P, info) with A ~= Q @ L.T @ P.T."""
+    A = _rowmajor(A, "A")
+    f = Factorizer(A.shape[0], A.shape[1], k, p, q, A.dtype, plan, A.device, split_k, fp16_scale_a)
+    Q, L, P = f(A, seed)
+    return Q, L, P, f.info()
+
+
+def omega(n: int, l: int, seed: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
+    out = torch.empty((n, l), dtype=dtype, device=device)
+    _check(_lib().pbpqlp_omega(n, l, ctypes.c_uint64(seed), _dt(out), ctypes.c_void_p(out.data_ptr()),
+                               l, _stream(out.device)), "pbpqlp_omega")
+    return out
+
+
+def matmul(A: torch.Tensor, X: torch.Tensor, trans: bool = False, prec: str = "native",
+           fp16_scale_a: float = 1.0) -> torch.Tensor:
+    """Y = A @ X (trans=False) or A.T @ X through the streaming kernels."""
+    A = _rowmajor(A, "A")
+    X = _rowmajor(X, "X")
+    m, n = A.shape
+    rows = n if trans else m
+    if X.shape[0] != (m if trans else n) or X.dtype != A.dtype:
+        raise ValueError("X shape/dtype mismatch")
+    l = X.shape[1]
+    Y = torch.empty((rows, l), dtype=A.dtype, device=A.device)
+    _check(_lib().pbpqlp_matmul(1 if trans else 0, ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0),
+                                _dt(A), ctypes.c_void_p(X.data_ptr()), X.stride(0), l, PREC[prec],
+                                fp16_scale_a, ctypes.c_void_p(Y.data_ptr()), l,
+                                _stream(A.device)), "pbpqlp_matmul")
+    return Y
+
+
+def orth(Y: torch.Tensor, passes: int = 2, want_r: bool = True):
+    """Y = Q R (CholeskyQR sweeps with FP64 Grams); returns (Q, R or None, Info)."""
+    Y = _rowmajor(Y, "Y")
+    rows, l = Y.shape
+    Q = torch.empty_like(Y)
+    R = torch.empty((l, l), dtype=torch.float64, device=Y.device) if want_r else None
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=Y.device)
+    _check(_lib().pbpqlp_orth(ctypes.c_void_p(Y.data_ptr()), rows, l, Y.stride(0), _dt(Y), passes,
+                              ctypes.c_void_p(Q.data_ptr()), l,
+                              ctypes.c_void_p(R.data_ptr() if R is not None else 0), l,
+                              ctypes.c_void_p(info.data_ptr()), _stream(Y.device)), "pbpqlp_orth")
+    return Q, R, Info.from_device(info)
+
+
+def small_qr(R: torch.Tensor):
+    """R^T = Qt L^T for an upper-triangular FP64 R (l x l); returns (Qt, L)."""
+    R = _rowmajor(R, "R")
+    if R.dtype != torch.float64:
+        raise TypeError("R must be float64")
+    l = R.shape[0]
+    Qt = torch.empty((l, l), dtype=torch.float64, device=R.device)
+    L = torch.empty((l, l), dtype=torch.float64, device=R.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=R.device)
+    _check(_lib().pbpqlp_small_qr(ctypes.c_void_p(R.data_ptr()), l, R.stride(0),
+                                  ctypes.c_void_p(Qt.data_ptr()), l, ctypes.c_void_p(L.data_ptr()),
+                                  l, ctypes.c_void_p(info.data_ptr()), _stream(R.device)),
+           "pbpqlp_small_qr")
+    return Qt, L

@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/pbpqlp.h declares, and rejects bad arguments
+synchronously, before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2103_07245_amd import pbpqlp as B
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "pbpqlp.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pbpqlp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.library()
+    names = _declared_functions()
+    assert "pbpqlp_factor" in names and len(names) >= 8
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_status_strings():
+    lib = B.library()
+    assert lib.pbpqlp_version() == 100
+    for s in range(5):
+        assert lib.pbpqlp_status_string(s).startswith(b"PBPQLP")
+
+
+def test_info_struct_layout():
+    assert ctypes.sizeof(B.InfoStruct) == 56
+    assert ctypes.sizeof(B.Opts) == 40
+
+
+FAKE = ctypes.c_void_p(0x1000)
+
+
+def _factor(m=100, n=80, lda=80, dt=B.F32, k=5, p=3, q=1, ldq=8, ldl=8, ldp=8, opts=None):
+    lib = B.library()
+    return lib.pbpqlp_factor(FAKE, m, n, lda, dt, k, p, q, ctypes.c_uint64(1), ctypes.c_void_p(0x2000),
+                             ldq, ctypes.c_void_p(0x3000), ldl, ctypes.c_void_p(0x4000), ldp,
+                             opts, None, None)
+
+
+@pytest.mark.parametrize("kw", [dict(k=0), dict(p=-1), dict(k=80, p=1), dict(q=17), dict(q=-1),
+                                dict(lda=79), dict(ldq=7), dict(ldl=7), dict(ldp=7), dict(m=0),
+                                dict(dt=7)])
+def test_invalid_arguments_rejected_before_launch(kw):
+    assert _factor(**kw) == B.EINVAL
+
+
+def test_unsupported_width_and_precision():
+    assert _factor(m=400, n=400, lda=400, k=250, p=10, ldq=260, ldl=260, ldp=260) == B.EUNSUPPORTED
+    o = B.make_opts("bf16")
+    assert _factor(dt=B.F64, opts=ctypes.byref(o)) == B.EUNSUPPORTED
+
+
+def test_null_pointers_rejected():
+    lib = B.library()
+    st = lib.pbpqlp_factor(None, 10, 10, 10, B.F32, 2, 1, 0, ctypes.c_uint64(1), FAKE, 3, FAKE, 3,
+                           FAKE, 3, None, None, None)
+    assert st == B.EINVAL
+
+
+def test_workspace_size_grows_with_problem():
+    a = B.workspace_size(1000, 800, 20, 5)
+    b = B.workspace_size(4000, 800, 20, 5)
+    c = B.workspace_size(4000, 800, 60, 4)
+    assert 0 < a < b < c
+    # mixed precision needs the 16-bit operand copies
+    assert B.workspace_size(1000, 800, 20, 5, plan="mixed") > a
+
+
+def test_too_small_workspace_rejected():
+    o = B.make_opts("native")
+    o.workspace = 0x10000
+    o.workspace_bytes = 1024
+    assert _factor(opts=ctypes.byref(o)) == B.ENOMEM

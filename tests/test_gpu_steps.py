@@ -1,0 +1,192 @@
+"""Step-level GPU parity: each C-ABI step entry point against the oracle's
+definition of that step, on seeded inputs with ragged sizes.
+
+* sketch generator: bit-exact against the oracle's independent twin;
+* A-streaming products, every precision: against the FP64 product of the
+  operands rounded the way the precision defines (so rounding mode and
+  matrix-core lane layout are both pinned), to FP32-accumulation tolerance;
+* orth / qr (CholeskyQR): against the oracle's sign-normalized Householder QR;
+* the l x l QR of R^T: against the oracle's Householder QR.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import bf16_rne, householder_qr, omega as oracle_omega
+from paper_2103_07245_amd import pbpqlp as B
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("n,l,seed", [(1000, 25, 1_500_000), (257, 1, 3), (333, 17, 2**40 + 5),
+                                      (64, 256, 77)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_omega_bit_exact(n, l, seed, dtype):
+    print(f"omega n={n} l={l} seed={seed} {dtype}", flush=True)
+    g = _host(B.omega(n, l, seed, dtype=dtype, device=DEV))
+    ref = oracle_omega(n, l, seed)
+    assert np.array_equal(g, ref)
+
+
+def _round16(x, prec, scale=1.0):
+    if prec == "bf16":
+        return bf16_rne(x), None
+    if prec == "fp16":
+        return (x * scale).astype(np.float16).astype(np.float64) / scale, None
+    if prec == "bf16x3":
+        hi = bf16_rne(x)
+        lo = bf16_rne(x - hi)
+        return hi, lo
+    return x, None
+
+
+def _ref_product(A, X, trans, prec, a_scale=1.0):
+    Am = A.T if trans else A
+    if prec in ("native",):
+        return Am @ X
+    if prec == "bf16x3":
+        ah, al = _round16(Am, prec)
+        xh, xl = _round16(X, prec)
+        return ah @ xh + ah @ xl + al @ xh
+    a16, _ = _round16(Am, prec, a_scale)
+    x16, _ = _round16(X, prec)
+    return a16 @ x16
+
+
+SHAPES = [(1000, 777, 25), (129, 70, 7), (70, 129, 16), (3000, 520, 33), (515, 300, 220),
+          (256, 256, 256), (40, 33, 1)]
+
+
+@pytest.mark.parametrize("m,n,l", SHAPES)
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("prec", ["native", "bf16", "fp16", "bf16x3"])
+def test_streaming_product(m, n, l, trans, prec):
+    print(f"matmul m={m} n={n} l={l} trans={trans} prec={prec}", flush=True)
+    rng = synth.rng_for(m * 7 + n * 3 + l)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    X = rng.standard_normal((m if trans else n, l)).astype(np.float32)
+    Y = _host(B.matmul(_dev(A), _dev(X), trans=trans, prec=prec))
+    ref = _ref_product(A.astype(np.float64), X.astype(np.float64), trans, prec)
+    # FP32 accumulation of products that are exact in FP32: elementwise the
+    # rigorous bound |err| <= gamma_K |A| |X| (K terms, 3K for the split form),
+    # and normwise the random-walk level sqrt(K) u32.
+    K = (m if trans else n) * (3 if prec == "bf16x3" else 1)
+    Am = np.abs(A.T if trans else A).astype(np.float64)
+    absprod = Am @ np.abs(X).astype(np.float64)
+    u = 2.0 ** -24
+    assert np.all(np.abs(Y - ref) <= 1.01 * K * u * absprod + 1e-30)
+    assert np.linalg.norm(Y - ref) <= 4 * np.sqrt(K) * u * np.linalg.norm(absprod)
+
+
+@pytest.mark.parametrize("m,n,l", SHAPES[:5])
+@pytest.mark.parametrize("trans", [False, True])
+def test_streaming_product_f64(m, n, l, trans):
+    print(f"matmul f64 m={m} n={n} l={l} trans={trans}", flush=True)
+    rng = synth.rng_for(m * 5 + n + l)
+    A = rng.standard_normal((m, n))
+    X = rng.standard_normal((m if trans else n, l))
+    Y = _host(B.matmul(_dev(A), _dev(X), trans=trans))
+    ref = (A.T if trans else A) @ X
+    assert np.abs(Y - ref).max() <= 1e-13 * np.abs(ref).max() * np.sqrt(m if trans else n)
+
+
+def test_streaming_product_padded_lda_and_fp16_scale():
+    rng = synth.rng_for(4242)
+    m, n, l = 300, 101, 12
+    big = rng.standard_normal((m, n + 7)).astype(np.float32) * 4096.0
+    A = _dev(big)[:, :n]          # lda = n + 7 (unaligned rows: scalar load path)
+    X = rng.standard_normal((n, l)).astype(np.float32)
+    Y = _host(B.matmul(A, _dev(X), prec="native"))
+    ref = big[:, :n].astype(np.float64) @ X.astype(np.float64)
+    assert np.abs(Y - ref).max() <= 1e-5 * np.abs(ref).max()
+    # FP16 with a power-of-two prescale keeps |A| in half range
+    Y16 = _host(B.matmul(A.contiguous(), _dev(X), prec="fp16", fp16_scale_a=2.0 ** -12))
+    ref16 = _ref_product(big[:, :n].astype(np.float64), X.astype(np.float64), False, "fp16", 2.0 ** -12)
+    assert np.linalg.norm(Y16 - ref16) <= 1e-5 * np.linalg.norm(ref16)
+
+
+def _signed_qr(Y):
+    return householder_qr(Y)
+
+
+@pytest.mark.parametrize("rows,l,dtype", [(1000, 25, torch.float64), (5000, 80, torch.float32),
+                                          (300, 220, torch.float64), (777, 33, torch.float32),
+                                          (64, 64, torch.float64)])
+def test_orth_matches_householder(rows, l, dtype):
+    print(f"orth rows={rows} l={l} {dtype}", flush=True)
+    rng = synth.rng_for(rows + l)
+    # moderately conditioned (kappa ~ 1e3)
+    U = synth.haar_panel(rng, rows, l)
+    V = synth.haar_panel(rng, l, l)
+    Y = (U * np.logspace(0, -3, l)) @ V.T
+    if dtype == torch.float32:
+        Y = Y.astype(np.float32).astype(np.float64)
+    Q, R, info = B.orth(_dev(Y).to(dtype), passes=2)
+    Qh, Rh = _host(Q), _host(R)
+    Qo, Ro = _signed_qr(Y)
+    eps = 1e-12 if dtype == torch.float64 else 2e-4
+    assert np.abs(Qh - Qo).max() <= eps
+    assert np.abs(Rh - Ro).max() <= eps * np.abs(Ro).max()
+    assert np.abs(Qh.T @ Qh - np.eye(l)).max() <= (1e-13 if dtype == torch.float64 else 1e-5)
+    assert np.array_equal(np.tril(Rh, -1), np.zeros_like(Rh))
+    assert info.status_flags == 0
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_orth_dependent_columns_completed(dtype):
+    rng = synth.rng_for(99)
+    rows, l, r = 500, 20, 7
+    Y = rng.standard_normal((rows, r)) @ rng.standard_normal((r, l))
+    Y[:, 3] = 0.0                      # an exactly zero column as well
+    Q, R, info = B.orth(_dev(Y).to(dtype), passes=2)
+    Qh, Rh = _host(Q), _host(R)
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert np.abs(Qh.T @ Qh - np.eye(l)).max() <= tol * 10
+    assert np.abs(Qh @ Rh - Y).max() <= tol * np.abs(Y).max() * 10
+    assert info.status_flags & B.FLAG_DEPENDENT
+    assert info.n_dependent >= l - r
+    # the span of the leading independent columns matches Householder's
+    Qo, _ = _signed_qr(Y)
+    assert np.abs(Qh[:, :3] - Qo[:, :3]).max() <= tol * 1e3
+
+
+def test_orth_zero_matrix():
+    Y = np.zeros((100, 8))
+    Q, R, info = B.orth(_dev(Y), passes=2)
+    Qh, Rh = _host(Q), _host(R)
+    assert np.abs(Qh.T @ Qh - np.eye(8)).max() <= 1e-13
+    assert np.array_equal(Rh, np.zeros((8, 8)))
+    assert info.n_dependent == 8 and (info.status_flags & B.FLAG_DEPENDENT)
+
+
+def test_orth_nonfinite_flagged():
+    Y = np.ones((100, 4))
+    Y[5, 2] = np.nan
+    _, _, info = B.orth(_dev(Y), passes=1)
+    assert info.status_flags & B.FLAG_NONFINITE
+
+
+@pytest.mark.parametrize("l", [1, 5, 25, 80, 220, 256])
+def test_small_qr_matches_householder(l):
+    print(f"small_qr l={l}", flush=True)
+    rng = synth.rng_for(3000 + l)
+    # a well-conditioned triangular factor (kappa = 60): the R of a planted matrix
+    M = (synth.haar_panel(rng, 2 * l, l) * np.linspace(3.0, 0.05, l)) @ synth.haar_panel(rng, l, l).T
+    _, R = householder_qr(M)
+    Qt, L = B.small_qr(_dev(R))
+    Qh, Lh = _host(Qt), _host(L)
+    Qo, Uo = householder_qr(R.T)
+    assert np.abs(Qh - Qo).max() <= 1e-11
+    assert np.abs(Lh - Uo.T).max() <= 1e-11 * np.abs(Uo).max()
+    assert np.array_equal(np.triu(Lh, 1), np.zeros_like(Lh))
