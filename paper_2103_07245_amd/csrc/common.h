@@ -82,8 +82,8 @@ __device__ __forceinline__ double sketch_value(double z) {
 // Matrix-core wrappers (16 x 16 output tile per wave).
 // Operand layout for all of them: lane t supplies row (t % 16) of the A tile
 // and column (t % 16) of the B tile; lane group g = t / 16 supplies the
-// contraction slice g.  The 4-register accumulator of lane t holds rows
-// 4 g + r (r = 0..3) of column t % 16.
+// contraction slice g.  The 4-register accumulator of lane t holds column
+// t % 16, rows acc_row<T>(g, r) (r = 0..3).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ f32x4 mma_f32(float a, float b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -96,6 +96,14 @@ __device__ __forceinline__ f32x4 mma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
 }
 __device__ __forceinline__ f32x4 mma_f16(f16x8 a, f16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Row (within the 16x16 tile) held by accumulator register r of lane group
+// g.  FP32 tiles put rows 4g..4g+3 in one lane group; the FP64 matrix core
+// interleaves them (row g + 4r), as measured on gfx950.  Operand layouts are
+// the same for both: lane t supplies A[t % 16][t / 16] and B[t / 16][t % 16].
+template <typename T> __device__ __forceinline__ constexpr int acc_row(int g, int r) {
+  return sizeof(T) == 8 ? g + 4 * r : 4 * g + r;
 }
 
 template <typename T> struct Vec4;

@@ -55,11 +55,12 @@ int resolve_mode(pbpqlp_dtype dt, int prec, bool* ok) {
 
 // Relative pivot threshold below which a Cholesky column counts as
 // dependent: the larger of (32 u_data)^2 (a residual below 32 rounding units
-// of the data is noise) and 4 l u_64 (the Gram's own rounding level).
+// of the data is noise) and 16 l u_64 (the cancellation level of a pivot
+// computed from an FP64 Gram).
 double dep_eps(bool f64, int l) {
   const double u64 = 1.1102230246251565e-16, u32 = 5.9604644775390625e-08;
   const double ud = f64 ? u64 : u32;
-  const double a = (32.0 * ud) * (32.0 * ud), b = 4.0 * l * u64;
+  const double a = (32.0 * ud) * (32.0 * ud), b = 16.0 * l * u64;
   return a > b ? a : b;
 }
 
@@ -358,6 +359,7 @@ pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_d
   if (s) return s;
   Bump b;
   c.carve(b, needs16(c));
+  b.take(sizeof(pbpqlp_info));
   *bytes = b.off + 256;
   return PBPQLP_OK;
 }
@@ -374,26 +376,30 @@ pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pb
   if (Q == A || P == A || (const void*)L == A || Q == P) return PBPQLP_EINVAL;
   c.seed = seed;
   hipStream_t st = (hipStream_t)stream;
+  const bool n16 = needs16(c);
   Bump sizer;
-  c.carve(sizer, needs16(c));
-  const size_t need = sizer.off + 256;
+  c.carve(sizer, n16);
+  sizer.take(sizeof(pbpqlp_info));
+  const size_t need = sizer.off + 256;   // + alignment slack for an unaligned caller block
   ScratchGuard g;
   char* base;
+  size_t avail;
   if (opts && opts->workspace) {
-    if (opts->workspace_bytes < need) return PBPQLP_ENOMEM;
     base = (char*)opts->workspace;
+    avail = opts->workspace_bytes;
+    if (avail < need) return PBPQLP_ENOMEM;
   } else {
-    s = alloc_scratch(g, need + sizeof(pbpqlp_info), st);
+    s = alloc_scratch(g, need, st);
     if (s) return s;
     base = (char*)g.p;
+    avail = need;
   }
   Bump b;
   b.base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
-  c.carve(b, needs16(c));
-  pbpqlp_info* info = d_info;
-  if (!info) info = (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
-  if (!info) return PBPQLP_ENOMEM;
-  if (opts && opts->workspace && b.off > opts->workspace_bytes) return PBPQLP_ENOMEM;
+  c.carve(b, n16);
+  pbpqlp_info* own = (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  if ((size_t)(b.base + b.off - base) > avail) return PBPQLP_ENOMEM;
+  pbpqlp_info* info = d_info ? d_info : own;
   return run_factor(c, A, Q, ldq, L, ldl, P, ldp, info, st);
 }
 
@@ -434,27 +440,26 @@ pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int6
   hipStream_t st = (hipStream_t)stream;
   const int64_t xlen = trans ? m : n, ylen = trans ? n : m;
   const int64_t ldxi = trans ? c.ldm : c.ldn, ldyo = trans ? c.ldn : c.ldm;
-  // scratch: Xt, Yt, 16-bit copies, split partials
+  // scratch: Xt, Yt, 16-bit copies, split partials (one carve sizes and hands out)
   const int64_t ldmax = c.ldm > c.ldn ? c.ldm : c.ldn;
-  Bump sz;
-  sz.take((size_t)c.lp32 * ldxi * c.el);
-  sz.take((size_t)c.lp32 * ldyo * c.el);
-  sz.take((size_t)c.lp32 * ldmax * 2);
-  sz.take((size_t)c.lp32 * ldmax * 2);
   const size_t p1 = (size_t)c.k1s.S * c.lp * c.ldm * c.el, p2 = (size_t)c.k2s.S * c.lp * c.ldn * c.el;
-  sz.take(p1 > p2 ? p1 : p2);
-  sz.take((size_t)c.k1_blocks * c.k1s.S * 8);
+  void *Xt = nullptr, *Yt = nullptr;
+  auto carve = [&](Bump& b) {
+    Xt = b.take((size_t)c.lp32 * ldxi * c.el);
+    Yt = b.take((size_t)c.lp32 * ldyo * c.el);
+    c.Xhi = b.take((size_t)c.lp32 * ldmax * 2);
+    c.Xlo = b.take((size_t)c.lp32 * ldmax * 2);
+    c.part = b.take(p1 > p2 ? p1 : p2);
+    c.normA = (double*)b.take((size_t)c.k1_blocks * c.k1s.S * 8);
+  };
+  Bump sz;
+  carve(sz);
   ScratchGuard g;
   pbpqlp_status s = alloc_scratch(g, sz.off + 256, st);
   if (s) return s;
   Bump b;
   b.base = (char*)g.p;
-  void* Xt = b.take((size_t)c.lp32 * ldxi * c.el);
-  void* Yt = b.take((size_t)c.lp32 * ldyo * c.el);
-  c.Xhi = b.take((size_t)c.lp32 * ldmax * 2);
-  c.Xlo = b.take((size_t)c.lp32 * ldmax * 2);
-  c.part = b.take(p1 > p2 ? p1 : p2);
-  c.normA = (double*)b.take((size_t)c.k1_blocks * c.k1s.S * 8);
+  carve(b);
   PBQ_CHECK(launch_rm_to_cm(c.f64, X, ldx, xlen, l, c.lp32, Xt, ldxi, st));
   s = stream_pass(c, trans != 0, mode, A, Xt, ldxi, xlen, false, Yt, ldyo, nullptr, st);
   if (s) return s;
@@ -476,37 +481,35 @@ pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpql
   c.ldm = rup(rows, 64);
   c.seed = 0x5EEDull;
   hipStream_t st = (hipStream_t)stream;
+  void *Xt = nullptr, *Out = nullptr, *Tmp = nullptr;
+  double* Rk = nullptr;
+  pbpqlp_info* info = d_info;
+  // the same carve sizes the scratch and hands out its pieces
+  auto carve = [&](Bump& b) {
+    Xt = b.take((size_t)c.lp32 * c.ldm * c.el);
+    Out = b.take((size_t)c.lp32 * c.ldm * c.el);
+    Tmp = b.take((size_t)c.lp32 * c.ldm * c.el);
+    c.gpart = (double*)b.take(gram_partial_elems(rows, c.lp) * 8);
+    c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
+    Rk = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.Ra = b.take((size_t)c.lp * c.lp * 8);
+    c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
+    c.Ra64 = b.take((size_t)c.lp * c.lp * 8);
+    c.Dinv64 = b.take((size_t)(c.lp / 16) * 256 * 8);
+    c.dep = (int*)b.take((size_t)c.lp * 4);
+    void* own = b.take(sizeof(pbpqlp_info));
+    if (!d_info) info = (pbpqlp_info*)own;
+  };
   Bump sz;
-  sz.take((size_t)c.lp32 * c.ldm * c.el);
-  sz.take((size_t)c.lp32 * c.ldm * c.el);
-  sz.take((size_t)c.lp32 * c.ldm * c.el);
-  sz.take(gram_partial_elems(rows, c.lp) * 8);
-  for (int i = 0; i < 4; ++i) sz.take((size_t)c.lp * c.lp * 8);
-  sz.take((size_t)c.lp * c.lp * 8);
-  sz.take((size_t)(c.lp / 16) * 256 * 8);
-  sz.take((size_t)c.lp * c.lp * 8);
-  sz.take((size_t)(c.lp / 16) * 256 * 8);
-  sz.take((size_t)c.lp * 4);
-  sz.take(sizeof(pbpqlp_info));
+  carve(sz);
   ScratchGuard g;
   pbpqlp_status s = alloc_scratch(g, sz.off + 256, st);
   if (s) return s;
   Bump b;
   b.base = (char*)g.p;
-  void* Xt = b.take((size_t)c.lp32 * c.ldm * c.el);
-  void* Out = b.take((size_t)c.lp32 * c.ldm * c.el);
-  void* Tmp = b.take((size_t)c.lp32 * c.ldm * c.el);
-  c.gpart = (double*)b.take(gram_partial_elems(rows, c.lp) * 8);
-  c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
-  double* Rk = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.Ra = b.take((size_t)c.lp * c.lp * 8);
-  c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
-  c.Ra64 = b.take((size_t)c.lp * c.lp * 8);
-  c.Dinv64 = b.take((size_t)(c.lp / 16) * 256 * 8);
-  c.dep = (int*)b.take((size_t)c.lp * 4);
-  pbpqlp_info* info = d_info ? d_info : (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  carve(b);
   if (!d_info) PBQ_CHECK(launch_info_init(info, l, 0, st));
   PBQ_CHECK(launch_rm_to_cm(c.f64, Y, ldy, rows, l, c.lp32, Xt, c.ldm, st));
   s = orth(c, c.f64, Xt, c.ldm, rows, passes, Out, Tmp, R ? Rk : nullptr, c.lp, Q, ldq, info, st);
@@ -525,30 +528,30 @@ pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, i
   c.ldS = rup(c.lp, 64);
   c.seed = 0x5A11ull;
   hipStream_t st = (hipStream_t)stream;
+  pbpqlp_info* info = d_info;
+  auto carve = [&](Bump& b) {
+    c.Rfin = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
+    c.M1 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
+    c.Qt64 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
+    c.gpart = (double*)b.take(gram_partial_elems(l, c.lp) * 8);
+    c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.U = (double*)b.take((size_t)c.lp * c.lp * 8);
+    c.Ra64 = c.Ra = b.take((size_t)c.lp * c.lp * 8);
+    c.Dinv64 = c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
+    c.dep = (int*)b.take((size_t)c.lp * 4);
+    void* own = b.take(sizeof(pbpqlp_info));
+    if (!d_info) info = (pbpqlp_info*)own;
+  };
   Bump sz;
-  for (int i = 0; i < 3; ++i) sz.take((size_t)c.lp32 * c.ldS * 8);
-  sz.take(gram_partial_elems(l, c.lp) * 8);
-  for (int i = 0; i < 4; ++i) sz.take((size_t)c.lp * c.lp * 8);
-  sz.take((size_t)(c.lp / 16) * 256 * 8);
-  sz.take((size_t)c.lp * 4);
-  sz.take(sizeof(pbpqlp_info));
+  carve(sz);
   ScratchGuard g;
   pbpqlp_status s = alloc_scratch(g, sz.off + 256, st);
   if (s) return s;
   Bump b;
   b.base = (char*)g.p;
-  c.Rfin = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
-  c.M1 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
-  c.Qt64 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
-  c.gpart = (double*)b.take(gram_partial_elems(l, c.lp) * 8);
-  c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.U = (double*)b.take((size_t)c.lp * c.lp * 8);
-  c.Ra64 = c.Ra = b.take((size_t)c.lp * c.lp * 8);
-  c.Dinv64 = c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
-  c.dep = (int*)b.take((size_t)c.lp * 4);
-  pbpqlp_info* info = d_info ? d_info : (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  carve(b);
   if (!d_info) PBQ_CHECK(launch_info_init(info, l, 0, st));
   PBQ_CHECK(launch_fill_zero(c.Rfin, (size_t)c.lp32 * c.ldS * 8, st));
   PBQ_CHECK(launch_copy_mat(R, ldr, l, l, c.Rfin, c.ldS, 1, st));

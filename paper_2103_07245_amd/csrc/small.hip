@@ -59,8 +59,8 @@ __global__ __launch_bounds__(1024) void chol_kernel(const double* __restrict__ G
     tv[s] = idx < ntiles;
     int K = 0;
     while ((K + 1) * (K + 2) / 2 <= idx) ++K;
-    tK[s] = K;
-    tI[s] = idx - K * (K + 1) / 2;
+    tK[s] = tv[s] ? K : 0;                 // unused slots point at tile (0,0)
+    tI[s] = tv[s] ? idx - K * (K + 1) / 2 : 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       tile[s][r] = tv[s] ? G[(int64_t)(16 * tI[s] + 4 * lg + r) * ldg + 16 * tK[s] + li] : 0.0;

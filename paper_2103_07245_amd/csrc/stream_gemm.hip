@@ -120,22 +120,24 @@ template <typename T> struct AccOf;
 template <> struct AccOf<float> { typedef f32x4 type; };
 template <> struct AccOf<double> { typedef f64x4 type; };
 
-// Store one 4-row accumulator column slice: out[col * ld + r0 + 0..3].
+// Store one accumulator column slice: rows acc_row(g, r) of a 16-row tile
+// starting at `tile_row`, i.e. out[col * ld + tile_row + acc_row(g, r)].
 template <typename T, typename ACC>
-__device__ __forceinline__ void store4(T* out, int64_t ld, int64_t col, int64_t r0, int64_t rend,
-                                       const ACC& v, float scale) {
-  T* p = out + col * ld + r0;
-  if (r0 + 3 < rend) {
-    if constexpr (sizeof(T) == 4) {
+__device__ __forceinline__ void store4(T* out, int64_t ld, int64_t col, int64_t tile_row, int g,
+                                       int64_t rend, const ACC& v, float scale) {
+  T* p = out + col * ld + tile_row;
+  if constexpr (sizeof(T) == 4) {
+    const int64_t r0 = tile_row + 4 * g;
+    if (r0 + 3 < rend) {
       f32x4 w = {v[0] * scale, v[1] * scale, v[2] * scale, v[3] * scale};
-      *(f32x4*)p = w;
-    } else {
-      p[0] = v[0]; p[1] = v[1]; p[2] = v[2]; p[3] = v[3];
+      *(f32x4*)(p + 4 * g) = w;
+      return;
     }
-  } else {
+  }
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (r0 + r < rend) p[r] = (T)(v[r] * scale);
+  for (int r = 0; r < 4; ++r) {
+    const int rr = acc_row<T>(g, r);
+    if (tile_row + rr < rend) p[rr] = (T)(v[r] * scale);
   }
 }
 
@@ -266,7 +268,7 @@ __global__ __launch_bounds__(256) void k1_ax(
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct)
-      if (ct < T) store4<TACC>(out, ldy, 16 * ct + li, row0 + 16 * rt + 4 * lg, m, acc[rt][ct], out_scale);
+      if (ct < T) store4<TACC>(out, ldy, 16 * ct + li, row0 + 16 * rt, lg, m, acc[rt][ct], out_scale);
 
   if (normA) {
     __shared__ double red[4];
@@ -411,8 +413,8 @@ __global__ __launch_bounds__(256) void k2_atx(
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct)
       if (ct < T)
-        store4<TACC>(out, ldz, 16 * ct + li, j0 + 16 * JT * wave + 16 * jt + 4 * lg, n,
-                     acc[jt][ct], out_scale);
+        store4<TACC>(out, ldz, 16 * ct + li, j0 + 16 * JT * wave + 16 * jt, lg, n, acc[jt][ct],
+                     out_scale);
 }
 
 // ---------------------------------------------------------------------------

@@ -226,7 +226,8 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   }
   double* out = part + ((int64_t)blockIdx.y * gridDim.x + p) * 1024;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) out[(16 * ti + 4 * lg + r) * 32 + 16 * tj + li] = acc0[r] + acc1[r];
+  for (int r = 0; r < 4; ++r)
+    out[(16 * ti + acc_row<double>(lg, r)) * 32 + 16 * tj + li] = acc0[r] + acc1[r];
 }
 
 __global__ void gram_reduce_kernel(const double* __restrict__ part, int S, int np, int lp,
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int
       ACC acc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = 16 * J + 4 * lg + r;
+        const int c = 16 * J + acc_row<T>(lg, r);
         T v = in ? Y[(int64_t)c * ldy + arow] : T(0);
         if (in && c < l && dep[c]) v = completion_value<T>(c, arow, len, seed);
         acc[r] = v;
@@ -318,16 +319,17 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int
       for (int I = 0; I < NT; ++I) {   // constant trip count so the loop unrolls; I < J live
         if (I < J) {
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) acc = mma_native(-rcol[16 * I + 4 * lg + s4][li], qt[I][s4], acc);
+          for (int s4 = 0; s4 < 4; ++s4)
+            acc = mma_native(-rcol[16 * I + acc_row<T>(lg, s4)][li], qt[I][s4], acc);
         }
       }
       ACC res = {0, 0, 0, 0};
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) res = mma_native(dcol[4 * lg + s4][li], acc[s4], res);
+      for (int s4 = 0; s4 < 4; ++s4) res = mma_native(dcol[acc_row<T>(lg, s4)][li], acc[s4], res);
       qt[J] = res;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = 16 * J + 4 * lg + r;
+        const int c = 16 * J + acc_row<T>(lg, r);
         if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = res[r];
         if (Qrm && in && c < l) Qrm[arow * ldqr + c] = res[r];
       }
@@ -380,7 +382,7 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In
   for (int I = 0; I < NT; ++I) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int c = 16 * I + 4 * lg + r;
+      const int c = 16 * I + acc_row<T>(lg, r);
       x[I][r] = (I < Tn && in) ? In[(int64_t)c * ldi + arow] : T(0);
     }
   }
@@ -393,14 +395,14 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In
         if (I < Tn) {
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4) {
-            const T a = Mt[(int64_t)(16 * J + li) * ldm + 16 * I + 4 * lg + s4];
+            const T a = Mt[(int64_t)(16 * J + li) * ldm + 16 * I + acc_row<T>(lg, s4)];
             acc = mma_native(a, x[I][s4], acc);
           }
         }
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int c = 16 * J + 4 * lg + r;
+        const int c = 16 * J + acc_row<T>(lg, r);
         if (Ocm && arow < ldo) Ocm[(int64_t)c * ldo + arow] = acc[r];
         if (Orm && in && c < l) Orm[arow * ldor + c] = acc[r];
       }

@@ -7,8 +7,10 @@ from the GPU's outputs):
   FP32 path: |dr| <= 1e-5, ||Q^T Q - I||, ||P^T P - I|| <= 1e-4;
   BF16 sketch/power with split-BF16 projection: |dr| <= 1e-4;
   all-BF16: |dr| <= 1e-2;  FP16 (low-rank-plus-noise): |dr| <= 1e-3.
-Leading-k subspaces (Q[:, :k], P[:, :k]) agree with the oracle's to 1e-3 in
-principal angle on every FP32-storage path.
+On the FP32 path the leading-k subspaces (Q[:, :k], P[:, :k]) agree with the
+oracle's to 1e-3 in principal angle; reduced-precision paths are held to a
+Weyl-type bound on diag(L) instead (their subspaces are only determined to
+eps / gap).
 """
 import math
 
@@ -77,14 +79,20 @@ def test_fp32_paths_against_oracle(c2_small, plan, tol):
     assert abs(r_gpu - r_ref) <= tol, (r_gpu, r_ref)
     assert np.abs(Q.T @ Q - np.eye(w.l)).max() <= 1e-4
     assert np.abs(P.T @ P - np.eye(w.l)).max() <= 1e-4
-    assert _sin_angle(ref.Q[:, :w.k], Q[:, :w.k]) <= 1e-3
-    assert _sin_angle(ref.P[:, :w.k], P[:, :w.k]) <= 1e-3
-    # R-value estimates track the oracle's
     d, dr = np.diag(L)[: w.k], np.diag(ref.L)[: w.k]
-    assert np.max(np.abs(d / dr - 1)) <= (1e-3 if plan != "bf16" else 5e-2)
     if plan == "native":
+        # FP32 rounding (~1e-7) over the gap sigma_k - sigma_k+1 = 2.7e-4 (Wedin)
+        assert _sin_angle(ref.Q[:, :w.k], Q[:, :w.k]) <= 1e-3
+        assert _sin_angle(ref.P[:, :w.k], P[:, :w.k]) <= 1e-3
+        assert np.max(np.abs(d / dr - 1)) <= 1e-4
         # a-posteriori residual of the record agrees with the explicit one
         assert abs(info.resid_rel_est - r_gpu) <= 1e-4
+    else:
+        # reduced-precision passes perturb A by ~eps ||A||; with sigma_i = 1/i the
+        # leading-k subspace is not determined to better than eps / gap, so only
+        # a Weyl-type absolute bound on the L-values is checked
+        eps = 1e-2 if plan == "bf16" else 1e-3
+        assert np.max(np.abs(d - dr)) <= eps * dr[0]
 
 
 def test_fp16_low_rank_plus_noise():
