@@ -159,6 +159,23 @@ pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpql
 pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, int64_t ldqt,
                               double* L, int64_t ldl, pbpqlp_info* d_info, void* stream);
 
+/* ---- instrumentation (benchmarking and profiling) ----
+ * With level >= 1, every later call records a pair of HIP events on its
+ * stream around each A-streaming product; with level >= 2 also around the
+ * Gram, Cholesky and apply kernels.  Records accumulate in a process-wide
+ * list until pbpqlp_trace_reset().  Reading a record's time is valid only
+ * once its stream has completed the call.  Level 0 (the default) records
+ * nothing; each record adds two event markers to the stream. */
+void pbpqlp_trace_enable(int level);
+void pbpqlp_trace_reset(void);
+int pbpqlp_trace_count(void);
+/* Record i: kernel class name (e.g. "k2_bf16", "gram", "chol"), its
+ * algorithmic bytes (the operands read once and the result written once) and
+ * flops, and the elapsed milliseconds between its two events.
+ * Errors: EINVAL for i out of range; EHIP if the events are not complete. */
+pbpqlp_status pbpqlp_trace_get(int i, char* name, int name_len, double* bytes, double* flops,
+                               float* ms);
+
 #ifdef __cplusplus
 }
 #endif

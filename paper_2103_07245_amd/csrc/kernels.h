@@ -68,12 +68,12 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, 
                              const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
                              hipStream_t s);
 hipError_t launch_cast_f64_to_f32(const double* in, int64_t n, float* out, hipStream_t s);
-// write L = U^T (lower) from upper U, zero elsewhere
+// write L = U^T (lower) from upper U, zero elsewhere; rowsq[i] = sum_j L[i][j]^2 (or null)
 hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, int64_t ldl,
-                                hipStream_t s);
+                                double* rowsq, hipStream_t s);
 hipError_t launch_info_init(void* info, int l, int q, hipStream_t s);
-hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts, const double* L,
-                                int64_t ldl, int l, hipStream_t s);
+hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts,
+                                const double* rowsq, int l, hipStream_t s);
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_copy_mat(const double* in, int64_t ldi, int rows, int cols, double* out,
                            int64_t ldo, int upper_only, hipStream_t s);

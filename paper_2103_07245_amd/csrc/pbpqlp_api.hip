@@ -8,6 +8,9 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "../../include/pbpqlp.h"
 #include "common.h"
@@ -83,6 +86,52 @@ Split plan_split(int64_t blocks, int64_t klen, int forced) {
   return {(int)S, chunk};
 }
 
+// ---------------------------------------------------------------------------
+// Optional event tracing of hot-path kernels (pbpqlp_trace_*).
+// ---------------------------------------------------------------------------
+struct TraceRec {
+  std::string name;
+  double bytes = 0, flops = 0;
+  hipEvent_t a = nullptr, b = nullptr;
+};
+std::mutex g_trace_mu;
+std::vector<TraceRec> g_trace;
+size_t g_trace_n = 0;
+int g_trace_level = 0;  // 0 off, 1 streaming products, 2 all hot-path kernels
+
+struct TraceScope {
+  TraceRec* rec = nullptr;
+  hipStream_t st;
+  TraceScope(const char* name, double bytes, double flops, hipStream_t s, int level = 2) : st(s) {
+    if (g_trace_level < level) return;
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    if (g_trace_n == g_trace.size()) {
+      TraceRec r;
+      if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+      g_trace.push_back(r);
+    }
+    rec = &g_trace[g_trace_n++];
+    rec->name = name;
+    rec->bytes = bytes;
+    rec->flops = flops;
+    (void)hipEventRecord(rec->a, st);
+  }
+  ~TraceScope() {
+    if (rec) (void)hipEventRecord(rec->b, st);
+  }
+};
+
+const char* mode_name(int mode) {
+  switch (mode) {
+    case M_F64: return "f64";
+    case M_F32: return "f32";
+    case M_BF16: return "bf16";
+    case M_F16: return "fp16";
+    case M_BF16X3: return "bf16x3";
+  }
+  return "?";
+}
+
 // Everything one factorization needs, carved from one workspace block.
 struct Ctx {
   // problem
@@ -106,6 +155,7 @@ struct Ctx {
          *Rfin = nullptr, *M1 = nullptr, *Qt64 = nullptr, *U = nullptr;
   void *Ra = nullptr, *Dinv = nullptr, *Ra64 = nullptr, *Dinv64 = nullptr, *Qt32 = nullptr;
   int* dep = nullptr;
+  double* rowsq = nullptr;
   uint64_t ncall = 0;
 
   void carve(Bump& b, bool need16) {
@@ -143,6 +193,7 @@ struct Ctx {
     Ra64 = b.take((size_t)lp * lp * 8);
     Dinv64 = b.take((size_t)(lp / 16) * 256 * 8);
     dep = (int*)b.take((size_t)lp * sizeof(int));
+    rowsq = (double*)b.take((size_t)lp * sizeof(double));
   }
 };
 
@@ -224,7 +275,14 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
     a.ldo = ldo;
     a.split_stride = (int64_t)c.lp * ldo;
   }
-  PBQ_CHECK(launch_stream(trans, mode, a, st));
+  {
+    const double xb = (mode >= M_BF16) ? 2.0 : (double)c.el;
+    const double bytes = (double)c.m * c.n * c.el + (double)xlen * c.l * xb * (mode == M_BF16X3 ? 2 : 1) +
+                         (double)olen * c.l * c.el;
+    std::string nm = std::string(trans ? "k2_" : "k1_") + mode_name(mode);
+    TraceScope ts(nm.c_str(), bytes, 2.0 * c.m * c.n * c.l, st, 1);
+    PBQ_CHECK(launch_stream(trans, mode, a, st));
+  }
   if (sp.S > 1)
     PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, a.split_stride, sp.S, ldo, c.lp, olen, out, ldo, st));
   return PBPQLP_OK;
@@ -246,10 +304,20 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     void* dst = last ? out : tmp;
     double* Rt = ps == 0 ? c.R1 : c.R2;
     const uint64_t cseed = c.seed ^ (0x9E3779B97F4A7C15ull * (++c.ncall));
-    PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, st));
-    PBQ_CHECK(launch_chol(f64, c.G, c.lp, c.l, c.lp, eps, Rt, c.lp, Ra, Dv, c.dep, info, st));
-    PBQ_CHECK(launch_apply(f64, src, ld, len, c.lp, c.l, Ra, Dv, c.dep, cseed, dst, ld,
-                           last ? rm : nullptr, ldrm, st));
+    const double el = f64 ? 8.0 : (double)c.el;
+    {
+      TraceScope ts("gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
+      PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, st));
+    }
+    {
+      TraceScope ts("chol", (double)c.l * c.l * 8 * 2, (double)c.l * c.l * c.l / 3.0, st);
+      PBQ_CHECK(launch_chol(f64, c.G, c.lp, c.l, c.lp, eps, Rt, c.lp, Ra, Dv, c.dep, info, st));
+    }
+    {
+      TraceScope ts("apply", 2.0 * len * c.l * el, (double)len * c.l * c.l, st);
+      PBQ_CHECK(launch_apply(f64, src, ld, len, c.lp, c.l, Ra, Dv, c.dep, cseed, dst, ld,
+                             last ? rm : nullptr, ldrm, st));
+    }
     src = dst;
   }
   if (Rkeep) {
@@ -297,7 +365,7 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   // S6: R^T = Qt L^T
   s = small_qr(c, c.Rfin, c.ldS, info, st);
   if (s) return s;
-  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, c.l, L, ldl, st));
+  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, c.l, L, ldl, c.rowsq, st));
   // S7: Q Qt, written row-major to the caller
   const void* Mt = c.Qt64;
   if (!c.f64) {
@@ -306,7 +374,7 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   }
   PBQ_CHECK(launch_right_mul(c.f64, c.Qm, c.ldm, c.m, c.lp, c.l, Mt, c.ldS, nullptr, 0, Q, ldq, st));
   // S8: result record
-  PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1s.S, L, ldl, c.l, st));
+  PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1s.S, c.rowsq, c.l, st));
   return PBPQLP_OK;
 }
 
@@ -558,7 +626,36 @@ pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, i
   s = small_qr(c, c.Rfin, c.ldS, info, st);
   if (s) return s;
   PBQ_CHECK(launch_cm_to_rm(true, c.Qt64, c.ldS, l, l, Qt, ldqt, st));
-  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, l, L, ldl, st));
+  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, l, L, ldl, nullptr, st));
+  return PBPQLP_OK;
+}
+
+void pbpqlp_trace_enable(int level) { g_trace_level = level < 0 ? 0 : level; }
+
+void pbpqlp_trace_reset(void) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  g_trace_n = 0;
+}
+
+int pbpqlp_trace_count(void) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  return (int)g_trace_n;
+}
+
+pbpqlp_status pbpqlp_trace_get(int i, char* name, int name_len, double* bytes, double* flops,
+                               float* ms) {
+  std::lock_guard<std::mutex> lk(g_trace_mu);
+  if (i < 0 || (size_t)i >= g_trace_n) return PBPQLP_EINVAL;
+  const TraceRec& r = g_trace[i];
+  if (name && name_len > 0) {
+    std::strncpy(name, r.name.c_str(), (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (bytes) *bytes = r.bytes;
+  if (flops) *flops = r.flops;
+  if (ms) {
+    if (hipEventElapsedTime(ms, r.a, r.b) != hipSuccess) return PBPQLP_EHIP;
+  }
   return PBPQLP_OK;
 }
 

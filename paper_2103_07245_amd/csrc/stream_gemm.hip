@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k1_ax(
 
   if (kb < ke) load_stage(kb);
   for (int64_t k0 = kb; k0 < ke; k0 += KC) {
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int j = 0; j < XCH; ++j) {
       const int q = tid + 256 * j;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k1_ax(
         for (int x = 0; x < XN; ++x) st16(&xs[x][c * kPitch + part * 16], xnext[x][j]);
       }
     }
-    __syncthreads();
+    lds_barrier();
     u32x4 acur[RT][2][NLA];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k1_ax(
     __shared__ double red[4];
     nrm = wave_sum(nrm);
     if (lane == 0) red[wave] = nrm;
-    __syncthreads();
+    lds_barrier();
     if (tid == 0) normA[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
   }
 }
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k2_atx(
 
   if (ab < ae) load_stage(ab);
   for (int64_t a0 = ab; a0 < ae; a0 += KC) {
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int j = 0; j < XCH; ++j) {
       const int q = tid + 256 * j;
@@ -380,7 +380,7 @@ __global__ __launch_bounds__(256) void k2_atx(
       st16(&as[0][off], hi);
       if constexpr (XN == 2) st16(&as[1][off], lo);
     }
-    __syncthreads();
+    lds_barrier();
     if (a0 + KC < ae) load_stage(a0 + KC);
 
 #pragma unroll

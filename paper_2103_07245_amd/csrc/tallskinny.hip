@@ -170,7 +170,7 @@ __host__ __device__ inline int npairs_of(int nb) { return nb * (nb + 1) / 2; }
 int gram_splits(int64_t len, int lp) {
   const int nb = (lp + 31) / 32;
   const int np = npairs_of(nb);
-  int64_t S = (2048 + np - 1) / np;              // aim at ~2048 workgroups
+  int64_t S = (512 + np - 1) / np;               // aim at ~512 workgroups
   const int64_t maxS = (len + 255) / 256;        // at least 256 rows per split
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
@@ -241,9 +241,19 @@ __global__ void gram_reduce_kernel(const double* __restrict__ part, int S, int n
     t = ii; ii = jj; jj = t;
   }
   const int p = bj * (bj + 1) / 2 + bi;
-  double s = 0.0;
-  for (int sp = 0; sp < S; ++sp) s += part[((int64_t)sp * np + p) * 1024 + ii * 32 + jj];
-  G[(int64_t)i * ldg + j] = s;
+  const double* src = part + (int64_t)p * 1024 + ii * 32 + jj;
+  const int64_t stride = (int64_t)np * 1024;
+  // four independent partial sums keep several loads in flight; the order is fixed
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int sp = 0;
+  for (; sp + 4 <= S; sp += 4) {
+    s0 += src[(int64_t)(sp + 0) * stride];
+    s1 += src[(int64_t)(sp + 1) * stride];
+    s2 += src[(int64_t)(sp + 2) * stride];
+    s3 += src[(int64_t)(sp + 3) * stride];
+  }
+  for (; sp < S; ++sp) s0 += src[(int64_t)sp * stride];
+  G[(int64_t)i * ldg + j] = (s0 + s1) + (s2 + s3);
 }
 
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
@@ -300,13 +310,13 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int
 #pragma unroll
   for (int J = 0; J < NT; ++J) {
     if (J < Tn) {
-      __syncthreads();
+      lds_barrier();
       for (int e = tid; e < 16 * J * 16; e += 256) {
         const int r = e >> 4, c = e & 15;
         rcol[r][c] = Ra[(int64_t)r * lp + 16 * J + c];
       }
       dcol[tid >> 4][tid & 15] = Dinv[J * 256 + tid];
-      __syncthreads();
+      lds_barrier();
       ACC acc;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {

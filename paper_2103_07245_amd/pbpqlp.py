@@ -88,6 +88,12 @@ def _lib():
         lib.pbpqlp_orth.argtypes = [vp, i64, i32, i64, i32, i32, vp, i64, dp, i64, vp, vp]
         lib.pbpqlp_small_qr.restype = i32
         lib.pbpqlp_small_qr.argtypes = [dp, i32, i64, dp, i64, dp, i64, vp, vp]
+        lib.pbpqlp_trace_enable.argtypes = [i32]
+        lib.pbpqlp_trace_reset.argtypes = []
+        lib.pbpqlp_trace_count.restype = i32
+        lib.pbpqlp_trace_get.restype = i32
+        lib.pbpqlp_trace_get.argtypes = [i32, ctypes.c_char_p, i32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float)]
         _LIB = lib
     return _LIB
 
@@ -261,3 +267,27 @@ def small_qr(R: torch.Tensor):
                                   l, ctypes.c_void_p(info.data_ptr()), _stream(R.device)),
            "pbpqlp_small_qr")
     return Qt, L
+
+
+def trace_enable(level: int = 1) -> None:
+    """Record HIP events around the streaming products (level 1) or every
+    hot-path kernel (level 2) of later calls; 0 switches tracing off."""
+    _lib().pbpqlp_trace_enable(int(level))
+
+
+def trace_reset() -> None:
+    _lib().pbpqlp_trace_reset()
+
+
+def trace_records():
+    """[(name, algorithmic bytes, flops, ms), ...] for the recorded kernels.
+    Call after the stream has finished the traced work."""
+    lib = _lib()
+    out = []
+    buf = ctypes.create_string_buffer(64)
+    b, f, ms = ctypes.c_double(), ctypes.c_double(), ctypes.c_float()
+    for i in range(lib.pbpqlp_trace_count()):
+        _check(lib.pbpqlp_trace_get(i, buf, 64, ctypes.byref(b), ctypes.byref(f), ctypes.byref(ms)),
+               "pbpqlp_trace_get")
+        out.append((buf.value.decode(), b.value, f.value, float(ms.value)))
+    return out
