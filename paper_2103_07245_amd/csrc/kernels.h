@@ -14,7 +14,8 @@ struct StreamArgs {
   const void* X;        // compute-type operand, column-major lp32 x ldx
   const void* Xlo;      // low bfloat16 part (BF16X3 only)
   int64_t ldx;
-  int lp;               // l rounded up to 16
+  int lp;               // l rounded up to 16: output columns stored
+  int lp32;             // l rounded up to 32: X columns (zero padded) multiplied
   void* out;            // split partials, column-major lp x ldo each
   int64_t ldo;
   int64_t split_stride; // elements between consecutive split partials

@@ -72,10 +72,10 @@ struct Split {
   int64_t chunk;
 };
 
-// Contraction split of one streaming pass: aim at ~512 workgroups (two per
-// CU), keep at least 4 stages of 64 per split.
+// Contraction split of one streaming pass: aim at ~256 workgroups (one
+// eight-wave block per CU), keep at least 4 stages of 64 per split.
 Split plan_split(int64_t blocks, int64_t klen, int forced) {
-  int64_t S = forced > 0 ? forced : (512 + blocks - 1) / blocks;
+  int64_t S = forced > 0 ? forced : (256 + blocks - 1) / blocks;
   const int64_t maxS = klen / 256 > 0 ? klen / 256 : 1;
   if (S > maxS) S = maxS;
   if (S > 64) S = 64;
@@ -144,9 +144,9 @@ struct Ctx {
   float fp16_scale = 1.0f;
   int forced_split = 0;
   uint64_t seed = 0;
-  // splits
-  Split k1s{1, 0}, k2s{1, 0};
-  int k1_blocks = 0;
+  // splits: the sketch pass's grid sizes the ||A||_F^2 partials
+  int k1_blocks = 0, k1_splits = 1;
+  size_t part_bytes = 0;
   // buffers
   void *Om = nullptr, *Y = nullptr, *Qm = nullptr, *W1m = nullptr, *Zn = nullptr, *Pn = nullptr,
        *W1n = nullptr;
@@ -157,6 +157,30 @@ struct Ctx {
   int* dep = nullptr;
   double* rowsq = nullptr;
   uint64_t ncall = 0;
+
+  // Split plan of a pass in compute mode `mode` (grid blocks depend on it).
+  Split split_for(int mode, bool trans) const {
+    const int64_t rb = stream_rows_per_block(mode);
+    const int64_t len = trans ? n : m, klen = trans ? m : n;
+    return plan_split((len + rb - 1) / rb, klen, forced_split);
+  }
+  // Sizes of the split partials and the ||A||^2 partials for the passes this
+  // context will run (sketch: K1; power: K1 and K2; projection: K2).
+  void plan_buffers(bool k1_sketch, bool k1_power, bool k2_power, bool k2_proj) {
+    part_bytes = 0;
+    auto need = [&](int mode, bool trans) {
+      const Split sp = split_for(mode, trans);
+      const size_t b = sp.S > 1 ? (size_t)sp.S * lp * (trans ? ldn : ldm) * el : 0;
+      if (b > part_bytes) part_bytes = b;
+    };
+    if (k1_sketch) need(mode_sketch, false);
+    if (k1_power) need(mode_power, false);
+    if (k2_power) need(mode_power, true);
+    if (k2_proj) need(mode_proj, true);
+    const int64_t rb = stream_rows_per_block(mode_sketch);
+    k1_blocks = (int)((m + rb - 1) / rb);
+    k1_splits = split_for(mode_sketch, false).S;
+  }
 
   void carve(Bump& b, bool need16) {
     const int64_t ldmax = ldm > ldn ? ldm : ldn;
@@ -171,10 +195,8 @@ struct Ctx {
       Xhi = b.take((size_t)lp32 * ldmax * 2);
       Xlo = b.take((size_t)lp32 * ldmax * 2);
     }
-    const size_t p1 = (size_t)k1s.S * lp * ldm * el;
-    const size_t p2 = (size_t)k2s.S * lp * ldn * el;
-    part = b.take(p1 > p2 ? p1 : p2);
-    normA = (double*)b.take((size_t)k1_blocks * k1s.S * sizeof(double));
+    part = b.take(part_bytes);
+    normA = (double*)b.take((size_t)k1_blocks * k1_splits * sizeof(double));
     size_t gp = gram_partial_elems(m, lp);
     const size_t gpn = gram_partial_elems(n, lp), gps = gram_partial_elems(l, lp);
     if (gpn > gp) gp = gpn;
@@ -224,10 +246,7 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
   if (!ok1 || !ok2 || !ok3) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
   c.fp16_scale = (float)(o.fp16_scale_a > 0 ? o.fp16_scale_a : 1.0);
   c.forced_split = o.split_k;
-  const int rb = stream_rows_per_block(c.f64 ? M_F64 : M_F32);
-  c.k1_blocks = (int)((m + rb - 1) / rb);
-  c.k1s = plan_split(c.k1_blocks, n, c.forced_split);
-  c.k2s = plan_split((n + rb - 1) / rb, m, c.forced_split);
+  c.plan_buffers(true, q > 0, q > 0, true);
   return PBPQLP_OK;
 }
 
@@ -242,6 +261,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
   StreamArgs a;
   a.A = A; a.lda = c.lda; a.m = c.m; a.n = c.n;
   a.lp = c.lp;
+  a.lp32 = c.lp32;
   a.a_scale = 1.0f;
   a.out_scale = 1.0f;
   if (mode >= M_BF16) {
@@ -261,7 +281,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
   }
   a.ldx = ldx;
   a.vec_ok = (((uintptr_t)A & 15) == 0 && ((c.lda * (int64_t)c.el) & 15) == 0) ? 1 : 0;
-  const Split sp = trans ? c.k2s : c.k1s;
+  const Split sp = c.split_for(mode, trans);
   a.splits = sp.S;
   a.chunk = sp.chunk;
   a.normA = normA;
@@ -374,7 +394,7 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   }
   PBQ_CHECK(launch_right_mul(c.f64, c.Qm, c.ldm, c.m, c.lp, c.l, Mt, c.ldS, nullptr, 0, Q, ldq, st));
   // S8: result record
-  PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1s.S, c.rowsq, c.l, st));
+  PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1_splits, c.rowsq, c.l, st));
   return PBPQLP_OK;
 }
 
@@ -501,24 +521,20 @@ pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int6
   if (!ok) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
   c.mode_sketch = c.mode_power = c.mode_proj = mode;
   c.fp16_scale = (float)(fp16_scale_a > 0 ? fp16_scale_a : 1.0);
-  const int rb = stream_rows_per_block(c.f64 ? M_F64 : M_F32);
-  c.k1_blocks = (int)((m + rb - 1) / rb);
-  c.k1s = plan_split(c.k1_blocks, n, 0);
-  c.k2s = plan_split((n + rb - 1) / rb, m, 0);
+  c.plan_buffers(!trans, false, false, trans != 0);
   hipStream_t st = (hipStream_t)stream;
   const int64_t xlen = trans ? m : n, ylen = trans ? n : m;
   const int64_t ldxi = trans ? c.ldm : c.ldn, ldyo = trans ? c.ldn : c.ldm;
   // scratch: Xt, Yt, 16-bit copies, split partials (one carve sizes and hands out)
   const int64_t ldmax = c.ldm > c.ldn ? c.ldm : c.ldn;
-  const size_t p1 = (size_t)c.k1s.S * c.lp * c.ldm * c.el, p2 = (size_t)c.k2s.S * c.lp * c.ldn * c.el;
   void *Xt = nullptr, *Yt = nullptr;
   auto carve = [&](Bump& b) {
     Xt = b.take((size_t)c.lp32 * ldxi * c.el);
     Yt = b.take((size_t)c.lp32 * ldyo * c.el);
     c.Xhi = b.take((size_t)c.lp32 * ldmax * 2);
     c.Xlo = b.take((size_t)c.lp32 * ldmax * 2);
-    c.part = b.take(p1 > p2 ? p1 : p2);
-    c.normA = (double*)b.take((size_t)c.k1_blocks * c.k1s.S * 8);
+    c.part = b.take(c.part_bytes);
+    c.normA = (double*)b.take((size_t)c.k1_blocks * c.k1_splits * 8);
   };
   Bump sz;
   carve(sz);

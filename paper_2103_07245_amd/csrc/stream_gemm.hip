@@ -5,11 +5,25 @@
 // matrices; 2q+2 of them):
 //   K1  Y = A X      (eq. (c) for A^T, i.e. the sketch, and the A-side power step)
 //   K2  Z = A^T X    (the A^T-side power step and the projection, eq. (D))
-// A (m x n, row-major, FP32 or FP64) is read exactly once per pass; the
-// l-column operand X is staged through LDS in the compute type and is read
-// from L2.  Both kernels split the contraction over the grid's y dimension
-// ("split-K") so small matrices still fill 256 CUs; the partial results are
-// summed by splitk_reduce in a fixed order (deterministic).
+// A (m x n, row-major, FP32 or FP64) is read exactly once per pass and never
+// touches LDS; the l-column operand X (column-major, compute type) is staged
+// through a double-buffered LDS ring shared by the four waves and re-read from
+// L2 by every block.  Both kernels split the contraction over the grid's y
+// dimension ("split-K") so small matrices still fill 256 CUs; the partial
+// results are summed by splitk_reduce in a fixed order (deterministic).
+//
+// One kernel serves both directions.  A matrix-core step computes
+// D[p][q] += sum_k Aop[p][k] Bop[k][q]:
+//   K1: Aop = A (p = row of A, a 16-byte row-contiguous load per lane),
+//       Bop = X (q = column of X);  D = (A X)[rows, cols].
+//   K2: Aop = X^T (p = column of X), Bop = A (q = column of A): each lane
+//       loads RT consecutive columns of V rows of A, so the transpose happens
+//       in registers;  D = (A^T X)^T[cols of X, cols of A].
+// Lane group g of a step owns the V contraction indices g V .. g V + V - 1 of
+// that step in both operands, so each lane's X fragment is one 16-byte LDS
+// read.  Full stages run without bounds checks (rows or columns of A past the
+// edge are clamped onto valid memory and discarded at the store); only the
+// ragged last stage of a split takes masked loads.
 //
 // Modes: F64 (v_mfma_f64_16x16x4), F32 (v_mfma_f32_16x16x4), BF16 / FP16
 // (v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulate; A converted in
@@ -22,44 +36,36 @@ namespace pbq {
 template <int MODE> struct Tr;
 template <> struct Tr<M_F64> {
   typedef double TA; typedef double TC; typedef double TACC;
-  static constexpr int V = 2, NSUB = 2, RT = 1, XN = 1;
+  static constexpr int V = 2, RT = 1, XN = 1, NW = 8;
 };
 template <> struct Tr<M_F32> {
   typedef float TA; typedef float TC; typedef float TACC;
-  static constexpr int V = 4, NSUB = 4, RT = 2, XN = 1;
+  static constexpr int V = 4, RT = 2, XN = 1, NW = 8;
 };
 template <> struct Tr<M_BF16> {
   typedef float TA; typedef __bf16 TC; typedef float TACC;
-  static constexpr int V = 8, NSUB = 1, RT = 2, XN = 1;
+  static constexpr int V = 8, RT = 2, XN = 1, NW = 8;
 };
 template <> struct Tr<M_F16> {
   typedef float TA; typedef _Float16 TC; typedef float TACC;
-  static constexpr int V = 8, NSUB = 1, RT = 2, XN = 1;
+  static constexpr int V = 8, RT = 2, XN = 1, NW = 8;
 };
 template <> struct Tr<M_BF16X3> {
   typedef float TA; typedef __bf16 TC; typedef float TACC;
-  static constexpr int V = 8, NSUB = 1, RT = 2, XN = 2;
+  static constexpr int V = 8, RT = 2, XN = 2, NW = 4;
 };
 
-// Every mode moves 128 bytes of compute-type operand per row per stage:
-// KS = 4 V contraction indices per step, two steps per stage.
-constexpr int kPitch = 128 + 16;  // LDS row pitch (bytes), padded against bank conflicts
+// Every mode moves 16 bytes of compute-type operand per lane per step
+// (KS = 4 V contraction indices) and two steps per stage: 128 bytes per X
+// column per stage.
+constexpr int kPitch = 128 + 16;  // LDS bytes per X column, padded against bank conflicts
+constexpr int kGroup = 4;         // X column tiles per scheduling group
 
-// Load 16 bytes of A (row `row`, columns k..k+E-1) with bounds checks.
-template <typename TA>
-__device__ __forceinline__ u32x4 load_a16(const TA* __restrict__ A, int64_t lda, int64_t row,
-                                          int64_t k, int64_t rend, int64_t kend, bool vec) {
-  constexpr int E = 16 / sizeof(TA);
-  if (vec && row < rend && k + E <= kend) return ld16(A + row * lda + k);
-  union { u32x4 v; TA e[E]; } u;
-#pragma unroll
-  for (int i = 0; i < E; ++i) u.e[i] = (row < rend && k + i < kend) ? A[row * lda + k + i] : TA(0);
-  return u.v;
-}
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ float u2f(uint32_t x) { return __uint_as_float(x); }
 
-// Convert 8 FP32 values (two 16-byte loads) to the 16-bit compute type.
+// Convert 8 FP32 values (two 16-byte groups) to the 16-bit compute type.
 template <int MODE>
 __device__ __forceinline__ void to16(const u32x4& a, const u32x4& b, float s, u32x4& hi, u32x4& lo) {
   float f[8] = {u2f(a.x), u2f(a.y), u2f(a.z), u2f(a.w), u2f(b.x), u2f(b.y), u2f(b.z), u2f(b.w)};
@@ -93,7 +99,7 @@ __device__ __forceinline__ void mma16(const u32x4& a, const u32x4& b, f32x4& c) 
   }
 }
 
-// acc += A_frag * B_frag for one 16-byte operand slice pair (one "step").
+// acc += Aop * Bop for one 16-byte operand slice pair (one step).
 template <int MODE, typename ACC>
 __device__ __forceinline__ void step_mma(const u32x4& ahi, const u32x4& alo, const u32x4& bhi,
                                          const u32x4& blo, ACC& acc) {
@@ -120,11 +126,11 @@ template <typename T> struct AccOf;
 template <> struct AccOf<float> { typedef f32x4 type; };
 template <> struct AccOf<double> { typedef f64x4 type; };
 
-// Store one accumulator column slice: rows acc_row(g, r) of a 16-row tile
-// starting at `tile_row`, i.e. out[col * ld + tile_row + acc_row(g, r)].
+// K1 store: rows acc_row(g, r) of a 16-row tile starting at `tile_row`,
+// column `col`: out[col * ld + tile_row + acc_row(g, r)].
 template <typename T, typename ACC>
-__device__ __forceinline__ void store4(T* out, int64_t ld, int64_t col, int64_t tile_row, int g,
-                                       int64_t rend, const ACC& v, float scale) {
+__device__ __forceinline__ void store_rows(T* out, int64_t ld, int64_t col, int64_t tile_row, int g,
+                                           int64_t rend, const ACC& v, float scale) {
   T* p = out + col * ld + tile_row;
   if constexpr (sizeof(T) == 4) {
     const int64_t r0 = tile_row + 4 * g;
@@ -141,34 +147,71 @@ __device__ __forceinline__ void store4(T* out, int64_t ld, int64_t col, int64_t 
   }
 }
 
+// Kernel arguments (by value).
+struct StreamParams {
+  const void* A;
+  int64_t lda, m, n;
+  const void* X;
+  const void* Xlo;
+  int64_t ldx;
+  int lp;               // output columns stored (multiple of 16)
+  void* out;
+  int64_t ldo, split_stride, chunk;
+  double* normA;
+  float a_scale, out_scale;
+};
+
 // ---------------------------------------------------------------------------
-// K1: Ypart[s] (lp x m, column-major) = A[:, kslice(s)] * X[kslice(s), :]
-// grid (ceil(m / (64 RT)), S); 4 waves, wave w owns rows 16 RT w .. +16 RT.
+// grid (ceil(len / (16 RT NW)), S), 64 NW threads (NW waves: 8, or 4 for
+// BF16X3 whose extra operands need 512 registers per lane).  Wave w owns the
+// A-side tiles (rows for K1, columns for K2) 16 RT (NW blockIdx.x + w) .. + 16 RT.
+// Eight waves make two per SIMD (one block per CU) and share one X stage.
+// VEC: A rows are 16-byte aligned (K1) / lda and n are multiples of RT (K2),
+// so full stages use vector loads; otherwise every load is masked.
 // ---------------------------------------------------------------------------
-template <int MODE, int NT>
-__global__ __launch_bounds__(256) void k1_ax(
-    const typename Tr<MODE>::TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-    const typename Tr<MODE>::TC* __restrict__ Xc, const typename Tr<MODE>::TC* __restrict__ Xlo,
-    int64_t ldx, int lp, typename Tr<MODE>::TACC* __restrict__ Ypart, int64_t ldy,
-    int64_t split_stride, int64_t kchunk, double* __restrict__ normA, float a_scale,
-    float out_scale, int vec_ok) {
+template <int MODE, int NT, bool TRANS, bool VEC>
+__global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void stream_kernel(StreamParams p) {
   typedef Tr<MODE> TR;
   typedef typename TR::TA TA;
   typedef typename TR::TC TC;
   typedef typename TR::TACC TACC;
   typedef typename AccOf<TACC>::type ACC;
   constexpr int V = TR::V, KS = 4 * V, KC = 2 * KS, RT = TR::RT, XN = TR::XN;
-  constexpr int NLA = (V * (int)sizeof(TA)) / 16;  // 16-byte A loads per lane per step
-  constexpr int XCH = (NT * 16 * 8 + 255) / 256;   // 16-byte X chunks per thread per stage (max)
-  __shared__ __attribute__((aligned(16))) char xs[XN][NT * 16 * kPitch];
+  constexpr int NBUF = XN == 1 ? 2 : 1;             // X ring depth in LDS
+  constexpr int NW = TR::NW, NTH = 64 * NW;
+  constexpr int XCH = (NT * 128 + NTH - 1) / NTH;   // 16-byte X chunks per thread per stage
+  constexpr int EA = 16 / (int)sizeof(TA);          // A elements per 16-byte load (K1)
+  constexpr int NLA = (V * (int)sizeof(TA)) / 16;   // 16-byte A loads per lane per step (K1)
+  constexpr int NAR = TRANS ? 2 * V : 2 * RT * NLA; // A registers-loads per lane per stage
+  static_assert(NT % 2 == 0, "NT must be even");
+  // a chunk index q < NT * 128 is valid; only the last j can overflow
+  auto xch_ok = [&](int j, int q) { return j < XCH - 1 || (NT * 128) % NTH == 0 || q < NT * 128; };
+  static_assert(RT * sizeof(TA) == 8, "K2 loads 8 bytes of A per row per lane");
+  __shared__ __attribute__((aligned(16))) char xs[NBUF][XN][NT * 16 * kPitch];
 
+  const TA* __restrict__ A = (const TA*)p.A;
+  const TC* __restrict__ Xc = (const TC*)p.X;
+  const TC* __restrict__ Xl = (const TC*)p.Xlo;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int T = lp >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * (64 * RT) + wave * (16 * RT);
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
-  const int64_t ke = min(n, kb + kchunk);
-  const bool vec = vec_ok != 0;
-  const int nxch = lp * 8;  // 16-byte chunks of X per stage
+  // A-side position of this lane: K1 a row of A per (rt), K2 RT columns.
+  const int64_t a0 = ((int64_t)blockIdx.x * NW + wave) * (16 * RT);
+  const int64_t alen = TRANS ? p.n : p.m;           // extent of the A-side dimension
+  const int64_t kb = (int64_t)blockIdx.y * p.chunk;
+  const int64_t ke = min(TRANS ? p.m : p.n, kb + p.chunk);
+  const int nst = (int)((ke - kb + KC - 1) / KC);
+  const int nfull = (int)((ke - kb) / KC);
+
+  // Clamped A-side indices (always valid memory); validity kept for normA.
+  int64_t arow[RT];  // K1: row of sub-tile rt
+  bool rowok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t r = a0 + 16 * rt + li;
+    rowok[rt] = r < alen;
+    arow[rt] = rowok[rt] ? r : alen - 1;
+  }
+  int64_t acol = a0 + li * RT;  // K2: first of RT consecutive columns
+  if (TRANS && VEC && acol + RT > alen) acol = alen - RT;
 
   ACC acc[RT][NT];
 #pragma unroll
@@ -176,294 +219,279 @@ __global__ __launch_bounds__(256) void k1_ax(
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[r][c] = ACC{0, 0, 0, 0};
 
-  u32x4 anext[RT][2][NLA];
-  u32x4 xnext[XN][XCH];
+  u32x4 an[TRANS ? 1 : NAR];   // K1: 16-byte A loads
+  u32x2 at[TRANS ? NAR : 1];   // K2: 8-byte A loads (RT consecutive columns of one row)
+  u32x4 xn[XN][XCH];
   double nrm = 0.0;
 
-  auto load_stage = [&](int64_t k0) {
-#pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-      for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int h = 0; h < NLA; ++h) {
-          const int64_t kk = k0 + st * KS + lg * V + h * (16 / (int)sizeof(TA));
-          anext[rt][st][h] = load_a16<TA>(A, lda, row0 + 16 * rt + li, kk, m, ke, vec);
-        }
+  // ---- loads of one stage starting at contraction index k0
+  auto load_x = [&](int64_t k0, bool full) {
 #pragma unroll
     for (int j = 0; j < XCH; ++j) {
-      const int q = tid + 256 * j;
-      if (q < nxch) {
-        const int c = q >> 3, part = q & 7;
-        const int64_t off = (int64_t)c * ldx + k0 + part * (16 / (int)sizeof(TC));
-        xnext[0][j] = ld16(Xc + off);
-        if constexpr (XN == 2) xnext[1][j] = ld16(Xlo + off);
+      const int q = tid + NTH * j;
+      if (!xch_ok(j, q)) continue;
+      const int c = q >> 3, part = q & 7;
+      constexpr int EX = 16 / (int)sizeof(TC);
+      const int64_t k = k0 + part * EX;
+      const int64_t off = (int64_t)c * p.ldx + k;
+#pragma unroll
+      for (int x = 0; x < XN; ++x) {
+        const TC* src = x == 0 ? Xc : Xl;
+        if (full) {
+          xn[x][j] = ld16(src + off);
+        } else {
+          union { u32x4 v; TC e[EX]; } u;
+#pragma unroll
+          for (int e = 0; e < EX; ++e) u.e[e] = (k + e < ke) ? src[off + e] : TC(0);
+          xn[x][j] = u.v;
+        }
       }
     }
   };
-
-  if (kb < ke) load_stage(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += KC) {
-    lds_barrier();
+  auto load_a = [&](int64_t k0, bool full) {
+    if constexpr (!TRANS) {
 #pragma unroll
-    for (int j = 0; j < XCH; ++j) {
-      const int q = tid + 256 * j;
-      if (q < nxch) {
-        const int c = q >> 3, part = q & 7;
+      for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int x = 0; x < XN; ++x) st16(&xs[x][c * kPitch + part * 16], xnext[x][j]);
-      }
-    }
-    lds_barrier();
-    u32x4 acur[RT][2][NLA];
+        for (int st = 0; st < 2; ++st)
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt)
+          for (int h = 0; h < NLA; ++h) {
+            const int64_t k = k0 + st * KS + lg * V + h * EA;
+            const TA* src = A + arow[rt] * p.lda + k;
+            u32x4& d = an[(rt * 2 + st) * NLA + h];
+            if (VEC && full) {
+              d = ld16(src);
+            } else {
+              union { u32x4 v; TA e[EA]; } u;
+#pragma unroll
+              for (int e = 0; e < EA; ++e) u.e[e] = (k + e < ke) ? src[e] : TA(0);
+              d = u.v;
+            }
+          }
+    } else {
 #pragma unroll
       for (int st = 0; st < 2; ++st)
 #pragma unroll
-        for (int h = 0; h < NLA; ++h) acur[rt][st][h] = anext[rt][st][h];
-    if (k0 + KC < ke) load_stage(k0 + KC);
+        for (int e = 0; e < V; ++e) {
+          const int64_t i = k0 + st * KS + lg * V + e;
+          u32x2& d = at[st * V + e];
+          if (VEC && full) {
+            d = *(const u32x2*)(A + i * p.lda + acol);
+          } else {
+            union { u32x2 v; TA e2[RT]; } u;
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+              u.e2[t] = (i < ke && acol + t < alen) ? A[i * p.lda + acol + t] : TA(0);
+            d = u.v;
+          }
+        }
+    }
+  };
 
+  if (nst > 0) {
+    const bool full = nfull > 0;
+    load_x(kb, full);
+    load_a(kb, full);
+  }
+  int buf = 0;
+  for (int s = 0; s < nst; ++s) {
+    const int64_t k0 = kb + (int64_t)s * KC;
+    if (NBUF == 1 && s > 0) lds_barrier();  // every wave is done reading the single X buffer
+    // X(s) -> LDS
 #pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      u32x4 ahi[RT], alo[RT];
+    for (int j = 0; j < XCH; ++j) {
+      const int q = tid + NTH * j;
+      if (!xch_ok(j, q)) continue;
+      const int c = q >> 3, part = q & 7;
 #pragma unroll
-      for (int rt = 0; rt < RT; ++rt) {
-        if (normA) {
+      for (int x = 0; x < XN; ++x) st16(&xs[buf][x][c * kPitch + part * 16], xn[x][j]);
+    }
+    // A(s) -> compute-type fragments afr[rt][st] (hi and, for BF16X3, lo)
+    u32x4 ahi[RT][2], alo[RT][2];
 #pragma unroll
-          for (int h = 0; h < NLA; ++h) {
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        u32x4 g0, g1;  // the V A values of this lane for (rt, st), as raw TA bits
+        if constexpr (!TRANS) {
+          g0 = an[(rt * 2 + st) * NLA];
+          g1 = NLA > 1 ? an[(rt * 2 + st) * NLA + NLA - 1] : g0;
+          if (!TRANS && p.normA && rowok[rt]) {
             if constexpr (sizeof(TA) == 8) {
               union { u32x4 v; double d[2]; } u;
-              u.v = acur[rt][st][h];
+              u.v = g0;
               nrm += u.d[0] * u.d[0] + u.d[1] * u.d[1];
             } else {
-              const u32x4 v = acur[rt][st][h];
-              const double a0 = u2f(v.x), a1 = u2f(v.y), a2 = u2f(v.z), a3 = u2f(v.w);
-              nrm += a0 * a0 + a1 * a1 + a2 * a2 + a3 * a3;
+#pragma unroll
+              for (int h = 0; h < NLA; ++h) {
+                const u32x4 v = an[(rt * 2 + st) * NLA + h];
+                const double x0 = u2f(v.x), x1 = u2f(v.y), x2 = u2f(v.z), x3 = u2f(v.w);
+                nrm += x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
+              }
             }
+          }
+        } else {
+          // element e of the fragment is row (lg V + e), column acol + rt
+          if constexpr (sizeof(TA) == 8) {
+            g0 = u32x4{at[st * V + 0].x, at[st * V + 0].y, at[st * V + 1].x, at[st * V + 1].y};
+            g1 = g0;
+          } else {
+            uint32_t w[8];
+#pragma unroll
+            for (int e = 0; e < V; ++e) w[e] = rt == 0 ? at[st * V + e].x : at[st * V + e].y;
+            g0 = u32x4{w[0], w[1], w[2], w[3]};
+            g1 = V > 4 ? u32x4{w[4 % V], w[5 % V], w[6 % V], w[7 % V]} : g0;
           }
         }
         if constexpr (MODE == M_F64 || MODE == M_F32) {
-          ahi[rt] = acur[rt][st][0];
+          ahi[rt][st] = g0;
+          alo[rt][st] = g0;
         } else {
-          to16<MODE>(acur[rt][st][0], acur[rt][st][1], a_scale, ahi[rt], alo[rt]);
+          to16<MODE>(g0, g1, p.a_scale, ahi[rt][st], alo[rt][st]);
         }
       }
+    // prefetch stage s + 1 (its loads stay in flight across the barrier)
+    if (s + 1 < nst) {
+      const bool full = s + 1 < nfull;
+      load_x(k0 + KC, full);
+      load_a(k0 + KC, full);
+    }
+    lds_barrier();
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct) {
-        if (ct < T) {
-          const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
-          const u32x4 bhi = *(const u32x4*)&xs[0][boff];
-          u32x4 blo = bhi;
-          if constexpr (XN == 2) blo = *(const u32x4*)&xs[XN - 1][boff];
+        // keep at most kGroup X fragments in flight: the scheduler would
+        // otherwise hoist every LDS read of the step and spill accumulators
+        if (ct % kGroup == 0 && (ct > 0 || st > 0)) __builtin_amdgcn_sched_barrier(0);
+        const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
+        const u32x4 xhi = *(const u32x4*)&xs[buf][0][boff];
+        const u32x4 xlo = XN == 2 ? *(const u32x4*)&xs[buf][XN - 1][boff] : xhi;
 #pragma unroll
-          for (int rt = 0; rt < RT; ++rt) step_mma<MODE>(ahi[rt], alo[rt], bhi, blo, acc[rt][ct]);
+        for (int rt = 0; rt < RT; ++rt) {
+          if constexpr (!TRANS)
+            step_mma<MODE>(ahi[rt][st], alo[rt][st], xhi, xlo, acc[rt][ct]);
+          else
+            step_mma<MODE>(xhi, xlo, ahi[rt][st], alo[rt][st], acc[rt][ct]);
         }
       }
     }
+    if (NBUF == 2) buf ^= 1;
   }
 
-  TACC* out = Ypart + (int64_t)blockIdx.y * split_stride;
+  TACC* out = (TACC*)p.out + (int64_t)blockIdx.y * p.split_stride;
+  const int Tst = p.lp >> 4;
+  if constexpr (!TRANS) {
 #pragma unroll
-  for (int rt = 0; rt < RT; ++rt)
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct)
+        if (ct < Tst)
+          store_rows<TACC>(out, p.ldo, 16 * ct + li, a0 + 16 * rt, lg, p.m, acc[rt][ct], p.out_scale);
+  } else {
+    const int64_t j = a0 + li * RT;  // unclamped: lanes past the edge store nothing
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct)
-      if (ct < T) store4<TACC>(out, ldy, 16 * ct + li, row0 + 16 * rt, lg, m, acc[rt][ct], out_scale);
+      if (ct < Tst)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t c = 16 * ct + acc_row<TACC>(lg, r);
+          TACC* dst = out + c * p.ldo + j;
+          if constexpr (RT == 2) {
+            if (j + 1 < alen) {
+              typedef float f32x2 __attribute__((ext_vector_type(2)));
+              *(f32x2*)dst = f32x2{acc[0][ct][r] * p.out_scale, acc[1][ct][r] * p.out_scale};
+            } else if (j < alen) {
+              dst[0] = acc[0][ct][r] * p.out_scale;
+            }
+          } else {
+            if (j < alen) dst[0] = (TACC)(acc[0][ct][r] * p.out_scale);
+          }
+        }
+  }
 
-  if (normA) {
-    __shared__ double red[4];
+  if (!TRANS && p.normA) {
+    __shared__ double red[NW];
     nrm = wave_sum(nrm);
     if (lane == 0) red[wave] = nrm;
     lds_barrier();
-    if (tid == 0) normA[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
-  }
-}
-
-// ---------------------------------------------------------------------------
-// K2: Zpart[s] (lp x n, column-major) = A[rslice(s), :]^T * X[rslice(s), :]
-// grid (ceil(n / (64 RT)), S); wave w owns A-columns 16 RT w .. +16 RT.
-// A tiles are transposed into LDS in the compute type so both matrix-core
-// operands read their contraction index (the rows of A) contiguously.
-// ---------------------------------------------------------------------------
-template <int MODE, int NT>
-__global__ __launch_bounds__(256) void k2_atx(
-    const typename Tr<MODE>::TA* __restrict__ A, int64_t lda, int64_t m, int64_t n,
-    const typename Tr<MODE>::TC* __restrict__ Xc, const typename Tr<MODE>::TC* __restrict__ Xlo,
-    int64_t ldx, int lp, typename Tr<MODE>::TACC* __restrict__ Zpart, int64_t ldz,
-    int64_t split_stride, int64_t rchunk, float a_scale, float out_scale, int vec_ok) {
-  typedef Tr<MODE> TR;
-  typedef typename TR::TA TA;
-  typedef typename TR::TC TC;
-  typedef typename TR::TACC TACC;
-  typedef typename AccOf<TACC>::type ACC;
-  constexpr int V = TR::V, KS = 4 * V, KC = 2 * KS, JT = TR::RT, XN = TR::XN;
-  constexpr int RB = 16 / sizeof(TC);   // A rows per thread (one 16-byte LDS chunk)
-  constexpr int VA = 16 / sizeof(TA);   // A columns per 16-byte global load
-  constexpr int XCH = (NT * 16 * 8 + 255) / 256;
-  static_assert((KC / RB) * (64 * JT / VA) == 256, "A tile map must use all 256 threads");
-  __shared__ __attribute__((aligned(16))) char xs[XN][NT * 16 * kPitch];
-  __shared__ __attribute__((aligned(16))) char as[XN][64 * JT * kPitch];
-
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int T = lp >> 4;
-  const int64_t j0 = (int64_t)blockIdx.x * (64 * JT);
-  const int64_t ab = (int64_t)blockIdx.y * rchunk;
-  const int64_t ae = min(m, ab + rchunk);
-  const bool vec = vec_ok != 0;
-  const int nxch = lp * 8;
-  const int tu = tid >> 5, tv = tid & 31;  // A-tile loader: rows tu*RB.., columns tv*VA..
-
-  ACC acc[JT][NT];
+    if (tid == 0) {
+      double t = 0.0;
 #pragma unroll
-  for (int r = 0; r < JT; ++r)
-#pragma unroll
-    for (int c = 0; c < NT; ++c) acc[r][c] = ACC{0, 0, 0, 0};
-
-  u32x4 anext[RB];
-  u32x4 xnext[XN][XCH];
-
-  auto load_stage = [&](int64_t a0) {
-#pragma unroll
-    for (int r = 0; r < RB; ++r)
-      anext[r] = load_a16<TA>(A, lda, a0 + tu * RB + r, j0 + tv * VA, ae, n, vec);
-#pragma unroll
-    for (int j = 0; j < XCH; ++j) {
-      const int q = tid + 256 * j;
-      if (q < nxch) {
-        const int c = q >> 3, part = q & 7;
-        const int64_t off = (int64_t)c * ldx + a0 + part * (16 / (int)sizeof(TC));
-        xnext[0][j] = ld16(Xc + off);
-        if constexpr (XN == 2) xnext[1][j] = ld16(Xlo + off);
-      }
-    }
-  };
-
-  if (ab < ae) load_stage(ab);
-  for (int64_t a0 = ab; a0 < ae; a0 += KC) {
-    lds_barrier();
-#pragma unroll
-    for (int j = 0; j < XCH; ++j) {
-      const int q = tid + 256 * j;
-      if (q < nxch) {
-        const int c = q >> 3, part = q & 7;
-#pragma unroll
-        for (int x = 0; x < XN; ++x) st16(&xs[x][c * kPitch + part * 16], xnext[x][j]);
-      }
-    }
-    // transpose the A tile: column (tv*VA + e) gets rows tu*RB .. +RB
-#pragma unroll
-    for (int e = 0; e < VA; ++e) {
-      u32x4 hi, lo;
-      if constexpr (MODE == M_F64) {
-        union { u32x4 v; double d[2]; } s0, s1, o;
-        s0.v = anext[0]; s1.v = anext[1];
-        o.d[0] = s0.d[e]; o.d[1] = s1.d[e];
-        hi = o.v;
-      } else if constexpr (MODE == M_F32) {
-        union { u32x4 v; float f[4]; } s[4], o;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) s[r].v = anext[r];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) o.f[r] = s[r].f[e];
-        hi = o.v;
-      } else {
-        union { u32x4 v; float f[4]; } s[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) s[r].v = anext[r];
-        const u32x4 p0 = {__float_as_uint(s[0].f[e]), __float_as_uint(s[1].f[e]),
-                          __float_as_uint(s[2].f[e]), __float_as_uint(s[3].f[e])};
-        const u32x4 p1 = {__float_as_uint(s[4].f[e]), __float_as_uint(s[5].f[e]),
-                          __float_as_uint(s[6].f[e]), __float_as_uint(s[7].f[e])};
-        to16<MODE>(p0, p1, a_scale, hi, lo);
-      }
-      const int off = (tv * VA + e) * kPitch + tu * 16;
-      st16(&as[0][off], hi);
-      if constexpr (XN == 2) st16(&as[1][off], lo);
-    }
-    lds_barrier();
-    if (a0 + KC < ae) load_stage(a0 + KC);
-
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-      u32x4 ahi[JT], alo[JT];
-#pragma unroll
-      for (int jt = 0; jt < JT; ++jt) {
-        const int aoff = (16 * JT * wave + 16 * jt + li) * kPitch + st * 64 + lg * 16;
-        ahi[jt] = *(const u32x4*)&as[0][aoff];
-        alo[jt] = ahi[jt];
-        if constexpr (XN == 2) alo[jt] = *(const u32x4*)&as[XN - 1][aoff];
-      }
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        if (ct < T) {
-          const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
-          const u32x4 bhi = *(const u32x4*)&xs[0][boff];
-          u32x4 blo = bhi;
-          if constexpr (XN == 2) blo = *(const u32x4*)&xs[XN - 1][boff];
-#pragma unroll
-          for (int jt = 0; jt < JT; ++jt) step_mma<MODE>(ahi[jt], alo[jt], bhi, blo, acc[jt][ct]);
-        }
-      }
+      for (int w = 0; w < NW; ++w) t += red[w];
+      p.normA[blockIdx.y * gridDim.x + blockIdx.x] = t;
     }
   }
-
-  TACC* out = Zpart + (int64_t)blockIdx.y * split_stride;
-#pragma unroll
-  for (int jt = 0; jt < JT; ++jt)
-#pragma unroll
-    for (int ct = 0; ct < NT; ++ct)
-      if (ct < T)
-        store4<TACC>(out, ldz, 16 * ct + li, j0 + 16 * JT * wave + 16 * jt, lg, n, acc[jt][ct],
-                     out_scale);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int MODE, int NT>
-static hipError_t launch_k1_t(const StreamArgs& a, hipStream_t s) {
+template <int MODE, int NT, bool TRANS>
+static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   typedef Tr<MODE> TR;
-  const int rows = 64 * TR::RT;
-  dim3 grid((unsigned)((a.m + rows - 1) / rows), (unsigned)a.splits);
-  hipLaunchKernelGGL((k1_ax<MODE, NT>), grid, dim3(256), 0, s, (const typename TR::TA*)a.A, a.lda,
-                     a.m, a.n, (const typename TR::TC*)a.X, (const typename TR::TC*)a.Xlo, a.ldx,
-                     a.lp, (typename TR::TACC*)a.out, a.ldo, a.split_stride, a.chunk, a.normA,
-                     a.a_scale, a.out_scale, a.vec_ok);
+  const int64_t len = TRANS ? a.n : a.m;
+  const int span = 16 * TR::RT * TR::NW;
+  dim3 grid((unsigned)((len + span - 1) / span), (unsigned)a.splits);
+  StreamParams p;
+  p.A = a.A; p.lda = a.lda; p.m = a.m; p.n = a.n;
+  p.X = a.X; p.Xlo = a.Xlo; p.ldx = a.ldx; p.lp = a.lp;
+  p.out = a.out; p.ldo = a.ldo; p.split_stride = a.split_stride; p.chunk = a.chunk;
+  p.normA = TRANS ? nullptr : a.normA;
+  p.a_scale = a.a_scale; p.out_scale = a.out_scale;
+  if (vec)
+    hipLaunchKernelGGL((stream_kernel<MODE, NT, TRANS, true>), grid, dim3(64 * TR::NW), 0, s, p);
+  else
+    hipLaunchKernelGGL((stream_kernel<MODE, NT, TRANS, false>), grid, dim3(64 * TR::NW), 0, s, p);
   return hipGetLastError();
 }
 
-template <int MODE, int NT>
-static hipError_t launch_k2_t(const StreamArgs& a, hipStream_t s) {
-  typedef Tr<MODE> TR;
-  const int cols = 64 * TR::RT;
-  dim3 grid((unsigned)((a.n + cols - 1) / cols), (unsigned)a.splits);
-  hipLaunchKernelGGL((k2_atx<MODE, NT>), grid, dim3(256), 0, s, (const typename TR::TA*)a.A, a.lda,
-                     a.m, a.n, (const typename TR::TC*)a.X, (const typename TR::TC*)a.Xlo, a.ldx,
-                     a.lp, (typename TR::TACC*)a.out, a.ldo, a.split_stride, a.chunk, a.a_scale,
-                     a.out_scale, a.vec_ok);
-  return hipGetLastError();
-}
-
-template <int MODE>
-static hipError_t dispatch_nt(bool trans, const StreamArgs& a, hipStream_t s) {
-  const int T = a.lp / 16;
-  if (T <= 2) return trans ? launch_k2_t<MODE, 2>(a, s) : launch_k1_t<MODE, 2>(a, s);
-  if (T <= 4) return trans ? launch_k2_t<MODE, 4>(a, s) : launch_k1_t<MODE, 4>(a, s);
-  if (T <= 8) return trans ? launch_k2_t<MODE, 8>(a, s) : launch_k1_t<MODE, 8>(a, s);
-  if (T <= 16) return trans ? launch_k2_t<MODE, 16>(a, s) : launch_k1_t<MODE, 16>(a, s);
+template <int MODE, bool TRANS>
+static hipError_t dispatch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
+  switch (a.lp32 / 16) {
+    case 2: return launch_nt<MODE, 2, TRANS>(a, vec, s);
+    case 4: return launch_nt<MODE, 4, TRANS>(a, vec, s);
+    case 6: return launch_nt<MODE, 6, TRANS>(a, vec, s);
+    case 8: return launch_nt<MODE, 8, TRANS>(a, vec, s);
+    case 10: return launch_nt<MODE, 10, TRANS>(a, vec, s);
+    case 12: return launch_nt<MODE, 12, TRANS>(a, vec, s);
+    case 14: return launch_nt<MODE, 14, TRANS>(a, vec, s);
+    case 16: return launch_nt<MODE, 16, TRANS>(a, vec, s);
+  }
   return hipErrorInvalidValue;
 }
 
-int stream_rows_per_block(int mode) { return (mode == M_F64) ? 64 : 128; }
+template <int MODE>
+static hipError_t dispatch_dir(bool trans, const StreamArgs& a, hipStream_t s) {
+  typedef Tr<MODE> TR;
+  const int el = (int)sizeof(typename TR::TA);
+  bool vec;
+  if (!trans)
+    vec = (((uintptr_t)a.A & 15) == 0) && ((a.lda * el) % 16 == 0);
+  else
+    vec = (((uintptr_t)a.A & 7) == 0) && (a.lda % TR::RT == 0) && (a.n % TR::RT == 0);
+  return trans ? dispatch_nt<MODE, true>(a, vec, s) : dispatch_nt<MODE, false>(a, vec, s);
+}
+
+int stream_rows_per_block(int mode) {
+  switch (mode) {
+    case M_F64: return 16 * Tr<M_F64>::RT * Tr<M_F64>::NW;
+    case M_F32: return 16 * Tr<M_F32>::RT * Tr<M_F32>::NW;
+    case M_BF16: return 16 * Tr<M_BF16>::RT * Tr<M_BF16>::NW;
+    case M_F16: return 16 * Tr<M_F16>::RT * Tr<M_F16>::NW;
+    default: return 16 * Tr<M_BF16X3>::RT * Tr<M_BF16X3>::NW;
+  }
+}
 int stream_kc(int mode) { return mode == M_F64 ? 16 : (mode == M_F32 ? 32 : 64); }
 
 hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s) {
+  if (a.lp32 < 32 || a.lp32 > 256 || a.lp32 % 32 != 0 || a.lp > a.lp32) return hipErrorInvalidValue;
   switch (mode) {
-    case M_F64: return dispatch_nt<M_F64>(trans, a, s);
-    case M_F32: return dispatch_nt<M_F32>(trans, a, s);
-    case M_BF16: return dispatch_nt<M_BF16>(trans, a, s);
-    case M_F16: return dispatch_nt<M_F16>(trans, a, s);
-    case M_BF16X3: return dispatch_nt<M_BF16X3>(trans, a, s);
+    case M_F64: return dispatch_dir<M_F64>(trans, a, s);
+    case M_F32: return dispatch_dir<M_F32>(trans, a, s);
+    case M_BF16: return dispatch_dir<M_BF16>(trans, a, s);
+    case M_F16: return dispatch_dir<M_F16>(trans, a, s);
+    case M_BF16X3: return dispatch_dir<M_BF16X3>(trans, a, s);
   }
   return hipErrorInvalidValue;
 }
