@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbpqlp.so")
 
-SOURCES = ["stream_gemm.hip", "tallskinny.hip", "small.hip", "pbpqlp_api.hip"]
+SOURCES = ["stream_gemm.hip", "tallskinny.hip", "small.hip", "apply.hip", "pbpqlp_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,0 +1,251 @@
+// Products of a tall column-major matrix with an l x l operand, the last two
+// steps of each orth()/qr() sweep and of the method:
+//   apply      Q = Y Ra^-1      (CholeskyQR: triangular solve with the factor)
+//   right_mul  Out = In M       (Q Qt of eq. (Ahat))
+// One wave owns 16 rows and keeps their lp columns in registers as 16 x 16
+// tiles in the matrix-core accumulator layout; the accumulator layout of a
+// finished tile is also the B-operand layout of the next product, so tiles
+// flow between products without leaving registers.  The l x l operand is
+// staged in LDS by the block's four waves (one block per CU), in as few
+// phases as its size allows; the tile count is a template parameter, so
+// every loop bound and phase boundary is a compile-time constant and the
+// scheduler sees one basic block per phase.
+#include "common.h"
+#include "kernels.h"
+
+namespace pbq {
+
+constexpr int kOpLdsBytes = 144 * 1024;  // LDS for the staged operand
+constexpr int kTile = 16 * 17;           // padded 16 x 16 tile in LDS
+
+// ---------------------------------------------------------------------------
+// Dependent columns (flagged by the Cholesky, count in dep[lp]) are replaced
+// in place by the seeded unit-variance vector w_c / sqrt(len) before the
+// solve; Ra has an identity row and column there, so the solve passes them
+// through.  Blocks exit at once when no column is dependent.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void complete_kernel(T* __restrict__ Y, int64_t ldy, int64_t len,
+                                                       int l, int lp, const int* __restrict__ dep,
+                                                       uint64_t seed) {
+  if (dep[lp] == 0) return;
+  __shared__ int sd[kMaxL];
+  for (int c = threadIdx.x; c < lp; c += blockDim.x) sd[c] = dep[c];
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= len) return;
+  const double sc = 1.0 / sqrt((double)len);
+#pragma nounroll
+  for (int c = 0; c < l; ++c)
+    if (sd[c]) Y[(int64_t)c * ldy + row] = (T)(normal_at((uint64_t)row, 1u, (uint32_t)c, seed) * sc);
+}
+
+// Row blocks of Ra staged per phase: row block J needs NT - J tiles (W_J and
+// -Ra_JK for K > J); a phase holds consecutive row blocks up to MAXT tiles.
+template <int NT, int MAXT> struct ApplyPhases {
+  int n = 0;
+  int j0[NT + 1] = {}, j1[NT + 1] = {};
+  constexpr ApplyPhases() {
+    int J = 0;
+    while (J < NT) {
+      int J1 = J, nt = 0;
+      while (J1 < NT && nt + (NT - J1) <= MAXT) { nt += NT - J1; ++J1; }
+      j0[n] = J;
+      j1[n] = J1;
+      ++n;
+      J = J1;
+    }
+  }
+};
+
+template <int NT, int MAXT> inline constexpr ApplyPhases<NT, MAXT> kApplyPhases{};
+
+// One staging phase P of the substitution (row blocks J0 .. J1-1), then the next.
+template <typename T, int NT, int MAXT, int P>
+__device__ __forceinline__ void apply_phase(typename Vec4<T>::type (&y)[NT], T* ops,
+                                            const T* __restrict__ Ra, const T* __restrict__ Dinv,
+                                            int lp, int tid, int li, int lg) {
+  typedef typename Vec4<T>::type ACC;
+  constexpr auto& PH = kApplyPhases<NT, MAXT>;
+  if constexpr (P < PH.n) {
+    constexpr int J0 = PH.j0[P], J1 = PH.j1[P];
+    if constexpr (P > 0) lds_barrier();  // every wave is done with the previous phase
+    const int si = tid >> 4, sc = tid & 15;  // staging: one element of each tile per thread
+    {
+      int t = 0;
+#pragma unroll
+      for (int J = J0; J < J1; ++J)
+#pragma unroll
+        for (int K = J; K < NT; ++K, ++t)
+          ops[t * kTile + si * 17 + sc] =
+              (K == J) ? Dinv[J * 256 + si * 16 + sc] : -Ra[(int64_t)(16 * J + si) * lp + 16 * K + sc];
+    }
+    lds_barrier();
+    int t = 0;
+#pragma unroll
+    for (int J = J0; J < J1; ++J) {
+      ACC q = {0, 0, 0, 0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) q = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], y[J][s4], q);
+      y[J] = q;
+      ++t;
+#pragma unroll
+      for (int K = J + 1; K < NT; ++K, ++t)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) y[K] = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], q[s4], y[K]);
+    }
+    apply_phase<T, NT, MAXT, P + 1>(y, ops, Ra, Dinv, lp, tid, li, lg);
+  }
+}
+
+// Right-looking blocked substitution: for J = 0, 1, ... the wave forms
+// Q_J = Y_J W_J (W_J the inverse of the diagonal block) in place of Y_J and
+// removes Q_J Ra_JK from every later tile K (independent chains).
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int64_t ldy,
+                                                    int64_t len, int l, int lp,
+                                                    const T* __restrict__ Ra,
+                                                    const T* __restrict__ Dinv,
+                                                    T* __restrict__ Qcm, int64_t ldq,
+                                                    T* __restrict__ Qrm, int64_t ldqr) {
+  typedef typename Vec4<T>::type ACC;
+  constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
+  static_assert(MAXT >= NT, "a phase must hold one full row block");
+  __shared__ T ops[MAXT * kTile];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int64_t arow = ((int64_t)blockIdx.x * 4 + wave) * 16 + li;
+  const bool in = arow < len;
+  ACC y[NT];
+#pragma unroll
+  for (int K = 0; K < NT; ++K)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      y[K][r] = in ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
+  apply_phase<T, NT, MAXT, 0>(y, ops, Ra, Dinv, lp, tid, li, lg);
+#pragma unroll
+  for (int J = 0; J < NT; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 16 * J + acc_row<T>(lg, r);
+      if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = y[J][r];
+      if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[J][r];
+    }
+}
+
+// Out = In M for a dense lp x lp M given row-major (Mr[k*ldm + j] = M[k][j]):
+// all output tiles accumulate at once while row blocks I of M stream
+// through LDS, MAXT / NT of them per phase.
+template <typename T, int NT>
+__global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In, int64_t ldi,
+                                                        int64_t len, int l,
+                                                        const T* __restrict__ Mr, int64_t ldm,
+                                                        T* __restrict__ Ocm, int64_t ldo,
+                                                        T* __restrict__ Orm, int64_t ldor) {
+  typedef typename Vec4<T>::type ACC;
+  constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
+  constexpr int RPP = MAXT / NT;  // row blocks of M per phase
+  static_assert(RPP >= 1, "a phase must hold one row block");
+  __shared__ T ops[RPP * NT * kTile];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int64_t arow = ((int64_t)blockIdx.x * 4 + wave) * 16 + li;
+  const bool in = arow < len;
+  ACC x[NT], acc[NT];
+#pragma unroll
+  for (int I = 0; I < NT; ++I) {
+    acc[I] = ACC{0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      x[I][r] = in ? In[(int64_t)(16 * I + acc_row<T>(lg, r)) * ldi + arow] : T(0);
+  }
+  const int si = tid >> 4, sc = tid & 15;
+#pragma unroll
+  for (int I0 = 0; I0 < NT; I0 += RPP) {
+    if (I0 > 0) lds_barrier();
+#pragma unroll
+    for (int I = I0; I < I0 + RPP && I < NT; ++I) {
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+        ops[((I - I0) * NT + J) * kTile + si * 17 + sc] = Mr[(int64_t)(16 * I + si) * ldm + 16 * J + sc];
+      __builtin_amdgcn_sched_barrier(0);  // at most one row block of loads in flight
+    }
+    lds_barrier();
+#pragma unroll
+    for (int I = I0; I < I0 + RPP && I < NT; ++I) {
+#pragma unroll
+      for (int J = 0; J < NT; ++J)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+          acc[J] = mma_native(ops[((I - I0) * NT + J) * kTile + acc_row<T>(lg, s4) * 17 + li], x[I][s4], acc[J]);
+      // bound the LDS operands in flight to one row block
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int J = 0; J < NT; ++J)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int c = 16 * J + acc_row<T>(lg, r);
+      if (Ocm && arow < ldo) Ocm[(int64_t)c * ldo + arow] = acc[J][r];
+      if (Orm && in && c < l) Orm[arow * ldor + c] = acc[J][r];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (tile count dispatched to the exact template)
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+static void apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
+                         const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
+                         void* Qrm, int64_t ldqr, hipStream_t s) {
+  hipLaunchKernelGGL(complete_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
+                     (T*)Y, ldy, len, l, lp, dep, seed);
+  const int64_t rows = Qcm ? (ldq > len ? ldq : len) : len;
+  hipLaunchKernelGGL((apply_kernel<T, NT>), dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
+                     (const T*)Y, ldy, len, l, lp, (const T*)Ra, (const T*)Dinv, (T*)Qcm, ldq,
+                     (T*)Qrm, ldqr);
+}
+
+template <typename T, int NT>
+static void right_mul_launch(const void* In, int64_t ldi, int64_t len, int l, const void* Mr,
+                             int64_t ldm, void* Ocm, int64_t ldo, void* Orm, int64_t ldor,
+                             hipStream_t s) {
+  const int64_t rows = Ocm ? (ldo > len ? ldo : len) : len;
+  hipLaunchKernelGGL((right_mul_kernel<T, NT>), dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
+                     (const T*)In, ldi, len, l, (const T*)Mr, ldm, (T*)Ocm, ldo, (T*)Orm, ldor);
+}
+
+#define PBQ_TILES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
+                        const void* Ra, const void* Dinv, const int* dep, uint64_t seed, void* Qcm,
+                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s) {
+  if (lp % 16 || lp < 16 || lp > kMaxL) return hipErrorInvalidValue;
+  switch (lp / 16) {
+#define PBQ_CASE(N)                                                                                  \
+  case N:                                                                                            \
+    if (f64) apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s); \
+    else apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s);      \
+    break;
+    PBQ_TILES(PBQ_CASE)
+#undef PBQ_CASE
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
+                            const void* Mr, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
+                            int64_t ldor, hipStream_t s) {
+  if (lp % 16 || lp < 16 || lp > kMaxL) return hipErrorInvalidValue;
+  switch (lp / 16) {
+#define PBQ_CASE(N)                                                                        \
+  case N:                                                                                  \
+    if (f64) right_mul_launch<double, N>(In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor, s); \
+    else right_mul_launch<float, N>(In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor, s);      \
+    break;
+    PBQ_TILES(PBQ_CASE)
+#undef PBQ_CASE
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pbq

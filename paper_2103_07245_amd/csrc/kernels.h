@@ -55,10 +55,13 @@ hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, do
 hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
                         const void* Ra, const void* Dinv, const int* dep, uint64_t seed,
                         void* Qcm, int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s);
-// Out = In M with M dense l x l given column-major (Mt[j*ldm + k] = M[k][j])
+// Out = In M with M dense l x l given row-major (Mr[k*ldm + j] = M[k][j])
 hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
-                            const void* Mt, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
+                            const void* Mr, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
                             int64_t ldor, hipStream_t s);
+// out[k * ldo + j] = in[j * ldi + k] for k < rows, j < cols (FP64 in; FP64 or FP32 out)
+hipError_t launch_transpose_cast(bool f64_out, const double* in, int64_t ldi, int rows, int cols,
+                                 void* out, int64_t ldo, hipStream_t s);
 // layout conversions
 hipError_t launch_rm_to_cm(bool f64, const void* X, int64_t ldx, int64_t len, int l, int lp32,
                            void* Xt, int64_t ldt, hipStream_t s);

@@ -214,7 +214,7 @@ struct Ctx {
     Dinv = b.take((size_t)(lp / 16) * 256 * el);
     Ra64 = b.take((size_t)lp * lp * 8);
     Dinv64 = b.take((size_t)(lp / 16) * 256 * 8);
-    dep = (int*)b.take((size_t)lp * sizeof(int));
+    dep = (int*)b.take((size_t)(lp + 1) * sizeof(int));
     rowsq = (double*)b.take((size_t)lp * sizeof(double));
   }
 };
@@ -386,13 +386,11 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   s = small_qr(c, c.Rfin, c.ldS, info, st);
   if (s) return s;
   PBQ_CHECK(launch_write_lower_t(c.U, c.lp, c.l, L, ldl, c.rowsq, st));
-  // S7: Q Qt, written row-major to the caller
-  const void* Mt = c.Qt64;
-  if (!c.f64) {
-    PBQ_CHECK(launch_cast_f64_to_f32(c.Qt64, (int64_t)c.lp32 * c.ldS, (float*)c.Qt32, st));
-    Mt = c.Qt32;
-  }
-  PBQ_CHECK(launch_right_mul(c.f64, c.Qm, c.ldm, c.m, c.lp, c.l, Mt, c.ldS, nullptr, 0, Q, ldq, st));
+  // S7: Q Qt, written row-major to the caller; Qt (column-major FP64) is first
+  // transposed to row-major in the data type (M1 is free once small_qr is done)
+  void* Mr = c.f64 ? (void*)c.M1 : c.Qt32;
+  PBQ_CHECK(launch_transpose_cast(c.f64, c.Qt64, c.ldS, c.lp, c.lp, Mr, c.ldS, st));
+  PBQ_CHECK(launch_right_mul(c.f64, c.Qm, c.ldm, c.m, c.lp, c.l, Mr, c.ldS, nullptr, 0, Q, ldq, st));
   // S8: result record
   PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1_splits, c.rowsq, c.l, st));
   return PBPQLP_OK;
@@ -582,7 +580,7 @@ pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpql
     c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
     c.Ra64 = b.take((size_t)c.lp * c.lp * 8);
     c.Dinv64 = b.take((size_t)(c.lp / 16) * 256 * 8);
-    c.dep = (int*)b.take((size_t)c.lp * 4);
+    c.dep = (int*)b.take((size_t)(c.lp + 1) * 4);
     void* own = b.take(sizeof(pbpqlp_info));
     if (!d_info) info = (pbpqlp_info*)own;
   };
@@ -624,7 +622,7 @@ pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, i
     c.U = (double*)b.take((size_t)c.lp * c.lp * 8);
     c.Ra64 = c.Ra = b.take((size_t)c.lp * c.lp * 8);
     c.Dinv64 = c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
-    c.dep = (int*)b.take((size_t)c.lp * 4);
+    c.dep = (int*)b.take((size_t)(c.lp + 1) * 4);
     void* own = b.take(sizeof(pbpqlp_info));
     if (!d_info) info = (pbpqlp_info*)own;
   };

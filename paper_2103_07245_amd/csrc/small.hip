@@ -13,12 +13,18 @@ namespace pbq {
 // The upper triangle lives in registers as 16x16 tiles in the FP64
 // matrix-core accumulator layout: wave w owns tile rows w and 15 - w
 // (17 tiles for every wave), so every register index is a compile-time
-// constant.  For each 16-column panel J:
-//   A. the owner of tile (J,J) factors it in one wave (diag_factor), forms
-//      the "apply" form of R_JJ and its inverse W_J;
-//   B. the owner of row J solves R_JK = W_J^T G_JK on the FP64 matrix core;
-//   C. every owner applies the rank-16 update G_IK -= R_JI^T R_JK (I,K > J).
-// Two barriers per panel; no global memory inside the panel loop.
+// constant.  Panel J (16 columns) goes through
+//   A. the owner of row J factors the (updated) diagonal tile in one wave
+//      (diag_factor) and stages the rest of row J, as updated through panel
+//      J - 2, in LDS;
+//   B. all waves share the tiles K > J of row J: apply panel J - 1's update
+//      G_JK -= R_{J-1,J}^T R_{J-1,K}, then R_JK = W_J^T G_JK on the FP64
+//      matrix core (W_J = inverse of the apply form of R_JJ);
+//   C. the owners of rows I > J + 1 apply the rank-16 update
+//      G_IK -= R_JI^T R_JK.
+// Step A of panel J+1 runs inside step C of panel J (lookahead): its owner
+// only updates the diagonal tile with panel J before factoring it.  Two
+// barriers per panel; no global memory inside the panel loop except W_J.
 //
 // Dependent columns: if the pivot satisfies !(d_k > eps * G_kk) (this also
 // catches d_k <= 0, G_kk = 0 and NaN), column k carries no new direction.
@@ -28,17 +34,16 @@ namespace pbq {
 // orthonormal direction after the next sweep) while Y = Q Rt still holds.
 // Padding columns (>= l) get 0 in Rt and identity in Ra and are not flagged.
 // Outputs: Rt (FP64, ldr), Ra (T, ld lp), Dinv (T, W_J for every panel),
-// dep[c] in {0,1}, status bits in info.
+// dep[c] in {0,1} for c < lp and their count dep[lp], status bits in info.
 // ---------------------------------------------------------------------------
 constexpr int kCholThreads = 512;
 
 struct CholShared {
   double gd[kMaxL];
   int sdep[kMaxL];
-  double dgt[16][17];         // diagonal tile: residual in, true R_JJ out
-  double raj[16][17];         // apply form of R_JJ
-  double winv[16][17];        // W_J = inverse of the apply form
-  double pnl[16][kMaxL + 1];  // panel row R_J,:
+  double dgt[16][17];            // diagonal tile: residual in, true R_JJ out
+  double winv[16][17];           // W_J = inverse of the apply form of R_JJ
+  double pnl[2][16][kMaxL + 1];  // panel rows, double buffered: raw G_J,: in, R_J,: out
   int sflag;
 };
 
@@ -53,62 +58,135 @@ __device__ __forceinline__ double bcast_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Factor the 16x16 residual diagonal tile held in sh.dgt (executed by the
-// tile's owner wave; lane c < 16 owns column c and pivots / row entries are
-// broadcast with readlane), writing the true factor back to sh.dgt, the
-// apply form to sh.raj, its inverse to sh.winv and the flags to sh.sdep.
+// Lane I of each row of 16 lanes, broadcast to its row (DPP row_newbcast).
+template <int I> __device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + I, 0xF, 0xF, true);
+}
+
+// Lanes 16..31 (and 48..63) receive lanes 0..15 (32..47); the even rows keep
+// their values (v_permlane16_swap of a register with itself).
+__device__ __forceinline__ double dup_even_rows(double v) {
+  const unsigned long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+  const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __longlong_as_double(((unsigned long long)rh[0] << 32) | rl[0]);
+}
+
+// sqrt(x) and 1/sqrt(x) for x > 0 to about one rounding unit: hardware
+// reciprocal square root estimate, then two coupled Newton steps on
+// g ~ sqrt(x), h ~ 1/(2 sqrt(x)) (residual r = 1/2 - g h).
+__device__ __forceinline__ void sqrt_rsqrt(double x, double& g, double& y) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  g = x * y0;
+  double h = 0.5 * y0;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+  }
+  y = h + h;
+}
+
+// One wave factors the 16x16 residual diagonal tile.  Lane row 0 (lanes
+// 0..15) holds the tile's columns, lane row 1 (lanes 16..31) the columns of
+// an identity; the same row operations (scale row k by 1/r_kk, subtract
+// r_ki times row k from row i) run on both, so lane row 1 ends with
+// M = R^-T of the apply form and W_J = M^T.  After each pivot the scaled
+// row k of the tile is copied into lane row 1 (one permlane swap), so one
+// DPP broadcast per row update serves both halves.  A dependent or padding
+// pivot zeroes row k of the tile and resets row k of M to e_k (M is then the
+// inverse transpose of the apply form).  Entries below the diagonal of the
+// tile are updated too and never read.
+// Each step updates row k+1 first and starts the next pivot's square root
+// before the remaining row updates, which then overlap that latency chain.
+struct DiagState {
+  double x[16];
+  double eps, gdv;
+  int c, live;
+  bool tile_lane;
+  uint32_t depm;
+};
+
+// Rows I .. min(I + 3, 15) of step K: four broadcasts, then four FMAs, then
+// a pin.  Left to itself the compiler hoists all broadcasts of a step and
+// sinks their FMAs (30 extra VGPRs live next to the 136 of the register-
+// resident tiles); one pin per row would serialize every broadcast on one
+// temporary register.
+template <int K, int I>
+__device__ __forceinline__ void diag_rows(DiagState& d, double s, double v) {
+  if constexpr (I < 16) {
+    constexpr int N = (16 - I) < 4 ? (16 - I) : 4;
+    double b[4];
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      if (u == 0) b[u] = row_bcast<I>(s);
+      if (u == 1) b[u] = row_bcast<(I + 1) & 15>(s);
+      if (u == 2) b[u] = row_bcast<(I + 2) & 15>(s);
+      if (u == 3) b[u] = row_bcast<(I + 3) & 15>(s);
+    }
+#pragma unroll
+    for (int u = 0; u < N; ++u) d.x[I + u] = __builtin_fma(-b[u], v, d.x[I + u]);
+    if constexpr (N == 4) asm volatile("" : "+v"(d.x[I]), "+v"(d.x[I + 1]), "+v"(d.x[I + 2]), "+v"(d.x[I + 3]));
+    if constexpr (N == 3) asm volatile("" : "+v"(d.x[I]), "+v"(d.x[I + 1]), "+v"(d.x[I + 2]));
+    if constexpr (N == 2) asm volatile("" : "+v"(d.x[I]), "+v"(d.x[I + 1]));
+    if constexpr (N == 1) asm volatile("" : "+v"(d.x[I]));
+    diag_rows<K, I + N>(d, s, v);
+  }
+}
+
+// pivot K: its value piv (uniform), sqrt g and 1/sqrt y (valid when the
+// pivot is live and independent)
+template <int K>
+__device__ __forceinline__ void diag_steps(DiagState& d, double piv, double g, double y) {
+  if constexpr (K < 16) {
+    const double gkk = bcast_f64(d.gdv, K);
+    const bool isdep = K < d.live && !(piv > d.eps * gkk);
+    const bool zero = K >= d.live || isdep;
+    d.depm |= isdep ? (1u << K) : 0u;
+    const double ys = zero ? 0.0 : y;
+    const double rkk = zero ? 0.0 : g;
+    double v = d.x[K] * ys;
+    v = (d.tile_lane && d.c == K) ? rkk : v;
+    v = (zero && !d.tile_lane) ? ((d.c == K) ? 1.0 : 0.0) : v;
+    d.x[K] = v;
+    const double s = dup_even_rows(v);  // the scaled tile row K, in both lane rows
+    if constexpr (K + 1 < 16) {
+      d.x[K + 1] = __builtin_fma(-row_bcast<K + 1>(s), v, d.x[K + 1]);
+      asm volatile("" : "+v"(d.x[K + 1]));
+      const double pn = bcast_f64(d.x[K + 1], K + 1);
+      double gn, yn;
+      sqrt_rsqrt(pn > 0.0 ? pn : 1.0, gn, yn);
+      diag_rows<K, K + 2>(d, s, v);
+      diag_steps<K + 1>(d, pn, gn, yn);
+    }
+  }
+}
+
 __device__ __forceinline__ void diag_factor(CholShared& sh, int J, int l, double eps) {
-  const int lane = threadIdx.x & 63, c = lane & 15;
-  const bool act = lane < 16;
-  double cv[16];
+  const int lane = threadIdx.x & 63;
+  DiagState d;
+  d.c = lane & 15;
+  d.tile_lane = lane < 16;
+  const bool ml = lane >= 16 && lane < 32;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) cv[i] = sh.dgt[i][c];
-  bool zc = false;
-  double rdiag[16];   // reciprocal of the apply-form diagonal
+  for (int i = 0; i < 16; ++i) d.x[i] = d.tile_lane ? sh.dgt[i][d.c] : ((i == d.c) ? 1.0 : 0.0);
+  d.gdv = sh.gd[16 * J + d.c];
+  d.live = l - 16 * J;
+  d.eps = eps;
+  d.depm = 0;
+  const double p0 = bcast_f64(d.x[0], 0);
+  double g0, y0;
+  sqrt_rsqrt(p0 > 0.0 ? p0 : 1.0, g0, y0);
+  diag_steps<0>(d, p0, g0, y0);
+  if (d.tile_lane) {
 #pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int kg = 16 * J + k;
-    const double piv = bcast_f64(cv[k], k);
-    const bool pad = kg >= l;
-    const bool isdep = !pad && !(piv > eps * sh.gd[kg]);
-    const bool zero = pad || isdep;
-    const double rkk = zero ? 0.0 : sqrt(piv);
-    const double rsc = zero ? 0.0 : 1.0 / rkk;
-    rdiag[k] = zero ? 1.0 : rsc;
-    if (c == k) zc = zero;
-    if (lane == 0) sh.sdep[kg] = isdep ? 1 : 0;
-    // row k of R: r_kc = g_kc / r_kk (c > k), r_kk on the diagonal
-    cv[k] = (c == k) ? rkk : ((c > k) ? cv[k] * rsc : cv[k]);
+    for (int i = 0; i < 16; ++i) sh.dgt[i][d.c] = (i <= d.c) ? d.x[i] : 0.0;
+    sh.sdep[16 * J + d.c] = (d.depm >> d.c) & 1u;
+  } else if (ml) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (i > k) {
-        const double rki = bcast_f64(cv[k], i);
-        if (c >= i) cv[i] -= rki * cv[k];
-      }
-    }
-  }
-  if (act) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const double t = (i <= c) ? cv[i] : 0.0;
-      sh.dgt[i][c] = t;
-      sh.raj[i][c] = (i == c) ? (zc ? 1.0 : t) : ((i < c && !zc) ? t : 0.0);
-    }
-  }
-  wave_lds_fence();
-  // W = inverse of the apply form: column c by back substitution, no divisions
-  if (act) {
-    double x[16];
-#pragma unroll
-    for (int i = 15; i >= 0; --i) {
-      double sum = 0.0;
-#pragma unroll
-      for (int j = 0; j < 16; ++j)
-        if (j > i) sum += sh.raj[i][j] * x[j];
-      x[i] = (i > c) ? 0.0 : ((i == c) ? rdiag[i] : -sum * rdiag[i]);
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) sh.winv[i][c] = x[i];
+    for (int i = 0; i < 16; ++i) sh.winv[d.c][i] = d.x[i];
   }
 }
 
@@ -128,22 +206,68 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
   __syncthreads();
   if (tid < l && !isfinite(sh.gd[tid])) atomicOr(&sh.sflag, 1);
 
-  // wave w owns tile rows RA = w and RB = 15 - w: slots 0..15 hold (RA, RA..15)
-  // followed by (RB, RB+1..15); slot 16 holds the diagonal tile (RB, RB).
+  // wave w owns tile rows RA = w and RB = 15 - w: slots 0..NA-1 hold
+  // (RA, RA + j), slots NA..15 hold (RB, j) and slot 16 the diagonal (RB, RB).
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int RA = w, RB = 15 - w, NA = 16 - w;
   const int Tn = lp >> 4;
   constexpr int NS = 17;
   f64x4 t[NS];
-  auto tile_i = [&](int j) { return j == 16 ? RB : (j < NA ? RA : RB); };
-  auto tile_k = [&](int j) { return j == 16 ? RB : (j < NA ? RA + j : RB + 1 + (j - NA)); };
+  {
+    const int RA = w, RB = 15 - w, NA = 16 - w;
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    const int I = tile_i(j), K = tile_k(j);
+    for (int j = 0; j < NS; ++j) {
+      const int I = j == 16 ? RB : (j < NA ? RA : RB);
+      const int K = j == 16 ? RB : (j < NA ? RA + j : j);
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      t[j][r] = (K < Tn) ? G[(int64_t)(16 * I + acc_row<double>(lg, r)) * ldg + 16 * K + li] : 0.0;
+      for (int r = 0; r < 4; ++r)
+        t[j][r] = (K < Tn) ? G[(int64_t)(16 * I + acc_row<double>(lg, r)) * ldg + 16 * K + li] : 0.0;
+    }
   }
+
+  // Step A for panel J by its owner: factor the diagonal tile (slot 0 if
+  // J == RA, else slot 16), stage the rest of row J in pnl[J & 1], emit W_J.
+  auto step_a = [&](int J, int RA, int NA) {
+    const bool a = J == RA;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sh.dgt[acc_row<double>(lg, r)][li] = a ? t[0][r] : t[16][r];
+    wave_lds_fence();
+    diag_factor(sh, J, l, eps);
+    wave_lds_fence();
+    // value selects only: a store through a selected tile address would force
+    // the tile array into scratch memory
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double v = sh.dgt[acc_row<double>(lg, r)][li];
+      t[0][r] = a ? v : t[0][r];
+      t[16][r] = a ? t[16][r] : v;
+    }
+    double(*pn)[kMaxL + 1] = sh.pnl[J & 1];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int I = j < NA ? RA : 15 - RA;
+      const int K = j < NA ? RA + j : j;
+      if (I == J && K > J && K < Tn) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pn[acc_row<double>(lg, r)][16 * K + li] = t[j][r];
+      }
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Dinv[J * 256 + i * 16 + li] = (T)sh.winv[i][li];
+    }
+  };
+  // G_IK -= R_JI^T R_JK for slot j (panel J in pnl[J & 1])
+  auto update = [&](int j, int J, int I, int K) {
+    double(*pn)[kMaxL + 1] = sh.pnl[J & 1];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int kk = acc_row<double>(lg, s4);
+      t[j] = mma_f64(-pn[kk][16 * I + li], pn[kk][16 * K + li], t[j]);
+    }
+  };
+
+  if (w == 0) step_a(0, 0, 16);  // panel 0 belongs to wave 0 (RA = 0)
+  lds_barrier();
 
   for (int J = 0; J < Tn; ++J) {
     // Re-derive the wave's tile coordinates each step from an opaque scalar
@@ -153,91 +277,104 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __rest
     asm volatile("s_mov_b32 %0, %1" : "=s"(wl) : "s"(w));
     const int RA = wl, RB = 15 - wl, NA = 16 - wl;
     auto tile_i = [&](int j) { return j == 16 ? RB : (j < NA ? RA : RB); };
-    auto tile_k = [&](int j) { return j == 16 ? RB : (j < NA ? RA + j : RB + 1 + (j - NA)); };
-    // ---- A: the owner factors the diagonal tile (staged through LDS)
-    if (J == RA || J == RB) {
-      const bool a = J == RA;
+    auto tile_k = [&](int j) { return j == 16 ? RB : (j < NA ? RA + j : j); };
+    double(*pn)[kMaxL + 1] = sh.pnl[J & 1];
+    double(*pp)[kMaxL + 1] = sh.pnl[(J + 1) & 1];  // panel J - 1
+
+    // ---- B: K = J + 1 + wl, J + 9 + wl
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sh.dgt[acc_row<double>(lg, r)][li] = a ? t[0][r] : t[16][r];
-      wave_lds_fence();
-      diag_factor(sh, J, l, eps);
-      wave_lds_fence();
+    for (int h = 0; h < 2; ++h) {
+      const int K = J + 1 + wl + 8 * h;
+      if (K < Tn) {
+        f64x4 g;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const double v = sh.dgt[acc_row<double>(lg, r)][li];
-        if (a) t[0][r] = v; else t[16][r] = v;
-      }
-      if (lane < 16) {
+        for (int r = 0; r < 4; ++r) g[r] = pn[acc_row<double>(lg, r)][16 * K + li];
+        if (J > 0) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) Dinv[J * 256 + i * 16 + li] = (T)sh.winv[i][li];
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int kk = acc_row<double>(lg, s4);
+            g = mma_f64(-pp[kk][16 * J + li], pp[kk][16 * K + li], g);
+          }
+        }
+        // the updated tile is the B operand as it stands: accumulator
+        // register r of lane group g holds row g + 4 r, which is the
+        // contraction index that lane group takes in step r
+        f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc = mma_f64(sh.winv[acc_row<double>(lg, s4)][li], g[s4], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row<double>(lg, r);
+          pn[row][16 * K + li] = sh.sdep[16 * J + row] ? 0.0 : acc[r];
+        }
       }
     }
     lds_barrier();
-    // ---- B: panel row R_JK = W_J^T G_JK (dependent rows zero), K > J
+    // the owner of row J keeps R_J,: in its registers (the factor's output)
     if (J == RA || J == RB) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int I = tile_i(j), K = tile_k(j);
         if (I == J && K > J && K < Tn) {
-          f64x4 acc = {0, 0, 0, 0};
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4)
-            acc = mma_f64(sh.winv[acc_row<double>(lg, s4)][li], t[j][s4], acc);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = acc_row<double>(lg, r);
-            const double v = sh.sdep[16 * J + row] ? 0.0 : acc[r];
-            t[j][r] = v;
-            sh.pnl[row][16 * K + li] = v;
-          }
+          for (int r = 0; r < 4; ++r) t[j][r] = pn[acc_row<double>(lg, r)][16 * K + li];
         }
       }
     }
-    lds_barrier();
-    // ---- C: trailing update G_IK -= R_JI^T R_JK for J < I <= K
+    // ---- C with lookahead: the owner of row J + 1 updates its diagonal tile
+    // and factors it first (raised priority: it is the critical path)
+    const int J1 = J + 1;
+    if (J1 < Tn && (J1 == RA || J1 == RB)) {
+      __builtin_amdgcn_s_setprio(3);
+      if (J1 == RA) update(0, J, RA, RA); else update(16, J, RB, RB);
+      step_a(J1, RA, NA);
+      __builtin_amdgcn_s_setprio(0);
+    }
 #pragma unroll
     for (int j = 0; j < NS; ++j) {
       const int I = tile_i(j), K = tile_k(j);
-      if (I > J && K < Tn) {
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          const int kk = acc_row<double>(lg, s4);
-          t[j] = mma_f64(-sh.pnl[kk][16 * I + li], sh.pnl[kk][16 * K + li], t[j]);
-        }
-      }
+      if (I > J1 && K < Tn) update(j, J, I, K);
+      // bound the LDS operands in flight (the tiles already hold 136 VGPRs)
+      if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
     }
+    lds_barrier();
   }
   __syncthreads();
   // write Rt (true factor) and Ra (apply factor); mirror tiles below the diagonal are zero
+  {
+    const int RA = w, RB = 15 - w, NA = 16 - w;
 #pragma unroll
-  for (int j = 0; j < NS; ++j) {
-    const int I = tile_i(j), K = tile_k(j);
-    if (K < Tn) {
-      const int c = 16 * K + li;
-      const bool zc = c >= l || sh.sdep[c];
+    for (int j = 0; j < NS; ++j) {
+      const int I = j == 16 ? RB : (j < NA ? RA : RB);
+      const int K = j == 16 ? RB : (j < NA ? RA + j : j);
+      if (K < Tn) {
+        const int c = 16 * K + li;
+        const bool zc = c >= l || sh.sdep[c];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * I + acc_row<double>(lg, r);
-        const double v = (i <= c) ? t[j][r] : 0.0;
-        Rt[(int64_t)i * ldr + c] = v;
-        const double a = (i == c) ? (zc ? 1.0 : v) : ((i < c && !zc) ? v : 0.0);
-        Ra[i * lp + c] = (T)a;
-        if (I != K) {
-          Rt[(int64_t)c * ldr + i] = 0.0;
-          Ra[c * lp + i] = T(0);
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + acc_row<double>(lg, r);
+          const double v = (i <= c) ? t[j][r] : 0.0;
+          Rt[(int64_t)i * ldr + c] = v;
+          const double a = (i == c) ? (zc ? 1.0 : v) : ((i < c && !zc) ? v : 0.0);
+          Ra[i * lp + c] = (T)a;
+          if (I != K) {
+            Rt[(int64_t)c * ldr + i] = 0.0;
+            Ra[c * lp + i] = T(0);
+          }
         }
       }
     }
   }
   if (tid < lp) dep[tid] = sh.sdep[tid];
-  if (tid == 0 && info) {
+  if (tid == 0) {
     int nd = 0;
     for (int k = 0; k < l; ++k) nd += sh.sdep[k];
-    if (nd) {
+    dep[lp] = nd;  // count of dependent columns: the completion pass skips when 0
+    if (nd && info) {
       atomicAdd(&info->n_dependent, nd);
       atomicOr(&info->status_flags, PBPQLP_FLAG_DEPENDENT);
     }
-    if (sh.sflag) atomicOr(&info->status_flags, PBPQLP_FLAG_NONFINITE);
+    if (sh.sflag && info) atomicOr(&info->status_flags, PBPQLP_FLAG_NONFINITE);
   }
 }
 
@@ -257,28 +394,63 @@ hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, do
 // ---------------------------------------------------------------------------
 // Small FP64 products C = op(A) op(B) (one thread per output element).
 // ---------------------------------------------------------------------------
-__global__ void small_gemm_kernel(int M, int N, int K, const double* __restrict__ A, int64_t lda,
-                                  int ta, const double* __restrict__ B, int64_t ldb, int tb,
-                                  double* __restrict__ C, int64_t ldc, int tc) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y;
-  if (j >= N || i >= M) return;
-  double s = 0.0;
-  for (int k = 0; k < K; ++k) {
-    const double a = ta ? A[(int64_t)k * lda + i] : A[(int64_t)i * lda + k];
-    const double b = tb ? B[(int64_t)j * ldb + k] : B[(int64_t)k * ldb + j];
-    s = fma(a, b, s);
+// One wave per 16 x 16 tile of C on the FP64 matrix core (M, N, K multiples of 16).
+__global__ __launch_bounds__(64) void small_gemm_kernel(int M, int N, int K,
+                                                        const double* __restrict__ A, int64_t lda,
+                                                        int ta, const double* __restrict__ B,
+                                                        int64_t ldb, int tb, double* __restrict__ C,
+                                                        int64_t ldc, int tc) {
+  const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
+  const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
+  f64x4 acc = {0, 0, 0, 0};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int k = k0 + acc_row<double>(lg, s4);
+      const double a = ta ? A[(int64_t)k * lda + i0 + li] : A[(int64_t)(i0 + li) * lda + k];
+      const double b = tb ? B[(int64_t)(j0 + li) * ldb + k] : B[(int64_t)k * ldb + j0 + li];
+      acc = mma_f64(a, b, acc);
+    }
   }
-  if (tc) C[(int64_t)j * ldc + i] = s;
-  else C[(int64_t)i * ldc + j] = s;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = i0 + acc_row<double>(lg, r), j = j0 + li;
+    if (tc) C[(int64_t)j * ldc + i] = acc[r];
+    else C[(int64_t)i * ldc + j] = acc[r];
+  }
 }
 
 hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, int ta,
                              const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
                              hipStream_t s) {
-  dim3 grid((unsigned)((N + 63) / 64), (unsigned)M);
+  if ((M | N | K) & 15) return hipErrorInvalidValue;
+  dim3 grid((unsigned)(N / 16), (unsigned)(M / 16));
   hipLaunchKernelGGL(small_gemm_kernel, grid, dim3(64), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C,
                      ldc, tc);
+  return hipGetLastError();
+}
+
+// out[k * ldo + j] = in[j * ldi + k] (k < rows, j < cols), FP64 in, FP64 or FP32 out
+template <typename T>
+__global__ void transpose_cast_kernel(const double* __restrict__ in, int64_t ldi, int rows, int cols,
+                                      T* __restrict__ out, int64_t ldo) {
+  __shared__ double tile[16][17];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int k0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
+  if (j0 + ty < cols && k0 + tx < rows) tile[ty][tx] = in[(int64_t)(j0 + ty) * ldi + k0 + tx];
+  __syncthreads();
+  if (k0 + ty < rows && j0 + tx < cols) out[(int64_t)(k0 + ty) * ldo + j0 + tx] = (T)tile[tx][ty];
+}
+
+hipError_t launch_transpose_cast(bool f64_out, const double* in, int64_t ldi, int rows, int cols,
+                                 void* out, int64_t ldo, hipStream_t s) {
+  dim3 grid((unsigned)((rows + 15) / 16), (unsigned)((cols + 15) / 16));
+  if (f64_out)
+    hipLaunchKernelGGL(transpose_cast_kernel<double>, grid, dim3(256), 0, s, in, ldi, rows, cols,
+                       (double*)out, ldo);
+  else
+    hipLaunchKernelGGL(transpose_cast_kernel<float>, grid, dim3(256), 0, s, in, ldi, rows, cols,
+                       (float*)out, ldo);
   return hipGetLastError();
 }
 

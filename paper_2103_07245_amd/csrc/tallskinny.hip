@@ -278,171 +278,6 @@ hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp,
 }
 
 // ---------------------------------------------------------------------------
-// Triangular apply Q = Y Ra^-1 by blocked forward substitution over 16-wide
-// column blocks, computed in the transposed space (rows of Q^T on the tile's
-// M side) so each step's previous blocks feed the matrix cores from registers:
-//   Q_J = (Y_J - sum_{I<J} Q_I Ra_IJ) Dinv_J.
-// A dependent column c (flagged by the Cholesky) is replaced by the seeded
-// unit-variance vector w_c / sqrt(len); Ra has an identity row/column there.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T completion_value(int c, int64_t a, int64_t len, uint64_t seed) {
-  return (T)(normal_at((uint64_t)a, 1u, (uint32_t)c, seed) / sqrt((double)len));
-}
-
-template <typename T, int NT>
-__global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int64_t ldy,
-                                                    int64_t len, int lp, int l,
-                                                    const T* __restrict__ Ra,
-                                                    const T* __restrict__ Dinv,
-                                                    const int* __restrict__ dep, uint64_t seed,
-                                                    T* __restrict__ Qcm, int64_t ldq,
-                                                    T* __restrict__ Qrm, int64_t ldqr) {
-  typedef typename Vec4<T>::type ACC;
-  // column block J of Ra (rows 0..16J+15) and Dinv_J, staged once per block for all waves
-  __shared__ T rcol[16 * NT][17];
-  __shared__ T dcol[16][17];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int64_t arow = (int64_t)blockIdx.x * 64 + wave * 16 + li;
-  const int Tn = lp >> 4;
-  const bool in = arow < len;
-  ACC qt[NT];
-#pragma unroll
-  for (int J = 0; J < NT; ++J) {
-    if (J < Tn) {
-      lds_barrier();
-      for (int e = tid; e < 16 * J * 16; e += 256) {
-        const int r = e >> 4, c = e & 15;
-        rcol[r][c] = Ra[(int64_t)r * lp + 16 * J + c];
-      }
-      dcol[tid >> 4][tid & 15] = Dinv[J * 256 + tid];
-      lds_barrier();
-      ACC acc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int c = 16 * J + acc_row<T>(lg, r);
-        T v = in ? Y[(int64_t)c * ldy + arow] : T(0);
-        if (in && c < l && dep[c]) v = completion_value<T>(c, arow, len, seed);
-        acc[r] = v;
-      }
-#pragma unroll
-      for (int I = 0; I < NT; ++I) {   // constant trip count so the loop unrolls; I < J live
-        if (I < J) {
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4)
-            acc = mma_native(-rcol[16 * I + acc_row<T>(lg, s4)][li], qt[I][s4], acc);
-        }
-      }
-      ACC res = {0, 0, 0, 0};
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) res = mma_native(dcol[acc_row<T>(lg, s4)][li], acc[s4], res);
-      qt[J] = res;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int c = 16 * J + acc_row<T>(lg, r);
-        if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = res[r];
-        if (Qrm && in && c < l) Qrm[arow * ldqr + c] = res[r];
-      }
-    }
-  }
-}
-
-template <typename T, int NT>
-static void apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
-                         const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
-                         void* Qrm, int64_t ldqr, hipStream_t s) {
-  const int64_t rows = Qcm ? (ldq > len ? ldq : len) : len;
-  dim3 grid((unsigned)((rows + 63) / 64));
-  hipLaunchKernelGGL((apply_kernel<T, NT>), grid, dim3(256), 0, s, (const T*)Y, ldy, len, lp, l,
-                     (const T*)Ra, (const T*)Dinv, dep, seed, (T*)Qcm, ldq, (T*)Qrm, ldqr);
-}
-
-hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
-                        const void* Ra, const void* Dinv, const int* dep, uint64_t seed, void* Qcm,
-                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s) {
-  const int T = lp / 16;
-#define PBQ_APPLY(NTV)                                                                           \
-  if (f64) apply_launch<double, NTV>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s); \
-  else apply_launch<float, NTV>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s);
-  if (T <= 2) { PBQ_APPLY(2) }
-  else if (T <= 4) { PBQ_APPLY(4) }
-  else if (T <= 8) { PBQ_APPLY(8) }
-  else if (T <= 16) { PBQ_APPLY(16) }
-  else return hipErrorInvalidValue;
-#undef PBQ_APPLY
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// Out = In M for a dense l x l M given column-major (Mt[j*ldm + k] = M[k][j]).
-// ---------------------------------------------------------------------------
-template <typename T, int NT>
-__global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In, int64_t ldi,
-                                                        int64_t len, int lp, int l,
-                                                        const T* __restrict__ Mt, int64_t ldm,
-                                                        T* __restrict__ Ocm, int64_t ldo,
-                                                        T* __restrict__ Orm, int64_t ldor) {
-  typedef typename Vec4<T>::type ACC;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int64_t arow = (int64_t)blockIdx.x * 64 + wave * 16 + li;
-  const int Tn = lp >> 4;
-  const bool in = arow < len;
-  ACC x[NT];
-#pragma unroll
-  for (int I = 0; I < NT; ++I) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = 16 * I + acc_row<T>(lg, r);
-      x[I][r] = (I < Tn && in) ? In[(int64_t)c * ldi + arow] : T(0);
-    }
-  }
-#pragma unroll
-  for (int J = 0; J < NT; ++J) {
-    if (J < Tn) {
-      ACC acc = {0, 0, 0, 0};
-#pragma unroll
-      for (int I = 0; I < NT; ++I) {
-        if (I < Tn) {
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            const T a = Mt[(int64_t)(16 * J + li) * ldm + 16 * I + acc_row<T>(lg, s4)];
-            acc = mma_native(a, x[I][s4], acc);
-          }
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int c = 16 * J + acc_row<T>(lg, r);
-        if (Ocm && arow < ldo) Ocm[(int64_t)c * ldo + arow] = acc[r];
-        if (Orm && in && c < l) Orm[arow * ldor + c] = acc[r];
-      }
-    }
-  }
-}
-
-hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
-                            const void* Mt, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
-                            int64_t ldor, hipStream_t s) {
-  const int T = lp / 16;
-  const int64_t rows = Ocm ? (ldo > len ? ldo : len) : len;
-  dim3 grid((unsigned)((rows + 63) / 64));
-#define PBQ_RM(NTV)                                                                               \
-  if (f64) hipLaunchKernelGGL((right_mul_kernel<double, NTV>), grid, dim3(256), 0, s,             \
-                              (const double*)In, ldi, len, lp, l, (const double*)Mt, ldm,         \
-                              (double*)Ocm, ldo, (double*)Orm, ldor);                             \
-  else hipLaunchKernelGGL((right_mul_kernel<float, NTV>), grid, dim3(256), 0, s,                  \
-                          (const float*)In, ldi, len, lp, l, (const float*)Mt, ldm, (float*)Ocm,  \
-                          ldo, (float*)Orm, ldor);
-  if (T <= 2) { PBQ_RM(2) }
-  else if (T <= 4) { PBQ_RM(4) }
-  else if (T <= 8) { PBQ_RM(8) }
-  else if (T <= 16) { PBQ_RM(16) }
-  else return hipErrorInvalidValue;
-#undef PBQ_RM
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
 // Layout conversions between the caller's row-major tall matrices and the
 // internal column-major buffers (32 x 32 tiles through LDS).
 // ---------------------------------------------------------------------------
