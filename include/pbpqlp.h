@@ -159,6 +159,55 @@ pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpql
 pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, int64_t ldqt,
                               double* L, int64_t ldl, pbpqlp_info* d_info, void* stream);
 
+/* ---- batches of independent problems (many uneven sizes, one plan) ----
+ *
+ * One problem of a batch: the arguments of pbpqlp_factor for one matrix, with
+ * the same meaning, layout and rules; `info` is that problem's device result
+ * record or NULL.  All pointers are DEVICE pointers owned by the caller. */
+typedef struct {
+  const void* A;
+  int64_t m, n, lda;
+  int k, p, q;
+  uint64_t seed;
+  void* Q;
+  int64_t ldq;
+  double* L;
+  int64_t ldl;
+  void* P;
+  int64_t ldp;
+  pbpqlp_info* info;
+} pbpqlp_problem;
+
+typedef struct pbpqlp_batch pbpqlp_batch;  /* opaque plan */
+
+/* Plan a batch (a project extension of the method: the same factorization as
+ * pbpqlp_factor for every problem, Algorithm 1 for A^T each).  The plan owns a
+ * device workspace for all problems (sized here, allocated with hipMalloc) and
+ * a HIP graph with one kernel launch per stage of the method and per shape
+ * class (problems whose tile counts or alignment differ use different kernel
+ * instances), the per-problem parameters in a device table.  Problems with
+ * different q form separate launch sequences inside the same graph.
+ * opts: precision plan as for pbpqlp_factor; split_k and workspace are
+ * ignored (every pass runs unsplit).  The problem list is copied; the caller's
+ * buffers must stay valid while the plan is used.  Synchronous: returns after
+ * the plan is ready.  Errors: EINVAL/EUNSUPPORTED as pbpqlp_factor would give
+ * for any problem, ENOMEM if the workspace cannot be allocated, EHIP if graph
+ * capture fails. */
+pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
+                                  const pbpqlp_opts* opts, pbpqlp_batch** out);
+/* Factorize every problem of the plan: one graph launch on `stream`
+ * (asynchronous; results and records valid when the stream reaches it). */
+pbpqlp_status pbpqlp_batch_run(pbpqlp_batch* b, void* stream);
+/* Run the same grouped launches without the graph (1) or through it (default, 1). */
+pbpqlp_status pbpqlp_batch_set_graph(pbpqlp_batch* b, int use_graph);
+/* Kernel launches per run and workspace bytes of a plan. */
+pbpqlp_status pbpqlp_batch_stats(const pbpqlp_batch* b, int* launches, size_t* workspace_bytes);
+/* Release a plan (its work must be complete). */
+void pbpqlp_batch_destroy(pbpqlp_batch* b);
+/* create + run + synchronize `stream` + destroy. */
+pbpqlp_status pbpqlp_factor_batched(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
+                                    const pbpqlp_opts* opts, void* stream);
+
 /* ---- instrumentation (benchmarking and profiling) ----
  * With level >= 1, every later call records a pair of HIP events on its
  * stream around each A-streaming product; with level >= 2 also around the

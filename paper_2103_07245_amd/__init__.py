@@ -3,8 +3,8 @@
 The computation lives in libpbpqlp.so (HIP kernels behind the C ABI of
 include/pbpqlp.h); this package only binds it.  See pbpqlp.py.
 """
-from .pbpqlp import (Factorizer, Info, PbpqlpError, PLANS, factor, library, matmul, omega, orth,
-                     small_qr, workspace_size)
+from .pbpqlp import (Batch, Factorizer, Info, PbpqlpError, PLANS, factor, library, matmul, omega,
+                     orth, small_qr, workspace_size)
 
-__all__ = ["Factorizer", "Info", "PbpqlpError", "PLANS", "factor", "library", "matmul", "omega",
-           "orth", "small_qr", "workspace_size"]
+__all__ = ["Batch", "Factorizer", "Info", "PbpqlpError", "PLANS", "factor", "library", "matmul",
+           "omega", "orth", "small_qr", "workspace_size"]

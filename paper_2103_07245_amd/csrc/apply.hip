@@ -12,6 +12,7 @@
 // scheduler sees one basic block per phase.
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pbq {
 
@@ -24,20 +25,31 @@ constexpr int kTile = 16 * 17;           // padded 16 x 16 tile in LDS
 // solve; Ra has an identity row and column there, so the solve passes them
 // through.  Blocks exit at once when no column is dependent.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void complete_kernel(T* __restrict__ Y, int64_t ldy, int64_t len,
-                                                       int l, int lp, const int* __restrict__ dep,
-                                                       uint64_t seed) {
-  if (dep[lp] == 0) return;
+struct CompleteP {
+  void* Y;
+  int64_t ldy, len;
+  int l, lp;
+  const int* dep;
+  uint64_t seed;
+  PBQ_GRID;
+};
+
+template <typename T, bool B>
+__global__ __launch_bounds__(256) void complete_kernel(const CompleteP* pb, CompleteP ps) {
+  bool past;
+  const CompleteP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  if (p.dep[p.lp] == 0) return;
   __shared__ int sd[kMaxL];
-  for (int c = threadIdx.x; c < lp; c += blockDim.x) sd[c] = dep[c];
+  for (int c = threadIdx.x; c < p.lp; c += blockDim.x) sd[c] = p.dep[c];
   __syncthreads();
   const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= len) return;
-  const double sc = 1.0 / sqrt((double)len);
+  if (row >= p.len) return;
+  T* Y = (T*)p.Y;
+  const double sc = 1.0 / sqrt((double)p.len);
 #pragma nounroll
-  for (int c = 0; c < l; ++c)
-    if (sd[c]) Y[(int64_t)c * ldy + row] = (T)(normal_at((uint64_t)row, 1u, (uint32_t)c, seed) * sc);
+  for (int c = 0; c < p.l; ++c)
+    if (sd[c]) Y[(int64_t)c * p.ldy + row] = (T)(normal_at((uint64_t)row, 1u, (uint32_t)c, p.seed) * sc);
 }
 
 // Row blocks of Ra staged per phase: row block J needs NT - J tiles (W_J and
@@ -101,13 +113,31 @@ __device__ __forceinline__ void apply_phase(typename Vec4<T>::type (&y)[NT], T* 
 // Right-looking blocked substitution: for J = 0, 1, ... the wave forms
 // Q_J = Y_J W_J (W_J the inverse of the diagonal block) in place of Y_J and
 // removes Q_J Ra_JK from every later tile K (independent chains).
-template <typename T, int NT>
-__global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int64_t ldy,
-                                                    int64_t len, int l, int lp,
-                                                    const T* __restrict__ Ra,
-                                                    const T* __restrict__ Dinv,
-                                                    T* __restrict__ Qcm, int64_t ldq,
-                                                    T* __restrict__ Qrm, int64_t ldqr) {
+struct ApplyP {
+  const void* Y;
+  int64_t ldy, len;
+  int l, lp;
+  const void* Ra;
+  const void* Dinv;
+  void* Qcm;
+  int64_t ldq;
+  void* Qrm;
+  int64_t ldqr;
+  PBQ_GRID;
+};
+
+template <typename T, int NT, bool B>
+__global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps) {
+  bool past;
+  const ApplyP prm = kparams<B>(pb, ps, past);
+  if (past) return;
+  const T* __restrict__ Y = (const T*)prm.Y;
+  const int64_t ldy = prm.ldy, len = prm.len, ldq = prm.ldq, ldqr = prm.ldqr;
+  const int l = prm.l, lp = prm.lp;
+  const T* __restrict__ Ra = (const T*)prm.Ra;
+  const T* __restrict__ Dinv = (const T*)prm.Dinv;
+  T* __restrict__ Qcm = (T*)prm.Qcm;
+  T* __restrict__ Qrm = (T*)prm.Qrm;
   typedef typename Vec4<T>::type ACC;
   constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
   static_assert(MAXT >= NT, "a phase must hold one full row block");
@@ -135,12 +165,30 @@ __global__ __launch_bounds__(256) void apply_kernel(const T* __restrict__ Y, int
 // Out = In M for a dense lp x lp M given row-major (Mr[k*ldm + j] = M[k][j]):
 // all output tiles accumulate at once while row blocks I of M stream
 // through LDS, MAXT / NT of them per phase.
-template <typename T, int NT>
-__global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In, int64_t ldi,
-                                                        int64_t len, int l,
-                                                        const T* __restrict__ Mr, int64_t ldm,
-                                                        T* __restrict__ Ocm, int64_t ldo,
-                                                        T* __restrict__ Orm, int64_t ldor) {
+struct RightMulP {
+  const void* In;
+  int64_t ldi, len;
+  int l;
+  const void* Mr;
+  int64_t ldm;
+  void* Ocm;
+  int64_t ldo;
+  void* Orm;
+  int64_t ldor;
+  PBQ_GRID;
+};
+
+template <typename T, int NT, bool B>
+__global__ __launch_bounds__(256) void right_mul_kernel(const RightMulP* pb, RightMulP ps) {
+  bool past;
+  const RightMulP prm = kparams<B>(pb, ps, past);
+  if (past) return;
+  const T* __restrict__ In = (const T*)prm.In;
+  const int64_t ldi = prm.ldi, len = prm.len, ldm = prm.ldm, ldo = prm.ldo, ldor = prm.ldor;
+  const int l = prm.l;
+  const T* __restrict__ Mr = (const T*)prm.Mr;
+  T* __restrict__ Ocm = (T*)prm.Ocm;
+  T* __restrict__ Orm = (T*)prm.Orm;
   typedef typename Vec4<T>::type ACC;
   constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
   constexpr int RPP = MAXT / NT;  // row blocks of M per phase
@@ -194,24 +242,27 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const T* __restrict__ In
 // Launchers (tile count dispatched to the exact template)
 // ---------------------------------------------------------------------------
 template <typename T, int NT>
-static void apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
-                         const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
-                         void* Qrm, int64_t ldqr, hipStream_t s) {
-  hipLaunchKernelGGL(complete_kernel<T>, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s,
-                     (T*)Y, ldy, len, l, lp, dep, seed);
+static hipError_t apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
+                               const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
+                               void* Qrm, int64_t ldqr, hipStream_t s) {
+  CompleteP c{(void*)Y, ldy, len, l, lp, dep, seed};
+  hipError_t e = launch_k(complete_kernel<T, false>, complete_kernel<T, true>, dim3((unsigned)((len + 255) / 256)),
+                          dim3(256), s, c);
+  if (e != hipSuccess) return e;
   const int64_t rows = Qcm ? (ldq > len ? ldq : len) : len;
-  hipLaunchKernelGGL((apply_kernel<T, NT>), dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
-                     (const T*)Y, ldy, len, l, lp, (const T*)Ra, (const T*)Dinv, (T*)Qcm, ldq,
-                     (T*)Qrm, ldqr);
+  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr};
+  return launch_k(apply_kernel<T, NT, false>, apply_kernel<T, NT, true>, dim3((unsigned)((rows + 63) / 64)),
+                  dim3(256), s, p);
 }
 
 template <typename T, int NT>
-static void right_mul_launch(const void* In, int64_t ldi, int64_t len, int l, const void* Mr,
-                             int64_t ldm, void* Ocm, int64_t ldo, void* Orm, int64_t ldor,
-                             hipStream_t s) {
+static hipError_t right_mul_launch(const void* In, int64_t ldi, int64_t len, int l, const void* Mr,
+                                   int64_t ldm, void* Ocm, int64_t ldo, void* Orm, int64_t ldor,
+                                   hipStream_t s) {
   const int64_t rows = Ocm ? (ldo > len ? ldo : len) : len;
-  hipLaunchKernelGGL((right_mul_kernel<T, NT>), dim3((unsigned)((rows + 63) / 64)), dim3(256), 0, s,
-                     (const T*)In, ldi, len, l, (const T*)Mr, ldm, (T*)Ocm, ldo, (T*)Orm, ldor);
+  RightMulP p{In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor};
+  return launch_k(right_mul_kernel<T, NT, false>, right_mul_kernel<T, NT, true>, dim3((unsigned)((rows + 63) / 64)),
+                  dim3(256), s, p);
 }
 
 #define PBQ_TILES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
@@ -221,15 +272,14 @@ hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int l
                         int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s) {
   if (lp % 16 || lp < 16 || lp > kMaxL) return hipErrorInvalidValue;
   switch (lp / 16) {
-#define PBQ_CASE(N)                                                                                  \
-  case N:                                                                                            \
-    if (f64) apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s); \
-    else apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s);      \
-    break;
+#define PBQ_CASE(N)                                                                                         \
+  case N:                                                                                                   \
+    return f64 ? apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s)   \
+               : apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s);
     PBQ_TILES(PBQ_CASE)
 #undef PBQ_CASE
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
@@ -237,15 +287,14 @@ hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, 
                             int64_t ldor, hipStream_t s) {
   if (lp % 16 || lp < 16 || lp > kMaxL) return hipErrorInvalidValue;
   switch (lp / 16) {
-#define PBQ_CASE(N)                                                                        \
-  case N:                                                                                  \
-    if (f64) right_mul_launch<double, N>(In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor, s); \
-    else right_mul_launch<float, N>(In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor, s);      \
-    break;
+#define PBQ_CASE(N)                                                                               \
+  case N:                                                                                         \
+    return f64 ? right_mul_launch<double, N>(In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor, s)    \
+               : right_mul_launch<float, N>(In, ldi, len, l, Mr, ldm, Ocm, ldo, Orm, ldor, s);
     PBQ_TILES(PBQ_CASE)
 #undef PBQ_CASE
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace pbq

@@ -71,7 +71,6 @@ hipError_t launch_cm_to_rm(bool f64, const void* Xt, int64_t ldt, int64_t len, i
 hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, int ta,
                              const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
                              hipStream_t s);
-hipError_t launch_cast_f64_to_f32(const double* in, int64_t n, float* out, hipStream_t s);
 // write L = U^T (lower) from upper U, zero elsewhere; rowsq[i] = sum_j L[i][j]^2 (or null)
 hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, int64_t ldl,
                                 double* rowsq, hipStream_t s);

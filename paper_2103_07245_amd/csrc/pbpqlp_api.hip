@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -15,8 +16,16 @@
 #include "../../include/pbpqlp.h"
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 using namespace pbq;
+
+namespace pbq {
+Recorder*& current_recorder() {
+  static thread_local Recorder* r = nullptr;
+  return r;
+}
+}  // namespace pbq
 
 namespace {
 
@@ -103,7 +112,7 @@ struct TraceScope {
   TraceRec* rec = nullptr;
   hipStream_t st;
   TraceScope(const char* name, double bytes, double flops, hipStream_t s, int level = 2) : st(s) {
-    if (g_trace_level < level) return;
+    if (g_trace_level < level || pbq::current_recorder()) return;
     std::lock_guard<std::mutex> lk(g_trace_mu);
     if (g_trace_n == g_trace.size()) {
       TraceRec r;
@@ -415,6 +424,65 @@ pbpqlp_status alloc_scratch(ScratchGuard& g, size_t bytes, hipStream_t st) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Batches: the single-problem orchestration is recorded once per problem and
+// the records become grouped launches (see launch.h).  Problems with the same
+// launch sequence (the same q) form a class; launch j of every problem in a
+// class runs in one kernel launch per distinct kernel (shape class), with the
+// per-problem parameters in a device array and blockIdx.z selecting the
+// problem.  Stream order between consecutive launches keeps each problem's
+// dependencies.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchGroup {
+  const void* fn;
+  dim3 grid, block;
+  size_t psize, offset;  // parameter block size and its offset in the device array
+  int count;
+};
+
+}  // namespace
+
+struct pbpqlp_batch {
+  int count = 0;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* dparams = nullptr;
+  size_t dparams_bytes = 0;
+  std::vector<BatchGroup> groups;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int use_graph = 1;
+};
+
+namespace {
+
+void batch_free(pbpqlp_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->dparams) (void)hipFree(b->dparams);
+  if (b->ws) (void)hipFree(b->ws);
+  delete b;
+}
+
+pbpqlp_status batch_launch_all(pbpqlp_batch* b, hipStream_t st) {
+  alignas(16) unsigned char zero[512] = {};
+  for (const BatchGroup& g : b->groups) {
+    void* dptr = (char*)b->dparams + g.offset;
+    void* args[2] = {&dptr, zero};
+    if (g.psize > sizeof(zero)) return PBPQLP_EHIP;
+    dim3 grid(g.grid.x, g.grid.y, (unsigned)g.count);
+    if (hipLaunchKernel(g.fn, grid, g.block, args, 0, st) != hipSuccess) return PBPQLP_EHIP;
+  }
+  return hipGetLastError() == hipSuccess ? PBPQLP_OK : PBPQLP_EHIP;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* pbpqlp_status_string(pbpqlp_status s) {
@@ -671,6 +739,160 @@ pbpqlp_status pbpqlp_trace_get(int i, char* name, int name_len, double* bytes, d
     if (hipEventElapsedTime(ms, r.a, r.b) != hipSuccess) return PBPQLP_EHIP;
   }
   return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
+                                  const pbpqlp_opts* opts, pbpqlp_batch** out) {
+  if (!out || count < 1 || !problems) return PBPQLP_EINVAL;
+  *out = nullptr;
+  pbpqlp_opts o;
+  pbpqlp_default_opts(&o);
+  if (opts) o = *opts;
+  o.split_k = 1;               // one contraction split: every problem runs the same launch sequence
+  o.workspace = nullptr;
+  o.workspace_bytes = 0;
+  std::vector<Ctx> ctx((size_t)count);
+  std::vector<size_t> off((size_t)count);
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    const pbpqlp_problem& pr = problems[i];
+    if (!pr.A || !pr.Q || !pr.L || !pr.P) return PBPQLP_EINVAL;
+    Ctx& c = ctx[(size_t)i];
+    pbpqlp_status s = setup(c, pr.m, pr.n, pr.lda, dt, pr.k, pr.p, pr.q, &o);
+    if (s) return s;
+    if (pr.ldq < c.l || pr.ldl < c.l || pr.ldp < c.l) return PBPQLP_EINVAL;
+    if (pr.Q == pr.A || pr.P == pr.A || pr.Q == pr.P) return PBPQLP_EINVAL;
+    c.seed = pr.seed;
+    Bump sizer;
+    c.carve(sizer, needs16(c));
+    sizer.take(sizeof(pbpqlp_info));
+    off[(size_t)i] = total;
+    total += (size_t)rup((int64_t)sizer.off, 256);
+  }
+  pbpqlp_batch* b = new pbpqlp_batch();
+  b->count = count;
+  b->ws_bytes = total;
+  if (hipMalloc(&b->ws, total > 0 ? total : 256) != hipSuccess) {
+    batch_free(b);
+    return PBPQLP_ENOMEM;
+  }
+  // record every problem's launch sequence
+  std::vector<Recorder> recs((size_t)count);
+  for (int i = 0; i < count; ++i) {
+    const pbpqlp_problem& pr = problems[i];
+    Ctx& c = ctx[(size_t)i];
+    Bump bp;
+    bp.base = (char*)b->ws + off[(size_t)i];
+    c.carve(bp, needs16(c));
+    pbpqlp_info* own = (pbpqlp_info*)bp.take(sizeof(pbpqlp_info));
+    current_recorder() = &recs[(size_t)i];
+    const pbpqlp_status s = run_factor(c, pr.A, pr.Q, pr.ldq, pr.L, pr.ldl, pr.P, pr.ldp,
+                                       pr.info ? pr.info : own, nullptr);
+    current_recorder() = nullptr;
+    if (s) {
+      batch_free(b);
+      return s;
+    }
+  }
+  // classes of identical sequences (same q), then one group per (slot, kernel)
+  std::map<int, std::vector<int>> classes;
+  for (int i = 0; i < count; ++i) classes[problems[i].q].push_back(i);
+  std::vector<unsigned char> host;
+  for (auto& kv : classes) {
+    const std::vector<int>& members = kv.second;
+    const size_t L = recs[(size_t)members[0]].recs.size();
+    for (int i : members)
+      if (recs[(size_t)i].recs.size() != L) {
+        batch_free(b);
+        return PBPQLP_EUNSUPPORTED;
+      }
+    for (size_t j = 0; j < L; ++j) {
+      std::vector<const void*> fns;
+      for (int i : members) {
+        const void* f = recs[(size_t)i].recs[j].fn;
+        bool seen = false;
+        for (const void* g : fns) seen = seen || g == f;
+        if (!seen) fns.push_back(f);
+      }
+      for (const void* f : fns) {
+        BatchGroup g{};
+        g.fn = f;
+        g.count = 0;
+        for (int i : members) {
+          const LaunchRec& r = recs[(size_t)i].recs[j];
+          if (r.fn != f) continue;
+          if (g.count == 0) {
+            g.block = r.block;
+            g.psize = r.params.size();
+            g.grid = dim3(0, 0, 1);
+            host.resize((host.size() + 255) & ~(size_t)255);
+            g.offset = host.size();
+          }
+          g.grid.x = r.grid.x > g.grid.x ? r.grid.x : g.grid.x;
+          g.grid.y = r.grid.y > g.grid.y ? r.grid.y : g.grid.y;
+          host.insert(host.end(), r.params.begin(), r.params.end());
+          ++g.count;
+        }
+        b->groups.push_back(g);
+      }
+    }
+  }
+  b->dparams_bytes = host.size();
+  if (hipMalloc(&b->dparams, host.size() > 0 ? host.size() : 256) != hipSuccess ||
+      hipMemcpy(b->dparams, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    batch_free(b);
+    return PBPQLP_ENOMEM;
+  }
+  // capture the grouped launches once; runs replay the graph
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+    batch_free(b);
+    return PBPQLP_EHIP;
+  }
+  if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    batch_free(b);
+    return PBPQLP_EHIP;
+  }
+  const pbpqlp_status ls = batch_launch_all(b, b->cap);
+  const hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
+  if (ls || ce != hipSuccess || hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+    batch_free(b);
+    return PBPQLP_EHIP;
+  }
+  *out = b;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_batch_run(pbpqlp_batch* b, void* stream) {
+  if (!b) return PBPQLP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (b->use_graph) return hipGraphLaunch(b->exec, st) == hipSuccess ? PBPQLP_OK : PBPQLP_EHIP;
+  return batch_launch_all(b, st);
+}
+
+pbpqlp_status pbpqlp_batch_set_graph(pbpqlp_batch* b, int use_graph) {
+  if (!b) return PBPQLP_EINVAL;
+  b->use_graph = use_graph ? 1 : 0;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_batch_stats(const pbpqlp_batch* b, int* launches, size_t* workspace_bytes) {
+  if (!b) return PBPQLP_EINVAL;
+  if (launches) *launches = (int)b->groups.size();
+  if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+  return PBPQLP_OK;
+}
+
+void pbpqlp_batch_destroy(pbpqlp_batch* b) { batch_free(b); }
+
+pbpqlp_status pbpqlp_factor_batched(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
+                                    const pbpqlp_opts* opts, void* stream) {
+  pbpqlp_batch* b = nullptr;
+  pbpqlp_status s = pbpqlp_batch_create(count, problems, dt, opts, &b);
+  if (s) return s;
+  s = pbpqlp_batch_run(b, stream);
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess && !s) s = PBPQLP_EHIP;
+  pbpqlp_batch_destroy(b);
+  return s;
 }
 
 }  // extern "C"

@@ -3,6 +3,7 @@
 // small products (R2 R1, U2 U1) and the result record.
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 #include "../../include/pbpqlp.h"
 
 namespace pbq {
@@ -190,12 +191,35 @@ __device__ __forceinline__ void diag_factor(CholShared& sh, int J, int l, double
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kCholThreads) void chol_kernel(const double* __restrict__ G, int64_t ldg,
-                                                            int l, int lp, double eps,
-                                                            double* __restrict__ Rt, int64_t ldr,
-                                                            T* __restrict__ Ra, T* __restrict__ Dinv,
-                                                            int* __restrict__ dep, pbpqlp_info* info) {
+struct CholP {
+  const double* G;
+  int64_t ldg;
+  int l, lp;
+  double eps;
+  double* Rt;
+  int64_t ldr;
+  void* Ra;
+  void* Dinv;
+  int* dep;
+  pbpqlp_info* info;
+  PBQ_GRID;
+};
+
+template <typename T, bool B>
+__global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, CholP ps) {
+  bool past;
+  const CholP prm = kparams<B>(pb, ps, past);
+  if (past) return;
+  const double* __restrict__ G = prm.G;
+  const int64_t ldg = prm.ldg;
+  const int l = prm.l, lp = prm.lp;
+  const double eps = prm.eps;
+  double* __restrict__ Rt = prm.Rt;
+  const int64_t ldr = prm.ldr;
+  T* __restrict__ Ra = (T*)prm.Ra;
+  T* __restrict__ Dinv = (T*)prm.Dinv;
+  int* __restrict__ dep = prm.dep;
+  pbpqlp_info* info = prm.info;
   __shared__ CholShared sh;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   if (tid < kMaxL) {
@@ -382,41 +406,51 @@ hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, do
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
                        hipStream_t s) {
   if (lp > kMaxL || (lp & 15)) return hipErrorInvalidValue;
-  if (f64)
-    hipLaunchKernelGGL(chol_kernel<double>, dim3(1), dim3(kCholThreads), 0, s, G, ldg, l, lp, eps_dep, Rt,
-                       ldr, (double*)Ra, (double*)Dinv, dep, (pbpqlp_info*)info);
-  else
-    hipLaunchKernelGGL(chol_kernel<float>, dim3(1), dim3(kCholThreads), 0, s, G, ldg, l, lp, eps_dep, Rt,
-                       ldr, (float*)Ra, (float*)Dinv, dep, (pbpqlp_info*)info);
-  return hipGetLastError();
+  CholP p{G, ldg, l, lp, eps_dep, Rt, ldr, Ra, Dinv, dep, (pbpqlp_info*)info};
+  if (f64) return launch_k(chol_kernel<double, false>, chol_kernel<double, true>, dim3(1), dim3(kCholThreads), s, p);
+  return launch_k(chol_kernel<float, false>, chol_kernel<float, true>, dim3(1), dim3(kCholThreads), s, p);
 }
 
 // ---------------------------------------------------------------------------
-// Small FP64 products C = op(A) op(B) (one thread per output element).
+// Small FP64 products C = op(A) op(B): one wave per 16 x 16 tile of C on the
+// FP64 matrix core (M, N, K multiples of 16).
 // ---------------------------------------------------------------------------
-// One wave per 16 x 16 tile of C on the FP64 matrix core (M, N, K multiples of 16).
-__global__ __launch_bounds__(64) void small_gemm_kernel(int M, int N, int K,
-                                                        const double* __restrict__ A, int64_t lda,
-                                                        int ta, const double* __restrict__ B,
-                                                        int64_t ldb, int tb, double* __restrict__ C,
-                                                        int64_t ldc, int tc) {
+struct GemmP {
+  int M, N, K;
+  const double* A;
+  int64_t lda;
+  int ta;
+  const double* Bm;
+  int64_t ldb;
+  int tb;
+  double* C;
+  int64_t ldc;
+  int tc;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ __launch_bounds__(64) void small_gemm_kernel(const GemmP* pb, GemmP ps) {
+  bool past;
+  const GemmP p = kparams<B>(pb, ps, past);
+  if (past) return;
   const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
   f64x4 acc = {0, 0, 0, 0};
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = 0; k0 < p.K; k0 += 16) {
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int k = k0 + acc_row<double>(lg, s4);
-      const double a = ta ? A[(int64_t)k * lda + i0 + li] : A[(int64_t)(i0 + li) * lda + k];
-      const double b = tb ? B[(int64_t)(j0 + li) * ldb + k] : B[(int64_t)k * ldb + j0 + li];
+      const double a = p.ta ? p.A[(int64_t)k * p.lda + i0 + li] : p.A[(int64_t)(i0 + li) * p.lda + k];
+      const double b = p.tb ? p.Bm[(int64_t)(j0 + li) * p.ldb + k] : p.Bm[(int64_t)k * p.ldb + j0 + li];
       acc = mma_f64(a, b, acc);
     }
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int i = i0 + acc_row<double>(lg, r), j = j0 + li;
-    if (tc) C[(int64_t)j * ldc + i] = acc[r];
-    else C[(int64_t)i * ldc + j] = acc[r];
+    if (p.tc) p.C[(int64_t)j * p.ldc + i] = acc[r];
+    else p.C[(int64_t)i * p.ldc + j] = acc[r];
   }
 }
 
@@ -424,56 +458,65 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, 
                              const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
                              hipStream_t s) {
   if ((M | N | K) & 15) return hipErrorInvalidValue;
-  dim3 grid((unsigned)(N / 16), (unsigned)(M / 16));
-  hipLaunchKernelGGL(small_gemm_kernel, grid, dim3(64), 0, s, M, N, K, A, lda, ta, B, ldb, tb, C,
-                     ldc, tc);
-  return hipGetLastError();
+  GemmP p{M, N, K, A, lda, ta, B, ldb, tb, C, ldc, tc};
+  return launch_k(small_gemm_kernel<false>, small_gemm_kernel<true>, dim3((unsigned)(N / 16), (unsigned)(M / 16)),
+                  dim3(64), s, p);
 }
 
 // out[k * ldo + j] = in[j * ldi + k] (k < rows, j < cols), FP64 in, FP64 or FP32 out
-template <typename T>
-__global__ void transpose_cast_kernel(const double* __restrict__ in, int64_t ldi, int rows, int cols,
-                                      T* __restrict__ out, int64_t ldo) {
+struct TransposeP {
+  const double* in;
+  int64_t ldi;
+  int rows, cols;
+  void* out;
+  int64_t ldo;
+  PBQ_GRID;
+};
+
+template <typename T, bool B>
+__global__ void transpose_cast_kernel(const TransposeP* pb, TransposeP ps) {
+  bool past;
+  const TransposeP p = kparams<B>(pb, ps, past);
+  if (past) return;
   __shared__ double tile[16][17];
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   const int k0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
-  if (j0 + ty < cols && k0 + tx < rows) tile[ty][tx] = in[(int64_t)(j0 + ty) * ldi + k0 + tx];
+  if (j0 + ty < p.cols && k0 + tx < p.rows) tile[ty][tx] = p.in[(int64_t)(j0 + ty) * p.ldi + k0 + tx];
   __syncthreads();
-  if (k0 + ty < rows && j0 + tx < cols) out[(int64_t)(k0 + ty) * ldo + j0 + tx] = (T)tile[tx][ty];
+  if (k0 + ty < p.rows && j0 + tx < p.cols) ((T*)p.out)[(int64_t)(k0 + ty) * p.ldo + j0 + tx] = (T)tile[tx][ty];
 }
 
 hipError_t launch_transpose_cast(bool f64_out, const double* in, int64_t ldi, int rows, int cols,
                                  void* out, int64_t ldo, hipStream_t s) {
   dim3 grid((unsigned)((rows + 15) / 16), (unsigned)((cols + 15) / 16));
-  if (f64_out)
-    hipLaunchKernelGGL(transpose_cast_kernel<double>, grid, dim3(256), 0, s, in, ldi, rows, cols,
-                       (double*)out, ldo);
-  else
-    hipLaunchKernelGGL(transpose_cast_kernel<float>, grid, dim3(256), 0, s, in, ldi, rows, cols,
-                       (float*)out, ldo);
-  return hipGetLastError();
-}
-
-__global__ void cast_kernel(const double* __restrict__ in, int64_t n, float* __restrict__ out) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = (float)in[i];
-}
-
-hipError_t launch_cast_f64_to_f32(const double* in, int64_t n, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(cast_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, n, out);
-  return hipGetLastError();
+  TransposeP p{in, ldi, rows, cols, out, ldo};
+  if (f64_out) return launch_k(transpose_cast_kernel<double, false>, transpose_cast_kernel<double, true>, grid, dim3(256), s, p);
+  return launch_k(transpose_cast_kernel<float, false>, transpose_cast_kernel<float, true>, grid, dim3(256), s, p);
 }
 
 // L = U^T (lower triangle, zero above) with one block per row i; the block
 // also leaves sum_j L[i][j]^2 in rowsq[i] for the result record.
-__global__ void write_lower_t_kernel(const double* __restrict__ U, int64_t ldu, int l,
-                                     double* __restrict__ L, int64_t ldl, double* __restrict__ rowsq) {
+struct LowerP {
+  const double* U;
+  int64_t ldu;
+  int l;
+  double* L;
+  int64_t ldl;
+  double* rowsq;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void write_lower_t_kernel(const LowerP* pb, LowerP ps) {
+  bool past;
+  const LowerP p = kparams<B>(pb, ps, past);
+  if (past) return;
   __shared__ double red[256];
   const int i = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
-  for (int j = t; j < l; j += 256) {
-    const double v = (j <= i) ? U[(int64_t)j * ldu + i] : 0.0;
-    L[(int64_t)i * ldl + j] = v;
+  for (int j = t; j < p.l; j += 256) {
+    const double v = (j <= i) ? p.U[(int64_t)j * p.ldu + i] : 0.0;
+    p.L[(int64_t)i * p.ldl + j] = v;
     s += v * v;
   }
   red[t] = s;
@@ -482,14 +525,13 @@ __global__ void write_lower_t_kernel(const double* __restrict__ U, int64_t ldu, 
     if (t < off) red[t] += red[t + off];
     __syncthreads();
   }
-  if (t == 0 && rowsq) rowsq[i] = red[0];
+  if (t == 0 && p.rowsq) p.rowsq[i] = red[0];
 }
 
 hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, int64_t ldl,
                                 double* rowsq, hipStream_t s) {
-  hipLaunchKernelGGL(write_lower_t_kernel, dim3((unsigned)l), dim3(256), 0, s, U, ldu, l, L, ldl,
-                     rowsq);
-  return hipGetLastError();
+  LowerP p{U, ldu, l, L, ldl, rowsq};
+  return launch_k(write_lower_t_kernel<false>, write_lower_t_kernel<true>, dim3((unsigned)l), dim3(256), s, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -498,12 +540,23 @@ hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, 
 // the a-posteriori residual sqrt(||A||^2 - ||L||^2) / ||A|| (for an
 // orthogonal projection Q Q^T A the two norms differ by the residual's).
 // ---------------------------------------------------------------------------
-__global__ void info_init_kernel(pbpqlp_info* info, int l, int q) {
+struct InfoInitP {
+  pbpqlp_info* info;
+  int l, q;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void info_init_kernel(const InfoInitP* pb, InfoInitP ps) {
+  bool past;
+  const InfoInitP p = kparams<B>(pb, ps, past);
+  if (past) return;
   if (threadIdx.x == 0) {
+    pbpqlp_info* info = p.info;
     info->status_flags = 0;
     info->n_dependent = 0;
-    info->l = l;
-    info->q = q;
+    info->l = p.l;
+    info->q = p.q;
     info->norm_a_fro2 = 0.0;
     info->norm_l_fro2 = 0.0;
     info->resid_rel_est = 0.0;
@@ -513,23 +566,35 @@ __global__ void info_init_kernel(pbpqlp_info* info, int l, int q) {
 }
 
 hipError_t launch_info_init(void* info, int l, int q, hipStream_t s) {
-  hipLaunchKernelGGL(info_init_kernel, dim3(1), dim3(64), 0, s, (pbpqlp_info*)info, l, q);
-  return hipGetLastError();
+  InfoInitP p{(pbpqlp_info*)info, l, q};
+  return launch_k(info_init_kernel<false>, info_init_kernel<true>, dim3(1), dim3(64), s, p);
 }
 
-__global__ void info_finalize_kernel(pbpqlp_info* info, const double* __restrict__ parts,
-                                     int nparts, const double* __restrict__ rowsq, int l) {
+struct InfoFinP {
+  pbpqlp_info* info;
+  const double* parts;
+  int nparts;
+  const double* rowsq;
+  int l;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void info_finalize_kernel(const InfoFinP* pb, InfoFinP ps) {
+  bool past;
+  const InfoFinP p = kparams<B>(pb, ps, past);
+  if (past) return;
   __shared__ double ra[256], rl[256];
   const int t = threadIdx.x;
   double a0 = 0.0, a1 = 0.0;
   int i = t;
-  for (; i + 256 < nparts; i += 512) {
-    a0 += parts[i];
-    a1 += parts[i + 256];
+  for (; i + 256 < p.nparts; i += 512) {
+    a0 += p.parts[i];
+    a1 += p.parts[i + 256];
   }
-  if (i < nparts) a0 += parts[i];
+  if (i < p.nparts) a0 += p.parts[i];
   ra[t] = a0 + a1;
-  rl[t] = (t < l) ? rowsq[t] : 0.0;
+  rl[t] = (t < p.l) ? p.rowsq[t] : 0.0;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (t < off) {
@@ -539,52 +604,68 @@ __global__ void info_finalize_kernel(pbpqlp_info* info, const double* __restrict
     __syncthreads();
   }
   if (t == 0) {
-    info->norm_a_fro2 = ra[0];
-    info->norm_l_fro2 = rl[0];
+    p.info->norm_a_fro2 = ra[0];
+    p.info->norm_l_fro2 = rl[0];
     const double d = ra[0] - rl[0];
-    info->resid_rel_est = ra[0] > 0.0 ? sqrt((d > 0.0 ? d : 0.0) / ra[0]) : 0.0;
+    p.info->resid_rel_est = ra[0] > 0.0 ? sqrt((d > 0.0 ? d : 0.0) / ra[0]) : 0.0;
   }
 }
 
 hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts,
                                 const double* rowsq, int l, hipStream_t s) {
-  hipLaunchKernelGGL(info_finalize_kernel, dim3(1), dim3(256), 0, s, (pbpqlp_info*)info,
-                     normA_part, nparts, rowsq, l);
-  return hipGetLastError();
+  InfoFinP p{(pbpqlp_info*)info, normA_part, nparts, rowsq, l};
+  return launch_k(info_finalize_kernel<false>, info_finalize_kernel<true>, dim3(1), dim3(256), s, p);
 }
 
-__global__ void fill_zero_kernel(uint32_t* p, size_t nwords) {
+struct FillP {
+  uint32_t* p;
+  size_t nwords;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void fill_zero_kernel(const FillP* pb, FillP ps) {
+  bool past;
+  const FillP p = kparams<B>(pb, ps, past);
+  if (past) return;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nwords) p[i] = 0u;
+  if (i < p.nwords) p.p[i] = 0u;
 }
 
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s) {
   const size_t nw = bytes / 4;
   if (nw == 0) return hipSuccess;
-  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, s,
-                     (uint32_t*)p, nw);
-  return hipGetLastError();
+  FillP f{(uint32_t*)p, nw};
+  return launch_k(fill_zero_kernel<false>, fill_zero_kernel<true>, dim3((unsigned)((nw + 255) / 256)), dim3(256), s, f);
 }
 
-}  // namespace pbq
+struct CopyP {
+  const double* in;
+  int64_t ldi;
+  int rows, cols;
+  double* out;
+  int64_t ldo;
+  int upper_only;
+  PBQ_GRID;
+};
 
-namespace pbq {
-
-__global__ void copy_mat_kernel(const double* __restrict__ in, int64_t ldi, int rows, int cols,
-                                double* __restrict__ out, int64_t ldo, int upper_only) {
+template <bool B>
+__global__ void copy_mat_kernel(const CopyP* pb, CopyP ps) {
+  bool past;
+  const CopyP p = kparams<B>(pb, ps, past);
+  if (past) return;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y;
-  if (j >= cols || i >= rows) return;
-  const double v = in[(int64_t)i * ldi + j];
-  out[(int64_t)i * ldo + j] = (upper_only && j < i) ? 0.0 : v;
+  if (j >= p.cols || i >= p.rows) return;
+  const double v = p.in[(int64_t)i * p.ldi + j];
+  p.out[(int64_t)i * p.ldo + j] = (p.upper_only && j < i) ? 0.0 : v;
 }
 
 hipError_t launch_copy_mat(const double* in, int64_t ldi, int rows, int cols, double* out,
                            int64_t ldo, int upper_only, hipStream_t s) {
-  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)rows);
-  hipLaunchKernelGGL(copy_mat_kernel, grid, dim3(64), 0, s, in, ldi, rows, cols, out, ldo,
-                     upper_only);
-  return hipGetLastError();
+  CopyP p{in, ldi, rows, cols, out, ldo, upper_only};
+  return launch_k(copy_mat_kernel<false>, copy_mat_kernel<true>, dim3((unsigned)((cols + 63) / 64), (unsigned)rows),
+                  dim3(64), s, p);
 }
 
 }  // namespace pbq

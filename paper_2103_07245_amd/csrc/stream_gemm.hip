@@ -30,6 +30,7 @@
 // registers), BF16X3 (hi*hi + hi*lo + lo*hi of bfloat16 splits).
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pbq {
 
@@ -159,6 +160,7 @@ struct StreamParams {
   int64_t ldo, split_stride, chunk;
   double* normA;
   float a_scale, out_scale;
+  PBQ_GRID;
 };
 
 // ---------------------------------------------------------------------------
@@ -169,8 +171,12 @@ struct StreamParams {
 // VEC: A rows are 16-byte aligned (K1) / lda and n are multiples of RT (K2),
 // so full stages use vector loads; otherwise every load is masked.
 // ---------------------------------------------------------------------------
-template <int MODE, int NT, bool TRANS, bool VEC>
-__global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void stream_kernel(StreamParams p) {
+template <int MODE, int NT, bool TRANS, bool VEC, bool B>
+__global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void stream_kernel(const StreamParams* pb,
+                                                                                       StreamParams ps) {
+  bool past;
+  const StreamParams p = kparams<B>(pb, ps, past);
+  if (past) return;
   typedef Tr<MODE> TR;
   typedef typename TR::TA TA;
   typedef typename TR::TC TC;
@@ -419,7 +425,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) t += red[w];
-      p.normA[blockIdx.y * gridDim.x + blockIdx.x] = t;
+      p.normA[blockIdx.y * p.gx + blockIdx.x] = t;
     }
   }
 }
@@ -440,10 +446,10 @@ static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   p.normA = TRANS ? nullptr : a.normA;
   p.a_scale = a.a_scale; p.out_scale = a.out_scale;
   if (vec)
-    hipLaunchKernelGGL((stream_kernel<MODE, NT, TRANS, true>), grid, dim3(64 * TR::NW), 0, s, p);
-  else
-    hipLaunchKernelGGL((stream_kernel<MODE, NT, TRANS, false>), grid, dim3(64 * TR::NW), 0, s, p);
-  return hipGetLastError();
+    return launch_k(stream_kernel<MODE, NT, TRANS, true, false>, stream_kernel<MODE, NT, TRANS, true, true>,
+                    grid, dim3(64 * TR::NW), s, p);
+  return launch_k(stream_kernel<MODE, NT, TRANS, false, false>, stream_kernel<MODE, NT, TRANS, false, true>,
+                  grid, dim3(64 * TR::NW), s, p);
 }
 
 template <int MODE, bool TRANS>

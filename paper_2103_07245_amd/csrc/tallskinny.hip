@@ -8,6 +8,7 @@
 // [len, ld) so consumers can read whole 64-element groups without checks.
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 #include "../../include/pbpqlp.h"
 
 namespace pbq {
@@ -22,18 +23,30 @@ __device__ __forceinline__ double omega_elem(int64_t i, int c, int l, uint64_t s
   return sketch_value(normal_at(t, 0u, 0u, seed));
 }
 
-template <typename T>
-__global__ void omega_cm_kernel(int64_t n, int l, int lp32, uint64_t seed, T* __restrict__ Ot,
-                                int64_t ld) {
+struct OmegaP {
+  int64_t n;
+  int l, lp32;
+  uint64_t seed;
+  void* Ot;
+  int64_t ld;
+  PBQ_GRID;
+};
+
+template <typename T, bool B>
+__global__ void omega_cm_kernel(const OmegaP* pb, OmegaP ps) {
+  bool past;
+  const OmegaP p = kparams<B>(pb, ps, past);
+  if (past) return;
   const int c = blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= ld) return;
+  if (i0 >= p.ld) return;
+  T* Ot = (T*)p.Ot;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t i = i0 + e;
     T v = 0;
-    if (c < l && i < n) v = (T)omega_elem(i, c, l, seed);
-    if (i < ld) Ot[(int64_t)c * ld + i] = v;
+    if (c < p.l && i < p.n) v = (T)omega_elem(i, c, p.l, p.seed);
+    if (i < p.ld) Ot[(int64_t)c * p.ld + i] = v;
   }
 }
 
@@ -48,13 +61,9 @@ __global__ void omega_rm_kernel(int64_t n, int l, uint64_t seed, T* __restrict__
 hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot,
                            int64_t ld, hipStream_t s) {
   dim3 grid((unsigned)((ld / 4 + 255) / 256), (unsigned)lp32);
-  if (f64)
-    hipLaunchKernelGGL(omega_cm_kernel<double>, grid, dim3(256), 0, s, n, l, lp32, seed,
-                       (double*)Ot, ld);
-  else
-    hipLaunchKernelGGL(omega_cm_kernel<float>, grid, dim3(256), 0, s, n, l, lp32, seed,
-                       (float*)Ot, ld);
-  return hipGetLastError();
+  OmegaP p{n, l, lp32, seed, Ot, ld};
+  if (f64) return launch_k(omega_cm_kernel<double, false>, omega_cm_kernel<double, true>, grid, dim3(256), s, p);
+  return launch_k(omega_cm_kernel<float, false>, omega_cm_kernel<float, true>, grid, dim3(256), s, p);
 }
 
 hipError_t launch_omega_rm(bool f64, int64_t n, int l, uint64_t seed, void* O, int64_t ldo,
@@ -70,31 +79,43 @@ hipError_t launch_omega_rm(bool f64, int64_t n, int l, uint64_t seed, void* O, i
 // ---------------------------------------------------------------------------
 // FP32 operand -> 16-bit compute type (hi, and lo = x - hi for BF16X3).
 // ---------------------------------------------------------------------------
-template <int MODE>
-__global__ void convert_kernel(const float* __restrict__ X, int64_t ld, int64_t len, int l,
-                               float scale, void* __restrict__ hi_, void* __restrict__ lo_) {
+struct ConvertP {
+  const float* X;
+  int64_t ld, len;
+  int l;
+  float scale;
+  void* hi;
+  void* lo;
+  PBQ_GRID;
+};
+
+template <int MODE, bool B>
+__global__ void convert_kernel(const ConvertP* pb, ConvertP ps) {
+  bool past;
+  const ConvertP p = kparams<B>(pb, ps, past);
+  if (past) return;
   const int c = blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= ld) return;
+  if (i0 >= p.ld) return;
   float v[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int64_t i = i0 + e;
-    v[e] = (c < l && i < len) ? X[(int64_t)c * ld + i] * scale : 0.0f;
+    v[e] = (c < p.l && i < p.len) ? p.X[(int64_t)c * p.ld + i] * p.scale : 0.0f;
   }
   if constexpr (MODE == M_F16) {
-    _Float16* hi = (_Float16*)hi_;
+    _Float16* hi = (_Float16*)p.hi;
     f16x4 h = {(_Float16)v[0], (_Float16)v[1], (_Float16)v[2], (_Float16)v[3]};
-    *(f16x4*)(hi + (int64_t)c * ld + i0) = h;
+    *(f16x4*)(hi + (int64_t)c * p.ld + i0) = h;
   } else {
-    __bf16* hi = (__bf16*)hi_;
+    __bf16* hi = (__bf16*)p.hi;
     bf16x4 h = {(__bf16)v[0], (__bf16)v[1], (__bf16)v[2], (__bf16)v[3]};
-    *(bf16x4*)(hi + (int64_t)c * ld + i0) = h;
+    *(bf16x4*)(hi + (int64_t)c * p.ld + i0) = h;
     if constexpr (MODE == M_BF16X3) {
-      __bf16* lo = (__bf16*)lo_;
+      __bf16* lo = (__bf16*)p.lo;
       bf16x4 w = {(__bf16)(v[0] - (float)h[0]), (__bf16)(v[1] - (float)h[1]),
                   (__bf16)(v[2] - (float)h[2]), (__bf16)(v[3] - (float)h[3])};
-      *(bf16x4*)(lo + (int64_t)c * ld + i0) = w;
+      *(bf16x4*)(lo + (int64_t)c * p.ld + i0) = w;
     }
   }
 }
@@ -102,61 +123,64 @@ __global__ void convert_kernel(const float* __restrict__ X, int64_t ld, int64_t 
 hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int l, int lp32,
                           float scale, void* hi, void* lo, hipStream_t s) {
   dim3 grid((unsigned)((ld / 4 + 255) / 256), (unsigned)lp32);
+  ConvertP p{X, ld, len, l, scale, hi, lo};
   switch (mode) {
-    case M_BF16:
-      hipLaunchKernelGGL(convert_kernel<M_BF16>, grid, dim3(256), 0, s, X, ld, len, l, scale, hi, lo);
-      break;
-    case M_F16:
-      hipLaunchKernelGGL(convert_kernel<M_F16>, grid, dim3(256), 0, s, X, ld, len, l, scale, hi, lo);
-      break;
-    case M_BF16X3:
-      hipLaunchKernelGGL(convert_kernel<M_BF16X3>, grid, dim3(256), 0, s, X, ld, len, l, scale, hi, lo);
-      break;
-    default:
-      return hipErrorInvalidValue;
+    case M_BF16: return launch_k(convert_kernel<M_BF16, false>, convert_kernel<M_BF16, true>, grid, dim3(256), s, p);
+    case M_F16: return launch_k(convert_kernel<M_F16, false>, convert_kernel<M_F16, true>, grid, dim3(256), s, p);
+    case M_BF16X3: return launch_k(convert_kernel<M_BF16X3, false>, convert_kernel<M_BF16X3, true>, grid, dim3(256), s, p);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
 // Split-K reduction in a fixed order (bitwise reproducible).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void splitk_reduce_kernel(const T* __restrict__ part, int64_t stride, int S,
-                                     int64_t ld, int64_t len, T* __restrict__ out, int64_t ldo) {
+struct ReduceP {
+  const void* part;
+  int64_t stride;
+  int S;
+  int64_t ld, len;
+  void* out;
+  int64_t ldo;
+  PBQ_GRID;
+};
+
+template <typename T, bool B>
+__global__ void splitk_reduce_kernel(const ReduceP* pb, ReduceP ps) {
+  bool past;
+  const ReduceP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  const T* part = (const T*)p.part;
+  T* out = (T*)p.out;
   const int c = blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= ldo) return;
+  if (i0 >= p.ldo) return;
   T acc[4] = {0, 0, 0, 0};
-  if (i0 + 3 < len) {
-    for (int sp = 0; sp < S; ++sp) {
-      const T* p = part + (int64_t)sp * stride + (int64_t)c * ld + i0;
+  if (i0 + 3 < p.len) {
+    for (int sp = 0; sp < p.S; ++sp) {
+      const T* q = part + (int64_t)sp * p.stride + (int64_t)c * p.ld + i0;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) acc[e] += p[e];
+      for (int e = 0; e < 4; ++e) acc[e] += q[e];
     }
   } else {
-    for (int sp = 0; sp < S; ++sp) {
-      const T* p = part + (int64_t)sp * stride + (int64_t)c * ld + i0;
+    for (int sp = 0; sp < p.S; ++sp) {
+      const T* q = part + (int64_t)sp * p.stride + (int64_t)c * p.ld + i0;
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        if (i0 + e < len) acc[e] += p[e];
+        if (i0 + e < p.len) acc[e] += q[e];
     }
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e)
-    if (i0 + e < ldo) out[(int64_t)c * ldo + i0 + e] = acc[e];
+    if (i0 + e < p.ldo) out[(int64_t)c * p.ldo + i0 + e] = acc[e];
 }
 
 hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
                                 int lp, int64_t len, void* out, int64_t ldo, hipStream_t s) {
   dim3 grid((unsigned)((ldo / 4 + 255) / 256), (unsigned)lp);
-  if (f64)
-    hipLaunchKernelGGL(splitk_reduce_kernel<double>, grid, dim3(256), 0, s, (const double*)part,
-                       stride, S, ld, len, (double*)out, ldo);
-  else
-    hipLaunchKernelGGL(splitk_reduce_kernel<float>, grid, dim3(256), 0, s, (const float*)part,
-                       stride, S, ld, len, (float*)out, ldo);
-  return hipGetLastError();
+  ReduceP p{part, stride, S, ld, len, out, ldo};
+  if (f64) return launch_k(splitk_reduce_kernel<double, false>, splitk_reduce_kernel<double, true>, grid, dim3(256), s, p);
+  return launch_k(splitk_reduce_kernel<float, false>, splitk_reduce_kernel<float, true>, grid, dim3(256), s, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,10 +206,23 @@ size_t gram_partial_elems(int64_t len, int lp) {
   return (size_t)gram_splits(len, lp) * npairs_of(nb) * 1024;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__ X, int64_t ld,
-                                                           int64_t len, int lp, int64_t kchunk,
-                                                           double* __restrict__ part) {
+struct GramP {
+  const void* X;
+  int64_t ld, len;
+  int lp;
+  int64_t kchunk;
+  double* part;
+  PBQ_GRID;
+};
+
+template <typename T, bool B>
+__global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, GramP ps) {
+  bool past;
+  const GramP prm = kparams<B>(pb, ps, past);
+  if (past) return;
+  const T* X = (const T*)prm.X;
+  const int64_t ld = prm.ld, len = prm.len;
+  const int lp = prm.lp;
   constexpr int VV = 16 / sizeof(T);
   const int p = blockIdx.x;
   int bj = 0;
@@ -194,7 +231,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int ti = wave >> 1, tj = wave & 1;
   const int rI = 32 * bi + 16 * ti + li, rJ = 32 * bj + 16 * tj + li;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk, ke = min(len, kb + kchunk);
+  const int64_t kb = (int64_t)blockIdx.y * prm.kchunk, ke = min(len, kb + prm.kchunk);
   const T* pI = X + (int64_t)rI * ld;
   const T* pJ = X + (int64_t)rJ * ld;
   const bool okI = rI < lp, okJ = rJ < lp;
@@ -224,36 +261,47 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const T* __restrict__
 #pragma unroll
     for (int e = 0; e < VV; ++e) acc1 = mma_f64((double)a1[e], (double)b1[e], acc1);
   }
-  double* out = part + ((int64_t)blockIdx.y * gridDim.x + p) * 1024;
+  double* out = prm.part + ((int64_t)blockIdx.y * prm.gx + p) * 1024;
 #pragma unroll
   for (int r = 0; r < 4; ++r)
     out[(16 * ti + acc_row<double>(lg, r)) * 32 + 16 * tj + li] = acc0[r] + acc1[r];
 }
 
-__global__ void gram_reduce_kernel(const double* __restrict__ part, int S, int np, int lp,
-                                   double* __restrict__ G, int64_t ldg) {
+struct GramReduceP {
+  const double* part;
+  int S, np, lp;
+  double* G;
+  int64_t ldg;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void gram_reduce_kernel(const GramReduceP* pb, GramReduceP ps) {
+  bool past;
+  const GramReduceP p = kparams<B>(pb, ps, past);
+  if (past) return;
   const int i = blockIdx.y;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= lp) return;
+  if (j >= p.lp) return;
   int bi = i >> 5, bj = j >> 5, ii = i & 31, jj = j & 31;
   if (bi > bj) {
     int t = bi; bi = bj; bj = t;
     t = ii; ii = jj; jj = t;
   }
-  const int p = bj * (bj + 1) / 2 + bi;
-  const double* src = part + (int64_t)p * 1024 + ii * 32 + jj;
-  const int64_t stride = (int64_t)np * 1024;
+  const int pr = bj * (bj + 1) / 2 + bi;
+  const double* src = p.part + (int64_t)pr * 1024 + ii * 32 + jj;
+  const int64_t stride = (int64_t)p.np * 1024;
   // four independent partial sums keep several loads in flight; the order is fixed
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   int sp = 0;
-  for (; sp + 4 <= S; sp += 4) {
+  for (; sp + 4 <= p.S; sp += 4) {
     s0 += src[(int64_t)(sp + 0) * stride];
     s1 += src[(int64_t)(sp + 1) * stride];
     s2 += src[(int64_t)(sp + 2) * stride];
     s3 += src[(int64_t)(sp + 3) * stride];
   }
-  for (; sp < S; ++sp) s0 += src[(int64_t)sp * stride];
-  G[(int64_t)i * ldg + j] = (s0 + s1) + (s2 + s3);
+  for (; sp < p.S; ++sp) s0 += src[(int64_t)sp * stride];
+  p.G[(int64_t)i * p.ldg + j] = (s0 + s1) + (s2 + s3);
 }
 
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
@@ -264,17 +312,13 @@ hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp,
   int64_t kchunk = (len + S - 1) / S;
   kchunk = (kchunk + 15) / 16 * 16;
   dim3 grid((unsigned)np, (unsigned)S);
-  if (f64)
-    hipLaunchKernelGGL(gram_partial_kernel<double>, grid, dim3(256), 0, s, (const double*)X, ld,
-                       len, lp, kchunk, part);
-  else
-    hipLaunchKernelGGL(gram_partial_kernel<float>, grid, dim3(256), 0, s, (const float*)X, ld, len,
-                       lp, kchunk, part);
-  hipError_t e = hipGetLastError();
+  GramP p{X, ld, len, lp, kchunk, part};
+  hipError_t e = f64 ? launch_k(gram_partial_kernel<double, false>, gram_partial_kernel<double, true>, grid, dim3(256), s, p)
+                     : launch_k(gram_partial_kernel<float, false>, gram_partial_kernel<float, true>, grid, dim3(256), s, p);
   if (e != hipSuccess) return e;
-  dim3 g2((unsigned)((lp + 63) / 64), (unsigned)lp);
-  hipLaunchKernelGGL(gram_reduce_kernel, g2, dim3(64), 0, s, part, S, np, lp, G, ldg);
-  return hipGetLastError();
+  GramReduceP r{part, S, np, lp, G, ldg};
+  return launch_k(gram_reduce_kernel<false>, gram_reduce_kernel<true>, dim3((unsigned)((lp + 63) / 64), (unsigned)lp),
+                  dim3(64), s, r);
 }
 
 // ---------------------------------------------------------------------------

@@ -57,6 +57,14 @@ class InfoStruct(ctypes.Structure):
 
 INFO_BYTES = ctypes.sizeof(InfoStruct)
 
+
+class ProblemStruct(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("k", ctypes.c_int), ("p", ctypes.c_int),
+                ("q", ctypes.c_int), ("seed", ctypes.c_uint64), ("Q", ctypes.c_void_p),
+                ("ldq", ctypes.c_int64), ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
+                ("P", ctypes.c_void_p), ("ldp", ctypes.c_int64), ("info", ctypes.c_void_p)]
+
 _LIB = None
 
 
@@ -88,6 +96,20 @@ def _lib():
         lib.pbpqlp_orth.argtypes = [vp, i64, i32, i64, i32, i32, vp, i64, dp, i64, vp, vp]
         lib.pbpqlp_small_qr.restype = i32
         lib.pbpqlp_small_qr.argtypes = [dp, i32, i64, dp, i64, dp, i64, vp, vp]
+        lib.pbpqlp_batch_create.restype = i32
+        lib.pbpqlp_batch_create.argtypes = [i32, ctypes.POINTER(ProblemStruct), i32,
+                                            ctypes.POINTER(Opts), ctypes.POINTER(vp)]
+        lib.pbpqlp_batch_run.restype = i32
+        lib.pbpqlp_batch_run.argtypes = [vp, vp]
+        lib.pbpqlp_batch_set_graph.restype = i32
+        lib.pbpqlp_batch_set_graph.argtypes = [vp, i32]
+        lib.pbpqlp_batch_stats.restype = i32
+        lib.pbpqlp_batch_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
+        lib.pbpqlp_batch_destroy.restype = None
+        lib.pbpqlp_batch_destroy.argtypes = [vp]
+        lib.pbpqlp_factor_batched.restype = i32
+        lib.pbpqlp_factor_batched.argtypes = [i32, ctypes.POINTER(ProblemStruct), i32,
+                                              ctypes.POINTER(Opts), vp]
         lib.pbpqlp_trace_enable.argtypes = [i32]
         lib.pbpqlp_trace_reset.argtypes = []
         lib.pbpqlp_trace_count.restype = i32
@@ -291,3 +313,74 @@ def trace_records():
                "pbpqlp_trace_get")
         out.append((buf.value.decode(), b.value, f.value, float(ms.value)))
     return out
+
+
+class Batch:
+    """A plan for factorizing many independent matrices (pbpqlp_batch_create).
+
+    ``mats`` is a list of 2-D device tensors of one dtype; ``ks``, ``ps``, ``qs``
+    and ``seeds`` give each problem's k, p, q and seed.  The plan allocates the
+    outputs (``Q[i]``, ``L[i]``, ``P[i]``) and one result record per problem;
+    ``run()`` factorizes all of them with one graph launch on the current stream.
+    The matrices must stay alive and in place while the plan is used.
+    """
+
+    def __init__(self, mats, ks, ps, qs, seeds, plan: str = "native", use_graph: bool = True):
+        if not mats:
+            raise ValueError("empty batch")
+        dtype = mats[0].dtype
+        self.device = mats[0].device
+        self.mats = [_rowmajor(a, "A") for a in mats]
+        if any(a.dtype != dtype for a in self.mats):
+            raise TypeError("all matrices of a batch must have one dtype")
+        cnt = len(self.mats)
+        self.count = cnt
+        self.ls = [int(k) + int(p) for k, p in zip(ks, ps)]
+        self.Q = [torch.empty((a.shape[0], l), dtype=dtype, device=self.device) for a, l in zip(self.mats, self.ls)]
+        self.P = [torch.empty((a.shape[1], l), dtype=dtype, device=self.device) for a, l in zip(self.mats, self.ls)]
+        self.L = [torch.empty((l, l), dtype=torch.float64, device=self.device) for l in self.ls]
+        self.info_buf = torch.zeros((cnt, INFO_BYTES), dtype=torch.uint8, device=self.device)
+        probs = (ProblemStruct * cnt)()
+        for i, a in enumerate(self.mats):
+            pr = probs[i]
+            pr.A = a.data_ptr(); pr.m = a.shape[0]; pr.n = a.shape[1]; pr.lda = a.stride(0)
+            pr.k = int(ks[i]); pr.p = int(ps[i]); pr.q = int(qs[i]); pr.seed = int(seeds[i])
+            pr.Q = self.Q[i].data_ptr(); pr.ldq = self.ls[i]
+            pr.L = self.L[i].data_ptr(); pr.ldl = self.ls[i]
+            pr.P = self.P[i].data_ptr(); pr.ldp = self.ls[i]
+            pr.info = self.info_buf[i].data_ptr()
+        opts = make_opts(plan)
+        handle = ctypes.c_void_p()
+        _check(_lib().pbpqlp_batch_create(cnt, probs, _dt(self.mats[0]), ctypes.byref(opts),
+                                          ctypes.byref(handle)), "pbpqlp_batch_create")
+        self._h = handle
+        if not use_graph:
+            _check(_lib().pbpqlp_batch_set_graph(self._h, 0), "pbpqlp_batch_set_graph")
+
+    def run(self):
+        _check(_lib().pbpqlp_batch_run(self._h, _stream(self.device)), "pbpqlp_batch_run")
+        return self
+
+    def use_graph(self, flag: bool):
+        _check(_lib().pbpqlp_batch_set_graph(self._h, 1 if flag else 0), "pbpqlp_batch_set_graph")
+
+    def stats(self):
+        n = ctypes.c_int(0)
+        ws = ctypes.c_size_t(0)
+        _check(_lib().pbpqlp_batch_stats(self._h, ctypes.byref(n), ctypes.byref(ws)), "pbpqlp_batch_stats")
+        return {"launches": n.value, "workspace_bytes": ws.value}
+
+    def info(self, i: int) -> "Info":
+        return Info.from_device(self.info_buf[i])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            _lib().pbpqlp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -82,3 +82,31 @@ def test_too_small_workspace_rejected():
     o.workspace = 0x10000
     o.workspace_bytes = 1024
     assert _factor(opts=ctypes.byref(o)) == B.ENOMEM
+
+
+def test_problem_struct_layout():
+    assert ctypes.sizeof(B.ProblemStruct) == 112
+
+
+def _problem(**kw):
+    pr = B.ProblemStruct()
+    pr.A = 0x1000; pr.m = 100; pr.n = 80; pr.lda = 80; pr.k = 5; pr.p = 3; pr.q = 1; pr.seed = 1
+    pr.Q = 0x2000; pr.ldq = 8; pr.L = 0x3000; pr.ldl = 8; pr.P = 0x4000; pr.ldp = 8; pr.info = None
+    for key, val in kw.items():
+        setattr(pr, key, val)
+    return pr
+
+
+@pytest.mark.parametrize("kw", [dict(k=0), dict(lda=79), dict(ldq=7), dict(q=17), dict(A=None)])
+def test_batch_rejects_bad_problems_before_allocating(kw):
+    lib = B.library()
+    probs = (B.ProblemStruct * 3)(_problem(), _problem(**kw), _problem())
+    h = ctypes.c_void_p()
+    assert lib.pbpqlp_batch_create(3, probs, B.F32, None, ctypes.byref(h)) == B.EINVAL
+    assert not h.value
+
+
+def test_batch_rejects_empty():
+    lib = B.library()
+    h = ctypes.c_void_p()
+    assert lib.pbpqlp_batch_create(0, None, B.F32, None, ctypes.byref(h)) == B.EINVAL
