@@ -9,8 +9,16 @@ whole factorization (sketch, 2q power passes with re-orthonormalization,
 projection, QR of B^T, QR of R^T, Q Qt) on the resident matrix.
 
     python bench.py [--steps K] [--warmup W] [--cpu-baseline full|none]
+    python bench.py --workload c4 [--steps K] [--warmup W]
 
 Prints one JSON line on stdout; progress goes to stderr.
+
+--workload c4 measures the batched form instead: 1024 FP32 matrices,
+m ~ U[256, 4096], n ~ U[256, 2048], rank r ~ U[8, 64] with sigma_i = exp(-i/r)
+plus 1e-5 N(0,1) (generated on the GPU from seeded generators, U and V from
+QR of Gaussian panels), k = r, p = 8, q = 1; one graph launch for the whole
+batch against one pbpqlp_factor call per matrix, with a sample of problems
+checked against the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -78,6 +86,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-baseline", choices=["full", "none"], default="full",
                     help="time the FP64 oracle on one factorization of the same matrix")
+    ap.add_argument("--workload", choices=["c2", "c4"], default="c2")
+    ap.add_argument("--plan", default="native", help="precision plan of the c4 batch")
+    ap.add_argument("--count", type=int, default=1024, help="c4 batch size")
+    ap.add_argument("--skip-per-matrix", action="store_true", help="c4: skip the per-matrix timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -99,6 +111,8 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     B.library()
+    if args.workload == "c4":
+        return bench_c4(args, torch, np, synth, B, dev)
 
     t = time.time()
     w = synth.config2()
@@ -203,6 +217,96 @@ def main():
         "speedup_mixed_vs_fp32": round(base["ms"] / flag["ms"], 3),
         "hbm_floor_ms": round(passes * m * n * 4 / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
         "algorithmic_tflop_per_factorization": flops / 1e12,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_c4(args, torch, np, synth, B, dev):
+    """Batched uneven sizes: one graph launch per batch vs one call per matrix."""
+    shapes = synth.config4_shapes(args.count)
+    t = time.time()
+    gen = torch.Generator(device=dev)
+    mats, ks, ps, qs, seeds = [], [], [], [], []
+    for b, (m, n, r) in enumerate(shapes):
+        gen.manual_seed(synth.seed_a(4, b))
+        U = torch.linalg.qr(torch.randn(m, r, generator=gen, device=dev, dtype=torch.float64))[0]
+        V = torch.linalg.qr(torch.randn(n, r, generator=gen, device=dev, dtype=torch.float64))[0]
+        sig = torch.exp(-torch.arange(1, r + 1, device=dev, dtype=torch.float64) / r)
+        A = (U * sig) @ V.T + 1e-5 * torch.randn(m, n, generator=gen, device=dev, dtype=torch.float64)
+        mats.append(A.float().contiguous())
+        ks.append(r); ps.append(8); qs.append(1); seeds.append(synth.seed_omega(4, b))
+    torch.cuda.synchronize()
+    log(f"generated {len(mats)} matrices on the GPU in {time.time() - t:.1f}s")
+    abytes = sum((2 * q + 2) * a.shape[0] * a.shape[1] * 4 for a, q in zip(mats, qs))
+
+    t = time.time()
+    bt = B.Batch(mats, ks, ps, qs, seeds, plan=args.plan)
+    torch.cuda.synchronize()
+    log(f"planned the batch in {time.time() - t:.1f}s: {bt.stats()}")
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    ms_batch = timed(bt.run, args.steps, args.warmup)
+    log(f"batched (graph): {ms_batch:.3f} ms per batch")
+    bt.use_graph(False)
+    ms_direct = timed(bt.run, max(1, args.steps // 2), 1)
+    bt.use_graph(True)
+    log(f"batched (grouped launches, no graph): {ms_direct:.3f} ms per batch")
+
+    # one pbpqlp_factor call per matrix with its own automatic plan
+    facs = [B.Factorizer(a.shape[0], a.shape[1], k, p, q, torch.float32, args.plan, dev)
+            for a, k, p, q in zip(mats, ks, ps, qs)]
+
+    def per_matrix():
+        for f, a, s_ in zip(facs, mats, seeds):
+            f(a, s_)
+
+    ms_single = None
+    if not args.skip_per_matrix:
+        ms_single = timed(per_matrix, max(1, args.steps // 4), 1)
+        log(f"per-matrix calls: {ms_single:.3f} ms per batch")
+
+    # sample against the FP64 oracle and against the per-matrix results
+    from oracle import pbpqlp as oracle_pbpqlp, rel_residual
+    bt.run()
+    torch.cuda.synchronize()
+    errs = []
+    for i in (0, len(mats) // 3, 2 * len(mats) // 3, len(mats) - 1):
+        A64 = mats[i].double().cpu().numpy()
+        ref = oracle_pbpqlp(A64, ks[i], ps[i], qs[i], seeds[i])
+        r_ref = rel_residual(A64, ref.Q, ref.L, ref.P)
+        r = rel_residual(A64, *(x.cpu().numpy().astype(np.float64) for x in (bt.Q[i], bt.L[i], bt.P[i])))
+        errs.append(abs(r - r_ref))
+        # pbpqlp_factor with the plan the batch chose reproduces it bit for bit
+        split_k, gram_wg = bt.problem_plan(i)
+        f1 = B.Factorizer(mats[i].shape[0], mats[i].shape[1], ks[i], ps[i], qs[i], torch.float32,
+                          args.plan, dev, split_k=split_k, gram_wg=gram_wg)
+        same = all(torch.equal(x, y) for x, y in zip((bt.Q[i], bt.L[i], bt.P[i]), f1(mats[i], seeds[i])))
+        if not same:
+            log(f"problem {i}: batched and per-matrix results differ")
+    line = {
+        "metric": "PbP-QLP batched factorizations: ms per batch of 1024 uneven FP32 matrices",
+        "value": round(ms_batch, 3), "unit": "ms/batch", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_batch, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.plan == "native" else "bf16",
+        "data": "synthetic",
+        "config": {"workload": f"{len(mats)} FP32 matrices m~U[256,4096] n~U[256,2048] r~U[8,64], "
+                               "sigma_i=exp(-i/r) + 1e-5 N(0,1), k=r p=8 q=1", "plan": args.plan},
+        "per_matrix_ms": round(ms_single, 3) if ms_single else None,
+        "grouped_no_graph_ms": round(ms_direct, 3),
+        "speedup_vs_per_matrix": round(ms_single / ms_batch, 2) if ms_single else None,
+        "launches_per_batch": bt.stats()["launches"],
+        "algorithmic_gb": abytes / 1e9, "achieved_gbs": round(abytes / (ms_batch * 1e-3) / 1e9, 1),
+        "hbm_frac": round(abytes / (ms_batch * 1e-3) / 8e12, 4),
+        "max_abs_dr_vs_fp64_oracle_sample": max(errs),
     }
     print(json.dumps(line), flush=True)
 

@@ -18,7 +18,8 @@
  *
  * Conventions for every entry point:
  *   - All matrix arguments are DEVICE pointers, row-major, with a leading
- *     dimension (elements between consecutive rows) >= the row length.
+ *     dimension (elements between consecutive rows) >= the row length, and
+ *     aligned to their element type (EINVAL otherwise).
  *   - The caller owns every buffer; the library never frees caller memory
  *     and keeps no pointer after the call returns.
  *   - Work is enqueued on `stream` (a hipStream_t passed as void*; NULL is
@@ -72,6 +73,8 @@ typedef struct {
   int power_prec;           /* the 2q passes of the power iterations              */
   int proj_prec;            /* pass B^T = A^T Q                                   */
   int split_k;              /* 0 = automatic; else forced split count of each pass */
+  int gram_workgroups;      /* 0 = automatic; else the workgroups each Gram aims at
+                               (contraction splits x column-block pairs)          */
   double fp16_scale_a;      /* power of two applied to A in FP16 passes (0 -> 1)  */
   void* workspace;          /* device memory owned by the caller, or NULL: then the
                                library allocates stream-ordered and frees it after */
@@ -198,10 +201,16 @@ pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbp
 /* Factorize every problem of the plan: one graph launch on `stream`
  * (asynchronous; results and records valid when the stream reaches it). */
 pbpqlp_status pbpqlp_batch_run(pbpqlp_batch* b, void* stream);
-/* Run the same grouped launches without the graph (1) or through it (default, 1). */
+/* Run the same grouped launches without the graph (0) or through it (1, default). */
 pbpqlp_status pbpqlp_batch_set_graph(pbpqlp_batch* b, int use_graph);
 /* Kernel launches per run and workspace bytes of a plan. */
 pbpqlp_status pbpqlp_batch_stats(const pbpqlp_batch* b, int* launches, size_t* workspace_bytes);
+/* The per-problem plan the batch chose for problem i (0 <= i < count): its
+ * contraction split count (always 1) and Gram workgroup target.  pbpqlp_factor
+ * called with these two values in opts launches the same kernels with the same
+ * parameters, so it gives the batch's results bit for bit.  EINVAL for a bad i. */
+pbpqlp_status pbpqlp_batch_problem_plan(const pbpqlp_batch* b, int i, int* split_k,
+                                        int* gram_workgroups);
 /* Release a plan (its work must be complete). */
 void pbpqlp_batch_destroy(pbpqlp_batch* b);
 /* create + run + synchronize `stream` + destroy. */

@@ -23,7 +23,6 @@ struct StreamArgs {
   int64_t chunk;        // contraction indices per split (multiple of 64)
   double* normA;        // per-block partial ||A||_F^2 (K1 only), or null
   float a_scale, out_scale;
-  int vec_ok;           // A rows are 16-byte aligned
 };
 
 hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s);
@@ -43,10 +42,11 @@ hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int
 hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
                                 int lp, int64_t len, void* out, int64_t ldo, hipStream_t s);
 // Gram partials and reduction: G (lp x lp, FP64, row-major, ldg) = X X^T over len
-int gram_splits(int64_t len, int lp);
-size_t gram_partial_elems(int64_t len, int lp);
+// `target`: workgroups to aim at (contraction splits x block pairs)
+int gram_splits(int64_t len, int lp, int target);
+size_t gram_partial_elems(int64_t len, int lp, int target);
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
-                       double* G, int64_t ldg, hipStream_t s);
+                       double* G, int64_t ldg, int target, hipStream_t s);
 // Cholesky of the Gram with dependent-column detection (single workgroup)
 hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,

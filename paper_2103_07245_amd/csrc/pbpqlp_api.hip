@@ -152,6 +152,7 @@ struct Ctx {
   int mode_sketch = 0, mode_power = 0, mode_proj = 0;
   float fp16_scale = 1.0f;
   int forced_split = 0;
+  int gram_target = 512;   // Gram workgroups to aim at (fewer per problem in a batch)
   uint64_t seed = 0;
   // splits: the sketch pass's grid sizes the ||A||_F^2 partials
   int k1_blocks = 0, k1_splits = 1;
@@ -206,8 +207,9 @@ struct Ctx {
     }
     part = b.take(part_bytes);
     normA = (double*)b.take((size_t)k1_blocks * k1_splits * sizeof(double));
-    size_t gp = gram_partial_elems(m, lp);
-    const size_t gpn = gram_partial_elems(n, lp), gps = gram_partial_elems(l, lp);
+    size_t gp = gram_partial_elems(m, lp, gram_target);
+    const size_t gpn = gram_partial_elems(n, lp, gram_target),
+                 gps = gram_partial_elems(l, lp, gram_target);
     if (gpn > gp) gp = gpn;
     if (gps > gp) gp = gps;
     gpart = (double*)b.take(gp * sizeof(double));
@@ -227,6 +229,9 @@ struct Ctx {
     rowsq = (double*)b.take((size_t)lp * sizeof(double));
   }
 };
+
+// Every matrix must be aligned to its element type.
+bool aligned(const void* p, size_t el) { return ((uintptr_t)p % el) == 0; }
 
 bool valid_args(int64_t m, int64_t n, int k, int p, int q) {
   if (m < 1 || n < 1 || k < 1 || p < 0 || q < 0 || q > 16) return false;
@@ -255,6 +260,8 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
   if (!ok1 || !ok2 || !ok3) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
   c.fp16_scale = (float)(o.fp16_scale_a > 0 ? o.fp16_scale_a : 1.0);
   c.forced_split = o.split_k;
+  if (o.split_k < 0 || o.gram_workgroups < 0) return PBPQLP_EINVAL;
+  if (o.gram_workgroups > 0) c.gram_target = o.gram_workgroups;
   c.plan_buffers(true, q > 0, q > 0, true);
   return PBPQLP_OK;
 }
@@ -289,7 +296,6 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
     a.Xlo = nullptr;
   }
   a.ldx = ldx;
-  a.vec_ok = (((uintptr_t)A & 15) == 0 && ((c.lda * (int64_t)c.el) & 15) == 0) ? 1 : 0;
   const Split sp = c.split_for(mode, trans);
   a.splits = sp.S;
   a.chunk = sp.chunk;
@@ -336,7 +342,7 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     const double el = f64 ? 8.0 : (double)c.el;
     {
       TraceScope ts("gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
-      PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, st));
+      PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, c.gram_target, st));
     }
     {
       TraceScope ts("chol", (double)c.l * c.l * 8 * 2, (double)c.l * c.l * c.l / 3.0, st);
@@ -455,9 +461,17 @@ struct pbpqlp_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int use_graph = 1;
+  std::vector<int> gram_wg;   // per problem
 };
 
 namespace {
+
+// Gram workgroups per problem in a batch: the problems already fill the chip
+// together, so each Gram splits only while the batch is small.
+int batch_gram_target(int count) {
+  const int t = (4096 + count - 1) / count;
+  return t < 512 ? t : 512;
+}
 
 void batch_free(pbpqlp_batch* b) {
   if (!b) return;
@@ -509,7 +523,8 @@ pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_d
                                     const pbpqlp_opts* opts, size_t* bytes) {
   if (!bytes) return PBPQLP_EINVAL;
   Ctx c;
-  pbpqlp_status s = setup(c, m, n, n, dt, k, p, 0, opts);
+  // sized for q >= 1: the power passes may split differently from the others
+  pbpqlp_status s = setup(c, m, n, n, dt, k, p, 1, opts);
   if (s) return s;
   Bump b;
   c.carve(b, needs16(c));
@@ -528,6 +543,8 @@ pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pb
   if (s) return s;
   if (ldq < c.l || ldl < c.l || ldp < c.l) return PBPQLP_EINVAL;
   if (Q == A || P == A || (const void*)L == A || Q == P) return PBPQLP_EINVAL;
+  if (!aligned(A, c.el) || !aligned(Q, c.el) || !aligned(P, c.el) || !aligned(L, 8))
+    return PBPQLP_EINVAL;
   c.seed = seed;
   hipStream_t st = (hipStream_t)stream;
   const bool n16 = needs16(c);
@@ -570,6 +587,10 @@ pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int6
                             double fp16_scale_a, void* Y, int64_t ldy, void* stream) {
   if (!A || !X || !Y || l < 1 || m < 1 || n < 1 || lda < n || ldx < l || ldy < l)
     return PBPQLP_EINVAL;
+  {
+    const size_t el = dt == PBPQLP_F64 ? 8 : 4;
+    if (!aligned(A, el) || !aligned(X, el) || !aligned(Y, el)) return PBPQLP_EINVAL;
+  }
   if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
   pbpqlp_opts o;
   pbpqlp_default_opts(&o);
@@ -639,7 +660,7 @@ pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpql
     Xt = b.take((size_t)c.lp32 * c.ldm * c.el);
     Out = b.take((size_t)c.lp32 * c.ldm * c.el);
     Tmp = b.take((size_t)c.lp32 * c.ldm * c.el);
-    c.gpart = (double*)b.take(gram_partial_elems(rows, c.lp) * 8);
+    c.gpart = (double*)b.take(gram_partial_elems(rows, c.lp, c.gram_target) * 8);
     c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
     c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
     c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
@@ -683,7 +704,7 @@ pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, i
     c.Rfin = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
     c.M1 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
     c.Qt64 = (double*)b.take((size_t)c.lp32 * c.ldS * 8);
-    c.gpart = (double*)b.take(gram_partial_elems(l, c.lp) * 8);
+    c.gpart = (double*)b.take(gram_partial_elems(l, c.lp, c.gram_target) * 8);
     c.G = (double*)b.take((size_t)c.lp * c.lp * 8);
     c.R1 = (double*)b.take((size_t)c.lp * c.lp * 8);
     c.R2 = (double*)b.take((size_t)c.lp * c.lp * 8);
@@ -762,7 +783,11 @@ pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbp
     if (s) return s;
     if (pr.ldq < c.l || pr.ldl < c.l || pr.ldp < c.l) return PBPQLP_EINVAL;
     if (pr.Q == pr.A || pr.P == pr.A || pr.Q == pr.P) return PBPQLP_EINVAL;
+    if (!aligned(pr.A, c.el) || !aligned(pr.Q, c.el) || !aligned(pr.P, c.el) ||
+        !aligned(pr.L, 8))
+      return PBPQLP_EINVAL;
     c.seed = pr.seed;
+    if (o.gram_workgroups == 0) c.gram_target = batch_gram_target(count);
     Bump sizer;
     c.carve(sizer, needs16(c));
     sizer.take(sizeof(pbpqlp_info));
@@ -771,6 +796,7 @@ pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbp
   }
   pbpqlp_batch* b = new pbpqlp_batch();
   b->count = count;
+  for (const Ctx& c : ctx) b->gram_wg.push_back(c.gram_target);
   b->ws_bytes = total;
   if (hipMalloc(&b->ws, total > 0 ? total : 256) != hipSuccess) {
     batch_free(b);
@@ -879,6 +905,14 @@ pbpqlp_status pbpqlp_batch_stats(const pbpqlp_batch* b, int* launches, size_t* w
   if (!b) return PBPQLP_EINVAL;
   if (launches) *launches = (int)b->groups.size();
   if (workspace_bytes) *workspace_bytes = b->ws_bytes;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_batch_problem_plan(const pbpqlp_batch* b, int i, int* split_k,
+                                        int* gram_workgroups) {
+  if (!b || i < 0 || i >= b->count) return PBPQLP_EINVAL;
+  if (split_k) *split_k = 1;
+  if (gram_workgroups) *gram_workgroups = b->gram_wg[(size_t)i];
   return PBPQLP_OK;
 }
 

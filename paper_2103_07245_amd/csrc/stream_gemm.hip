@@ -63,6 +63,11 @@ constexpr int kPitch = 128 + 16;  // LDS bytes per X column, padded against bank
 constexpr int kGroup = 4;         // X column tiles per scheduling group
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// The same vectors at element alignment: rows of A need only be aligned to
+// their element type (the matrix cores' global loads take dword-aligned
+// multi-dword addresses).
+typedef u32x4 u32x4_e __attribute__((aligned(4)));
+typedef u32x2 u32x2_e __attribute__((aligned(4)));
 
 __device__ __forceinline__ float u2f(uint32_t x) { return __uint_as_float(x); }
 
@@ -168,8 +173,10 @@ struct StreamParams {
 // BF16X3 whose extra operands need 512 registers per lane).  Wave w owns the
 // A-side tiles (rows for K1, columns for K2) 16 RT (NW blockIdx.x + w) .. + 16 RT.
 // Eight waves make two per SIMD (one block per CU) and share one X stage.
-// VEC: A rows are 16-byte aligned (K1) / lda and n are multiples of RT (K2),
-// so full stages use vector loads; otherwise every load is masked.
+// Full stages load A with element-aligned vector loads; only the ragged last
+// stage of a split masks its loads.  K2 with n % RT != 0 (VEC = false): the
+// lane holding the last, unpaired column loads the pair that ends there and
+// moves that column into its first slot (one select per load).
 // ---------------------------------------------------------------------------
 template <int MODE, int NT, bool TRANS, bool VEC, bool B>
 __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void stream_kernel(const StreamParams* pb,
@@ -205,7 +212,8 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
   const int64_t kb = (int64_t)blockIdx.y * p.chunk;
   const int64_t ke = min(TRANS ? p.m : p.n, kb + p.chunk);
   const int nst = (int)((ke - kb + KC - 1) / KC);
-  const int nfull = (int)((ke - kb) / KC);
+  // K2 needs RT columns for its paired loads; a narrower A runs masked only
+  const int nfull = (TRANS && alen < RT) ? 0 : (int)((ke - kb) / KC);
 
   // Clamped A-side indices (always valid memory); validity kept for normA.
   int64_t arow[RT];  // K1: row of sub-tile rt
@@ -216,8 +224,16 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
     rowok[rt] = r < alen;
     arow[rt] = rowok[rt] ? r : alen - 1;
   }
-  int64_t acol = a0 + li * RT;  // K2: first of RT consecutive columns
-  if (TRANS && VEC && acol + RT > alen) acol = alen - RT;
+  // K2: this lane's RT consecutive columns start at acol; its loads start at
+  // acol_ld = min(acol, alen - RT) so that a pair never leaves the row, and
+  // sh marks the lane whose first column is the last, unpaired one (odd n)
+  int64_t acol_ld = a0 + li * RT;
+  bool sh = false;
+  if (TRANS && acol_ld + RT > alen) {
+    const int64_t c = alen > RT ? alen - RT : 0;
+    sh = !VEC && RT == 2 && c + 1 == acol_ld;
+    acol_ld = c;
+  }
 
   ACC acc[RT][NT];
 #pragma unroll
@@ -265,8 +281,8 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
             const int64_t k = k0 + st * KS + lg * V + h * EA;
             const TA* src = A + arow[rt] * p.lda + k;
             u32x4& d = an[(rt * 2 + st) * NLA + h];
-            if (VEC && full) {
-              d = ld16(src);
+            if (full) {
+              d = *(const u32x4_e*)src;
             } else {
               union { u32x4 v; TA e[EA]; } u;
 #pragma unroll
@@ -281,14 +297,16 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
         for (int e = 0; e < V; ++e) {
           const int64_t i = k0 + st * KS + lg * V + e;
           u32x2& d = at[st * V + e];
-          if (VEC && full) {
-            d = *(const u32x2*)(A + i * p.lda + acol);
+          if (full) {
+            d = *(const u32x2_e*)(A + i * p.lda + acol_ld);
+            if (sh) d.x = d.y;
           } else {
             union { u32x2 v; TA e2[RT]; } u;
 #pragma unroll
             for (int t = 0; t < RT; ++t)
-              u.e2[t] = (i < ke && acol + t < alen) ? A[i * p.lda + acol + t] : TA(0);
+              u.e2[t] = (i < ke && acol_ld + t < alen) ? A[i * p.lda + acol_ld + t] : TA(0);
             d = u.v;
+            if (sh) d.x = d.y;
           }
         }
     }
@@ -445,11 +463,13 @@ static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   p.out = a.out; p.ldo = a.ldo; p.split_stride = a.split_stride; p.chunk = a.chunk;
   p.normA = TRANS ? nullptr : a.normA;
   p.a_scale = a.a_scale; p.out_scale = a.out_scale;
-  if (vec)
+  if (vec || !TRANS)
     return launch_k(stream_kernel<MODE, NT, TRANS, true, false>, stream_kernel<MODE, NT, TRANS, true, true>,
                     grid, dim3(64 * TR::NW), s, p);
-  return launch_k(stream_kernel<MODE, NT, TRANS, false, false>, stream_kernel<MODE, NT, TRANS, false, true>,
-                  grid, dim3(64 * TR::NW), s, p);
+  if constexpr (TRANS)
+    return launch_k(stream_kernel<MODE, NT, TRANS, false, false>, stream_kernel<MODE, NT, TRANS, false, true>,
+                    grid, dim3(64 * TR::NW), s, p);
+  return hipErrorInvalidValue;
 }
 
 template <int MODE, bool TRANS>
@@ -470,12 +490,9 @@ static hipError_t dispatch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
 template <int MODE>
 static hipError_t dispatch_dir(bool trans, const StreamArgs& a, hipStream_t s) {
   typedef Tr<MODE> TR;
-  const int el = (int)sizeof(typename TR::TA);
-  bool vec;
-  if (!trans)
-    vec = (((uintptr_t)a.A & 15) == 0) && ((a.lda * el) % 16 == 0);
-  else
-    vec = (((uintptr_t)a.A & 7) == 0) && (a.lda % TR::RT == 0) && (a.n % TR::RT == 0);
+  if (((uintptr_t)a.A % sizeof(typename TR::TA)) != 0) return hipErrorInvalidValue;
+  // K2 pairs columns: an odd last column takes the shifted-pair path
+  const bool vec = !trans || a.n % TR::RT == 0;
   return trans ? dispatch_nt<MODE, true>(a, vec, s) : dispatch_nt<MODE, false>(a, vec, s);
 }
 

@@ -191,19 +191,19 @@ hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int 
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int npairs_of(int nb) { return nb * (nb + 1) / 2; }
 
-int gram_splits(int64_t len, int lp) {
+int gram_splits(int64_t len, int lp, int target) {
   const int nb = (lp + 31) / 32;
   const int np = npairs_of(nb);
-  int64_t S = (512 + np - 1) / np;               // aim at ~512 workgroups
+  int64_t S = (target + np - 1) / np;            // aim at ~target workgroups
   const int64_t maxS = (len + 255) / 256;        // at least 256 rows per split
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
   return (int)S;
 }
 
-size_t gram_partial_elems(int64_t len, int lp) {
+size_t gram_partial_elems(int64_t len, int lp, int target) {
   const int nb = (lp + 31) / 32;
-  return (size_t)gram_splits(len, lp) * npairs_of(nb) * 1024;
+  return (size_t)gram_splits(len, lp, target) * npairs_of(nb) * 1024;
 }
 
 struct GramP {
@@ -305,10 +305,10 @@ __global__ void gram_reduce_kernel(const GramReduceP* pb, GramReduceP ps) {
 }
 
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
-                       double* G, int64_t ldg, hipStream_t s) {
+                       double* G, int64_t ldg, int target, hipStream_t s) {
   const int nb = (lp + 31) / 32;
   const int np = npairs_of(nb);
-  const int S = gram_splits(len, lp);
+  const int S = gram_splits(len, lp, target);
   int64_t kchunk = (len + S - 1) / S;
   kchunk = (kchunk + 15) / 16 * 16;
   dim3 grid((unsigned)np, (unsigned)S);

@@ -44,7 +44,7 @@ class PbpqlpError(RuntimeError):
 class Opts(ctypes.Structure):
     _fields_ = [("sketch_prec", ctypes.c_int), ("power_prec", ctypes.c_int),
                 ("proj_prec", ctypes.c_int), ("split_k", ctypes.c_int),
-                ("fp16_scale_a", ctypes.c_double), ("workspace", ctypes.c_void_p),
+                ("gram_workgroups", ctypes.c_int), ("fp16_scale_a", ctypes.c_double), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
@@ -105,6 +105,8 @@ def _lib():
         lib.pbpqlp_batch_set_graph.argtypes = [vp, i32]
         lib.pbpqlp_batch_stats.restype = i32
         lib.pbpqlp_batch_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_size_t)]
+        lib.pbpqlp_batch_problem_plan.restype = i32
+        lib.pbpqlp_batch_problem_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.pbpqlp_batch_destroy.restype = None
         lib.pbpqlp_batch_destroy.argtypes = [vp]
         lib.pbpqlp_factor_batched.restype = i32
@@ -152,13 +154,15 @@ def _rowmajor(t: torch.Tensor, name: str) -> torch.Tensor:
     return t
 
 
-def make_opts(plan="native", split_k: int = 0, fp16_scale_a: float = 1.0) -> Opts:
+def make_opts(plan="native", split_k: int = 0, fp16_scale_a: float = 1.0,
+              gram_wg: int = 0) -> Opts:
     if isinstance(plan, str):
         plan = PLANS[plan]
     o = Opts()
     _lib().pbpqlp_default_opts(ctypes.byref(o))
     o.sketch_prec, o.power_prec, o.proj_prec = (PREC[x] for x in plan)
     o.split_k = split_k
+    o.gram_workgroups = gram_wg
     o.fp16_scale_a = fp16_scale_a
     return o
 
@@ -181,9 +185,10 @@ class Info:
                     s.resid_rel_est)
 
 
-def workspace_size(m: int, n: int, k: int, p: int, dtype=torch.float32, plan="native") -> int:
+def workspace_size(m: int, n: int, k: int, p: int, dtype=torch.float32, plan="native",
+                   opts: Opts = None) -> int:
     sz = ctypes.c_size_t(0)
-    o = make_opts(plan)
+    o = make_opts(plan) if opts is None else opts
     _check(_lib().pbpqlp_workspace_size(m, n, k, p, F64 if dtype == torch.float64 else F32,
                                         ctypes.byref(o), ctypes.byref(sz)), "pbpqlp_workspace_size")
     return int(sz.value)
@@ -194,13 +199,14 @@ class Factorizer:
     outputs and the device info record so repeated calls allocate nothing."""
 
     def __init__(self, m: int, n: int, k: int, p: int, q: int, dtype=torch.float32,
-                 plan="native", device="cuda", split_k: int = 0, fp16_scale_a: float = 1.0):
+                 plan="native", device="cuda", split_k: int = 0, fp16_scale_a: float = 1.0,
+                 gram_wg: int = 0):
         self.m, self.n, self.k, self.p, self.q = m, n, k, p, q
         self.l = k + p
         self.dtype = dtype
         self.device = torch.device(device)
-        self.opts = make_opts(plan, split_k, fp16_scale_a)
-        ws = workspace_size(m, n, k, p, dtype, plan)
+        self.opts = make_opts(plan, split_k, fp16_scale_a, gram_wg)
+        ws = workspace_size(m, n, k, p, dtype, plan, self.opts)
         self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
         self.opts.workspace = self.workspace.data_ptr()
         self.opts.workspace_bytes = self.workspace.numel()
@@ -227,11 +233,13 @@ class Factorizer:
 
 
 def factor(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", split_k: int = 0,
-           fp16_scale_a: float = 1.0) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor, Info]:
+           fp16_scale_a: float = 1.0,
+           gram_wg: int = 0) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor, Info]:
     """PbP-QLP of a device matrix A (m x n, float32/float64): returns
     (Q, L, P, info) with A ~= Q @ L.T @ P.T."""
     A = _rowmajor(A, "A")
-    f = Factorizer(A.shape[0], A.shape[1], k, p, q, A.dtype, plan, A.device, split_k, fp16_scale_a)
+    f = Factorizer(A.shape[0], A.shape[1], k, p, q, A.dtype, plan, A.device, split_k, fp16_scale_a,
+                   gram_wg)
     Q, L, P = f(A, seed)
     return Q, L, P, f.info()
 
@@ -325,7 +333,8 @@ class Batch:
     The matrices must stay alive and in place while the plan is used.
     """
 
-    def __init__(self, mats, ks, ps, qs, seeds, plan: str = "native", use_graph: bool = True):
+    def __init__(self, mats, ks, ps, qs, seeds, plan: str = "native", use_graph: bool = True,
+                 gram_wg: int = 0):
         if not mats:
             raise ValueError("empty batch")
         dtype = mats[0].dtype
@@ -349,7 +358,7 @@ class Batch:
             pr.L = self.L[i].data_ptr(); pr.ldl = self.ls[i]
             pr.P = self.P[i].data_ptr(); pr.ldp = self.ls[i]
             pr.info = self.info_buf[i].data_ptr()
-        opts = make_opts(plan)
+        opts = make_opts(plan, gram_wg=gram_wg)
         handle = ctypes.c_void_p()
         _check(_lib().pbpqlp_batch_create(cnt, probs, _dt(self.mats[0]), ctypes.byref(opts),
                                           ctypes.byref(handle)), "pbpqlp_batch_create")
@@ -369,6 +378,15 @@ class Batch:
         ws = ctypes.c_size_t(0)
         _check(_lib().pbpqlp_batch_stats(self._h, ctypes.byref(n), ctypes.byref(ws)), "pbpqlp_batch_stats")
         return {"launches": n.value, "workspace_bytes": ws.value}
+
+    def problem_plan(self, i: int):
+        """(split_k, gram_wg) the plan uses for problem i: factor() with these
+        options reproduces that problem's results bit for bit."""
+        sk = ctypes.c_int(0)
+        gw = ctypes.c_int(0)
+        _check(_lib().pbpqlp_batch_problem_plan(self._h, i, ctypes.byref(sk), ctypes.byref(gw)),
+               "pbpqlp_batch_problem_plan")
+        return sk.value, gw.value
 
     def info(self, i: int) -> "Info":
         return Info.from_device(self.info_buf[i])

@@ -35,7 +35,7 @@ def test_version_and_status_strings():
 
 def test_info_struct_layout():
     assert ctypes.sizeof(B.InfoStruct) == 56
-    assert ctypes.sizeof(B.Opts) == 40
+    assert ctypes.sizeof(B.Opts) == 48
 
 
 FAKE = ctypes.c_void_p(0x1000)

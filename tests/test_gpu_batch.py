@@ -2,8 +2,9 @@
 problems in one plan.
 
 Each problem of a batch runs exactly the kernels and parameters of
-pbpqlp_factor with one contraction split (the batch runs every pass unsplit),
-so its outputs must equal that single call's bit for bit: with and without the
+pbpqlp_factor with the per-problem plan the batch reports (one contraction
+split, the batch's Gram workgroup target), so its outputs must equal that
+single call's bit for bit: with and without the
 graph, on repeated runs of one plan, across shape classes (different tile
 counts, aligned and unaligned rows) and across launch-sequence classes
 (different q).  Against the FP64 oracle the usual FP32 tolerance applies.
@@ -46,8 +47,10 @@ def _batch(members, plan="native", use_graph=True):
     return bt, mats
 
 
-def _single(At, k, p, q, seed, plan="native"):
-    return B.factor(At, k, p, q, seed, plan=plan, split_k=1)
+def _single(bt, i, At, k, p, q, seed, plan="native"):
+    """pbpqlp_factor with the plan the batch chose for problem i."""
+    split_k, gram_wg = bt.problem_plan(i)
+    return B.factor(At, k, p, q, seed, plan=plan, split_k=split_k, gram_wg=gram_wg)
 
 
 @pytest.fixture(scope="module")
@@ -62,7 +65,7 @@ def test_batch_equals_single_calls_bitwise(members, plan):
     bt.run()
     torch.cuda.synchronize()
     for i, (A, k, p, q, seed) in enumerate(members):
-        Q, L, P, info = _single(mats[i], k, p, q, seed, plan=plan)
+        Q, L, P, info = _single(bt, i, mats[i], k, p, q, seed, plan=plan)
         torch.cuda.synchronize()
         assert torch.equal(bt.Q[i], Q), i
         assert torch.equal(bt.L[i], L), i
@@ -125,7 +128,7 @@ def test_fp64_batch_and_padded_rows():
     bt.run()
     torch.cuda.synchronize()
     for i in range(len(shapes)):
-        Q, L, P, _ = _single(mats[i], ks[i], ps[i], qs[i], seeds[i])
+        Q, L, P, _ = _single(bt, i, mats[i], ks[i], ps[i], qs[i], seeds[i])
         torch.cuda.synchronize()
         assert torch.equal(bt.Q[i], Q) and torch.equal(bt.L[i], L) and torch.equal(bt.P[i], P), i
         A64 = mats[i].cpu().numpy()

@@ -116,6 +116,26 @@ def test_streaming_product_padded_lda_and_fp16_scale():
     assert np.linalg.norm(Y16 - ref16) <= 1e-5 * np.linalg.norm(ref16)
 
 
+@pytest.mark.parametrize("m,n,l", [(600, 1, 1), (700, 3, 2), (650, 65, 9), (333, 130, 40)])
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("prec", ["native", "bf16", "bf16x3"])
+def test_streaming_product_odd_rows(m, n, l, trans, prec):
+    """Rows aligned only to 4 bytes (odd padding) and narrow or odd-width A:
+    full stages with element-aligned vector loads, the shifted column pair of
+    an odd last column (A^T X), and A narrower than one column pair."""
+    print(f"matmul odd rows m={m} n={n} l={l} trans={trans} prec={prec}", flush=True)
+    rng = synth.rng_for(m + 11 * n + 101 * l)
+    big = rng.standard_normal((m, n + 1)).astype(np.float32)
+    A = _dev(big)[:, :n]                      # lda = n + 1
+    X = rng.standard_normal((m if trans else n, l)).astype(np.float32)
+    Y = _host(B.matmul(A, _dev(X), trans=trans, prec=prec))
+    A64 = big[:, :n].astype(np.float64)
+    ref = _ref_product(A64, X.astype(np.float64), trans, prec)
+    K = (m if trans else n) * (3 if prec == "bf16x3" else 1)
+    absprod = np.abs(A64.T if trans else A64) @ np.abs(X).astype(np.float64)
+    assert np.all(np.abs(Y - ref) <= 1.01 * K * 2.0 ** -24 * absprod + 1e-30)
+
+
 def _signed_qr(Y):
     return householder_qr(Y)
 
