@@ -217,6 +217,108 @@ void pbpqlp_batch_destroy(pbpqlp_batch* b);
 pbpqlp_status pbpqlp_factor_batched(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
                                     const pbpqlp_opts* opts, void* stream);
 
+/* ---- learned choice of q and k (project extension; the paper has none) ----
+ *
+ * A q = 0 probe with l = 64 gives L whose diagonal tracks the leading singular
+ * values of A (Section III-A, eq. (Ahat), and the diagonal bounds of Theorems
+ * 3-5).  Its 64 features
+ *     f_i = clip(ln(L_ii / L_11) / ln(1e6), -1, 1)   (-1 where the ratio is not
+ *           above 1e-6, not finite, or L_11 <= 0)
+ * feed an FP32 network 64 -> 128 (ReLU) -> 128 (ReLU) -> 6 whose outputs are
+ * five logits for the power-iteration count q in {0..4} (Section III-B,
+ * Algorithm 1) and a regression output for ln k.
+ *
+ * Parameters are one FP32 vector of PBPQLP_MLP_PARAMS values in the order
+ * W1 (128 x 64, row-major: row j holds the weights into hidden unit j), b1 (128),
+ * W2 (128 x 128), b2 (128), W3 (6 x 128), b3 (6).  Training minimizes, over a
+ * batch of B samples, the mean softmax cross-entropy of the five logits
+ * against the label q* plus the mean of (output_6 - ln k*)^2, with Adam
+ * (Kingma and Ba 2015, beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected). */
+#define PBPQLP_MLP_IN 64
+#define PBPQLP_MLP_HIDDEN 128
+#define PBPQLP_MLP_OUT 6
+#define PBPQLP_MLP_PARAMS 25606
+#define PBPQLP_PROBE_K 56          /* probe: k = 56, p = 8, q = 0 (l = 64) */
+#define PBPQLP_PROBE_P 8
+
+typedef struct pbpqlp_model pbpqlp_model;   /* device parameters + Adam state */
+
+/* New model with the given parameters (host array of PBPQLP_MLP_PARAMS
+ * floats; NULL = all zero) and zero Adam state.  Allocates device memory.
+ * Errors: EINVAL (out NULL), ENOMEM, EHIP. */
+pbpqlp_status pbpqlp_model_create(const float* h_params, pbpqlp_model** out);
+/* Load a model file written by pbpqlp_model_save (parameters, Adam moments and
+ * step count: training resumes where it stopped).  Errors: EINVAL if the file
+ * cannot be read or is not a model file of these dimensions; ENOMEM; EHIP. */
+pbpqlp_status pbpqlp_model_load(const char* path, pbpqlp_model** out);
+/* Write the model (synchronizes with the device).  File layout, little-endian:
+ * 8-byte magic "PBQMLP01", int32 in, hidden, out, int32 reserved (0), int64
+ * Adam step count, then parameters, first moments and second moments, each
+ * PBPQLP_MLP_PARAMS float32.  Errors: EINVAL (cannot write), EHIP. */
+pbpqlp_status pbpqlp_model_save(const pbpqlp_model* model, const char* path);
+/* Copy the parameters to a host array of PBPQLP_MLP_PARAMS floats (synchronous). */
+pbpqlp_status pbpqlp_model_get_params(const pbpqlp_model* model, float* h_params);
+/* Adam steps taken so far. */
+int64_t pbpqlp_model_steps(const pbpqlp_model* model);
+/* Release a model (no work may still use it). */
+void pbpqlp_model_free(pbpqlp_model* model);
+
+/* Probe features from the diagonal of L (device, FP64, row-major, ldl >= 64,
+ * at least 64 x 64) into f (device, 64 floats).  Errors: EINVAL. */
+pbpqlp_status pbpqlp_probe_features(const double* L, int64_t ldl, float* f, void* stream);
+
+/* Network outputs for `batch` feature rows: X (device, batch x 64 FP32,
+ * row-major, ldx >= 64) -> Z (device, batch x 6 FP32, row-major, ldz >= 6).
+ * Errors: EINVAL (batch < 1, bad leading dimensions, NULL). */
+pbpqlp_status pbpqlp_mlp_forward(const pbpqlp_model* model, const float* X, int64_t ldx, int batch,
+                                 float* Z, int64_t ldz, void* stream);
+/* Loss of a batch and its gradient.  X as above; q (device, batch int32 in
+ * 0..4), logk (device, batch floats).  Writes the loss to d_loss (device, one
+ * float, may be NULL) and the gradient (PBPQLP_MLP_PARAMS floats, the same
+ * order as the parameters) to the model's gradient buffer and, if d_grad is
+ * not NULL, to d_grad (device).  The model's activation buffers grow to the
+ * largest batch seen (device allocation, synchronous).  Calls on one model
+ * must not overlap.  Errors: EINVAL, ENOMEM, EHIP. */
+pbpqlp_status pbpqlp_mlp_loss_grad(pbpqlp_model* model, const float* X, int64_t ldx,
+                                   const int* q, const float* logk, int batch, float* d_loss,
+                                   float* d_grad, void* stream);
+/* One Adam step on the gradient held in the model (from the last
+ * pbpqlp_mlp_loss_grad), learning rate lr > 0.  Errors: EINVAL, EHIP. */
+pbpqlp_status pbpqlp_mlp_adam_step(pbpqlp_model* model, float lr, void* stream);
+/* pbpqlp_mlp_loss_grad followed by pbpqlp_mlp_adam_step. */
+pbpqlp_status pbpqlp_mlp_train_step(pbpqlp_model* model, const float* X, int64_t ldx,
+                                    const int* q, const float* logk, int batch, float lr,
+                                    float* d_loss, void* stream);
+
+/* What pbpqlp_factor_auto chose and measured (host struct). */
+typedef struct {
+  int q_pred, k_pred;        /* the network's choice                                  */
+  int q_used, k_used;        /* what the returned factorization used                  */
+  int fell_back;             /* 1: the first residual was above tau, rerun with q = 3 */
+  int reserved;
+  double resid_first;        /* resid_rel_est of the predicted run                    */
+  double resid_final;        /* resid_rel_est of the returned run                     */
+} pbpqlp_auto_result;
+
+/* Learned factorization: probe (k = 56, p = 8, q = 0) -> features -> network ->
+ * q_hat = argmax of the logits (lowest index on ties), k_hat = exp(output_6)
+ * rounded to the nearest integer and clamped to [1, k_max] -> pbpqlp_factor
+ * with (q_hat, k_hat, p) -> if its resid_rel_est exceeds tau (or a non-finite
+ * input was flagged) the fallback pbpqlp_factor with (q = 3, k_hat, p).
+ *   A, dt, lda, seed, opts as for pbpqlp_factor (seed also drives the probe);
+ *   requires min(m, n) >= 64 and k_max + p <= min(m, n), k_max + p <= 256.
+ *   Q (m x (k_used + p)), L, P (n x (k_used + p)) are written as pbpqlp_factor
+ *   writes them, so ldq, ldl, ldp must be >= k_max + p.
+ * Synchronizes `stream` twice (to read the prediction and the residual), so
+ * it cannot be captured in a graph.  The probe's buffers are allocated and
+ * freed stream-ordered.  Errors: as pbpqlp_factor, and EINVAL for a NULL
+ * model, tau <= 0 or bad k_max. */
+pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* model, const void* A, int64_t m, int64_t n,
+                                 int64_t lda, pbpqlp_dtype dt, int p, uint64_t seed, int k_max,
+                                 double tau, void* Q, int64_t ldq, double* L, int64_t ldl,
+                                 void* P, int64_t ldp, const pbpqlp_opts* opts,
+                                 pbpqlp_info* d_info, pbpqlp_auto_result* result, void* stream);
+
 /* ---- instrumentation (benchmarking and profiling) ----
  * With level >= 1, every later call records a pair of HIP events on its
  * stream around each A-streaming product; with level >= 2 also around the

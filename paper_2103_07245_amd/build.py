@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbpqlp.so")
 
-SOURCES = ["stream_gemm.hip", "tallskinny.hip", "small.hip", "apply.hip", "pbpqlp_api.hip"]
+SOURCES = ["stream_gemm.hip", "tallskinny.hip", "small.hip", "apply.hip", "pbpqlp_api.hip",
+           "learned.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

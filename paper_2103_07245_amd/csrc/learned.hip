@@ -1,0 +1,565 @@
+// Learned choice of the power-iteration count q and the rank k (a project
+// extension; the paper has no learned part).
+//
+// A q = 0 probe with l = 64 yields L whose diagonal tracks the leading singular
+// values of A (Section III-A, eq. (Ahat); Theorems 3-5 bound the diagonal of L
+// by the singular values).  Its normalized log-ratios feed a small FP32
+// network 64 -> 128 -> 128 -> 6 (five logits for q in 0..4, one output for
+// ln k).  Everything the network does runs in the kernels below: features,
+// forward pass (tiled GEMM with fused bias and ReLU), softmax cross-entropy
+// plus squared-error head, backward pass, Adam, and a fused one-sample
+// inference kernel used by pbpqlp_factor_auto.
+//
+// The layers are tiny (at most 128 x 128 weights, batches of a few hundred to
+// a few thousand rows): every kernel here is latency-bound, so they use plain
+// FP32 FMAs in a fixed summation order (deterministic, and the one-sample
+// inference kernel reproduces the batched forward pass bit for bit) rather
+// than matrix-core tiles.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/pbpqlp.h"
+
+namespace {
+
+constexpr int NI = PBPQLP_MLP_IN, NH = PBPQLP_MLP_HIDDEN, NO = PBPQLP_MLP_OUT, NQ = 5;
+constexpr int NP = PBPQLP_MLP_PARAMS;
+constexpr int OW1 = 0, OB1 = OW1 + NH * NI, OW2 = OB1 + NH, OB2 = OW2 + NH * NH, OW3 = OB2 + NH,
+              OB3 = OW3 + NO * NH;
+static_assert(OB3 + NO == NP, "parameter layout");
+constexpr double kFloor = 1e-6;   // smallest L_ii / L_11 the features resolve
+constexpr float kLambdaK = 1.0f;  // weight of the ln k head
+
+#define PBQ_TRY(expr)                         \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return PBPQLP_EHIP; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Probe features: f_i = clip(ln(L_ii / L_11) / ln(1 / floor), -1, 1), -1 for a
+// ratio not above the floor (or not finite, or L_11 <= 0).  64 threads.
+// ---------------------------------------------------------------------------
+__global__ void features_kernel(const double* __restrict__ L, int64_t ldl, float* __restrict__ f) {
+  const int i = threadIdx.x;
+  const double d0 = L[0];
+  float out = -1.0f;
+  if (d0 > 0.0 && isfinite(d0)) {
+    const double t = L[(int64_t)i * ldl + i] / d0;
+    if (isfinite(t) && t > kFloor) out = (float)fmin(log(t) / log(1.0 / kFloor), 1.0);
+  }
+  f[i] = out;
+}
+
+// ---------------------------------------------------------------------------
+// C (M x N) = sum_k A(m, k) B(k, n) with A(m, k) = A[m ars + k acs] and
+// B(k, n) = B[k brs + n bcs], then an epilogue:
+//   EPI_NONE  C = acc
+//   EPI_BIAS  C = acc + bias[n]            (EPI_RELU: then max(., 0))
+//   EPI_MASK  C = acc where H[m ldh + n] > 0, else 0   (ReLU derivative)
+// 32 x 32 tiles staged through LDS, 256 threads with 4 outputs each; the sum
+// over k runs in increasing k for every output.
+// ---------------------------------------------------------------------------
+enum { EPI_NONE = 0, EPI_BIAS = 1, EPI_RELU = 2, EPI_MASK = 3 };
+
+struct MmArgs {
+  const float* A;
+  int64_t ars, acs;
+  const float* B;
+  int64_t brs, bcs;
+  float* C;
+  int64_t ldc;
+  int M, N, K;
+  const float* bias;
+  const float* H;
+  int64_t ldh;
+};
+
+template <int EPI>
+__global__ __launch_bounds__(256) void mm_kernel(MmArgs g) {
+  __shared__ float As[32][33];
+  __shared__ float Bs[32][33];
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  const int m0 = blockIdx.y * 32, n0 = blockIdx.x * 32;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = tid + 256 * j;
+      // the faster-varying tile index follows the unit-stride operand dimension
+      const int am = g.acs == 1 ? e >> 5 : e & 31, ak = g.acs == 1 ? e & 31 : e >> 5;
+      const int gm = m0 + am, gk = k0 + ak;
+      As[am][ak] = (gm < g.M && gk < g.K) ? g.A[gm * g.ars + gk * g.acs] : 0.f;
+      const int bn = g.bcs == 1 ? e & 31 : e >> 5, bk = g.bcs == 1 ? e >> 5 : e & 31;
+      const int gn = n0 + bn, gk2 = k0 + bk;
+      Bs[bk][bn] = (gn < g.N && gk2 < g.K) ? g.B[gk2 * g.brs + gn * g.bcs] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < 32; ++kk) {
+      const float b = Bs[kk][tx];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = fmaf(As[ty + 8 * r][kk], b, acc[r]);
+    }
+    __syncthreads();
+  }
+  const int n = n0 + tx;
+  if (n >= g.N) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int m = m0 + ty + 8 * r;
+    if (m >= g.M) continue;
+    float v = acc[r];
+    if (EPI == EPI_BIAS || EPI == EPI_RELU) v = v + g.bias[n];
+    if (EPI == EPI_RELU) v = fmaxf(v, 0.f);
+    if (EPI == EPI_MASK) v = g.H[m * g.ldh + n] > 0.f ? v : 0.f;
+    g.C[m * g.ldc + n] = v;
+  }
+}
+
+template <int EPI>
+hipError_t mm(const MmArgs& g, hipStream_t s) {
+  dim3 grid((unsigned)((g.N + 31) / 32), (unsigned)((g.M + 31) / 32));
+  hipLaunchKernelGGL(mm_kernel<EPI>, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+// Column sums of D (rows x cols, ld), summed in increasing row order.
+__global__ void colsum_kernel(const float* __restrict__ D, int64_t ld, int rows, int cols,
+                              float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += D[(int64_t)r * ld + c];
+  out[c] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Loss of a batch and d loss / d Z:
+//   loss = (1/B) sum_b [ lse(z_b[0..4]) - z_b[q_b] + lambda (z_b[5] - logk_b)^2 ]
+//   dZ_b[c] = (softmax(z_b)[c] - [c == q_b]) / B,  dZ_b[5] = 2 lambda (z_b[5] - logk_b) / B
+// One block of 256 threads; per-thread partial sums, then a fixed-order tree.
+// q outside 0..4 is clamped into range.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ Z, int64_t ldz,
+                                                   const int* __restrict__ q,
+                                                   const float* __restrict__ logk, int B,
+                                                   float* __restrict__ dZ, int64_t lddz,
+                                                   float* __restrict__ loss) {
+  __shared__ float red[256];
+  const int tid = threadIdx.x;
+  const float invB = 1.0f / (float)B;
+  float acc = 0.f;
+  for (int b = tid; b < B; b += 256) {
+    const float* z = Z + (int64_t)b * ldz;
+    float mx = z[0];
+#pragma unroll
+    for (int c = 1; c < NQ; ++c) mx = fmaxf(mx, z[c]);
+    float e[NQ], se = 0.f;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) {
+      e[c] = expf(z[c] - mx);
+      se += e[c];
+    }
+    int qb = q[b];
+    qb = qb < 0 ? 0 : (qb >= NQ ? NQ - 1 : qb);
+    const float err = z[NQ] - logk[b];
+    acc += (mx + logf(se) - z[qb]) + kLambdaK * err * err;
+    float* d = dZ + (int64_t)b * lddz;
+#pragma unroll
+    for (int c = 0; c < NQ; ++c) d[c] = (e[c] / se - (c == qb ? 1.f : 0.f)) * invB;
+    d[NQ] = 2.f * kLambdaK * err * invB;
+  }
+  red[tid] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0 && loss) loss[0] = red[0] * invB;
+}
+
+// Adam with bias correction; c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+__global__ void adam_kernel(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m,
+                            float* __restrict__ v, int n, float lr, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + 1e-8f);
+}
+
+// One sample through the whole network (128 threads).  Every dot product runs
+// in increasing index order and adds its bias last, exactly as mm_kernel does,
+// so the result equals the batched forward pass bit for bit.
+__global__ __launch_bounds__(128) void infer_kernel(const float* __restrict__ th,
+                                                    const float* __restrict__ f,
+                                                    float* __restrict__ z) {
+  __shared__ float fs[NI], h1[NH], h2[NH];
+  const int t = threadIdx.x;
+  if (t < NI) fs[t] = f[t];
+  __syncthreads();
+  {
+    const float* w = th + OW1 + t * NI;
+    float a = 0.f;
+    for (int i = 0; i < NI; ++i) a = fmaf(fs[i], w[i], a);
+    h1[t] = fmaxf(a + th[OB1 + t], 0.f);
+  }
+  __syncthreads();
+  {
+    const float* w = th + OW2 + t * NH;
+    float a = 0.f;
+    for (int i = 0; i < NH; ++i) a = fmaf(h1[i], w[i], a);
+    h2[t] = fmaxf(a + th[OB2 + t], 0.f);
+  }
+  __syncthreads();
+  if (t < NO) {
+    const float* w = th + OW3 + t * NH;
+    float a = 0.f;
+    for (int i = 0; i < NH; ++i) a = fmaf(h2[i], w[i], a);
+    z[t] = a + th[OB3 + t];
+  }
+}
+
+// Forward pass of `batch` rows: H1 = relu(X W1^T + b1), H2 = relu(H1 W2^T + b2),
+// Z = H2 W3^T + b3.  H1, H2 are batch x NH (ld NH).
+hipError_t forward_pass(const float* th, const float* X, int64_t ldx, int batch, float* H1,
+                        float* H2, float* Z, int64_t ldz, hipStream_t s) {
+  MmArgs g{};
+  g.A = X; g.ars = ldx; g.acs = 1;
+  g.B = th + OW1; g.brs = 1; g.bcs = NI;        // B(k, n) = W1[n, k]
+  g.C = H1; g.ldc = NH; g.M = batch; g.N = NH; g.K = NI; g.bias = th + OB1;
+  hipError_t e = mm<EPI_RELU>(g, s);
+  if (e != hipSuccess) return e;
+  g.A = H1; g.ars = NH;
+  g.B = th + OW2; g.bcs = NH;
+  g.C = H2; g.N = NH; g.K = NH; g.bias = th + OB2;
+  e = mm<EPI_RELU>(g, s);
+  if (e != hipSuccess) return e;
+  g.A = H2;
+  g.B = th + OW3;
+  g.C = Z; g.ldc = ldz; g.N = NO; g.K = NH; g.bias = th + OB3;
+  return mm<EPI_BIAS>(g, s);
+}
+
+// dW (nout x nin) = dY^T X, db = column sums of dY, and (if dX) dX = (dY W) * [H > 0].
+hipError_t layer_backward(const float* dY, int64_t lddy, int batch, int nout, const float* X,
+                          int64_t ldx, int nin, const float* W, float* dW, float* db, float* dX,
+                          int64_t lddx, const float* H, hipStream_t s) {
+  MmArgs g{};
+  g.A = dY; g.ars = 1; g.acs = lddy;             // A(m = j, k = b) = dY[b, j]
+  g.B = X; g.brs = ldx; g.bcs = 1;               // B(k = b, n = i) = X[b, i]
+  g.C = dW; g.ldc = nin; g.M = nout; g.N = nin; g.K = batch;
+  hipError_t e = mm<EPI_NONE>(g, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(colsum_kernel, dim3((unsigned)((nout + 127) / 128)), dim3(128), 0, s, dY, lddy,
+                     batch, nout, db);
+  e = hipGetLastError();
+  if (e != hipSuccess || !dX) return e;
+  MmArgs h{};
+  h.A = dY; h.ars = lddy; h.acs = 1;
+  h.B = W; h.brs = nin; h.bcs = 1;               // B(k = j, n = i) = W[j, i]
+  h.C = dX; h.ldc = lddx; h.M = batch; h.N = nin; h.K = nout;
+  h.H = H; h.ldh = nin;
+  return mm<EPI_MASK>(h, s);
+}
+
+}  // namespace
+
+struct pbpqlp_model {
+  float* buf = nullptr;      // theta | grad | m | v, NP floats each
+  int64_t t = 0;             // Adam steps taken
+  float* act = nullptr;      // activations of the largest batch seen
+  int cap = 0;
+  float* theta() const { return buf; }
+  float* grad() const { return buf + NP; }
+  float* mom1() const { return buf + 2 * (size_t)NP; }
+  float* mom2() const { return buf + 3 * (size_t)NP; }
+};
+
+namespace {
+
+// Per-sample activation floats of a training step: H1, H2, Z, dZ, dH2, dH1.
+constexpr int kActPerRow = NH + NH + NO + NO + NH + NH;
+
+pbpqlp_status ensure_act(pbpqlp_model* md, int batch) {
+  if (batch <= md->cap) return PBPQLP_OK;
+  if (md->act) {
+    if (hipDeviceSynchronize() != hipSuccess) return PBPQLP_EHIP;
+    (void)hipFree(md->act);
+    md->act = nullptr;
+    md->cap = 0;
+  }
+  if (hipMalloc(&md->act, (size_t)batch * kActPerRow * sizeof(float)) != hipSuccess) return PBPQLP_ENOMEM;
+  md->cap = batch;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status new_model(pbpqlp_model** out) {
+  pbpqlp_model* md = new pbpqlp_model();
+  if (hipMalloc(&md->buf, 4 * (size_t)NP * sizeof(float)) != hipSuccess) {
+    delete md;
+    return PBPQLP_ENOMEM;
+  }
+  if (hipMemset(md->buf, 0, 4 * (size_t)NP * sizeof(float)) != hipSuccess) {
+    (void)hipFree(md->buf);
+    delete md;
+    return PBPQLP_EHIP;
+  }
+  *out = md;
+  return PBPQLP_OK;
+}
+
+const char kMagic[8] = {'P', 'B', 'Q', 'M', 'L', 'P', '0', '1'};
+
+}  // namespace
+
+extern "C" {
+
+pbpqlp_status pbpqlp_model_create(const float* h_params, pbpqlp_model** out) {
+  if (!out) return PBPQLP_EINVAL;
+  *out = nullptr;
+  pbpqlp_model* md = nullptr;
+  pbpqlp_status s = new_model(&md);
+  if (s) return s;
+  if (h_params && hipMemcpy(md->theta(), h_params, (size_t)NP * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+    pbpqlp_model_free(md);
+    return PBPQLP_EHIP;
+  }
+  *out = md;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_model_load(const char* path, pbpqlp_model** out) {
+  if (!path || !out) return PBPQLP_EINVAL;
+  *out = nullptr;
+  FILE* fp = std::fopen(path, "rb");
+  if (!fp) return PBPQLP_EINVAL;
+  char magic[8];
+  int32_t dims[4];
+  int64_t t = 0;
+  std::vector<float> host(3 * (size_t)NP);
+  const bool ok = std::fread(magic, 1, 8, fp) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+                  std::fread(dims, 4, 4, fp) == 4 && dims[0] == NI && dims[1] == NH && dims[2] == NO &&
+                  std::fread(&t, 8, 1, fp) == 1 && t >= 0 &&
+                  std::fread(host.data(), 4, host.size(), fp) == host.size();
+  std::fclose(fp);
+  if (!ok) return PBPQLP_EINVAL;
+  pbpqlp_model* md = nullptr;
+  pbpqlp_status s = new_model(&md);
+  if (s) return s;
+  // file order: theta, m, v; device order: theta, grad, m, v
+  if (hipMemcpy(md->theta(), host.data(), (size_t)NP * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(md->mom1(), host.data() + NP, 2 * (size_t)NP * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    pbpqlp_model_free(md);
+    return PBPQLP_EHIP;
+  }
+  md->t = t;
+  *out = md;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_model_save(const pbpqlp_model* md, const char* path) {
+  if (!md || !path) return PBPQLP_EINVAL;
+  std::vector<float> host(3 * (size_t)NP);
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(host.data(), md->theta(), (size_t)NP * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(host.data() + NP, md->mom1(), 2 * (size_t)NP * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return PBPQLP_EHIP;
+  FILE* fp = std::fopen(path, "wb");
+  if (!fp) return PBPQLP_EINVAL;
+  const int32_t dims[4] = {NI, NH, NO, 0};
+  const bool ok = std::fwrite(kMagic, 1, 8, fp) == 8 && std::fwrite(dims, 4, 4, fp) == 4 &&
+                  std::fwrite(&md->t, 8, 1, fp) == 1 &&
+                  std::fwrite(host.data(), 4, host.size(), fp) == host.size();
+  const bool closed = std::fclose(fp) == 0;
+  return ok && closed ? PBPQLP_OK : PBPQLP_EINVAL;
+}
+
+pbpqlp_status pbpqlp_model_get_params(const pbpqlp_model* md, float* h_params) {
+  if (!md || !h_params) return PBPQLP_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess ||
+      hipMemcpy(h_params, md->theta(), (size_t)NP * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return PBPQLP_EHIP;
+  return PBPQLP_OK;
+}
+
+int64_t pbpqlp_model_steps(const pbpqlp_model* md) { return md ? md->t : 0; }
+
+void pbpqlp_model_free(pbpqlp_model* md) {
+  if (!md) return;
+  if (md->act) (void)hipFree(md->act);
+  if (md->buf) (void)hipFree(md->buf);
+  delete md;
+}
+
+pbpqlp_status pbpqlp_probe_features(const double* L, int64_t ldl, float* f, void* stream) {
+  if (!L || !f || ldl < NI) return PBPQLP_EINVAL;
+  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NI), 0, (hipStream_t)stream, L, ldl, f);
+  return hipGetLastError() == hipSuccess ? PBPQLP_OK : PBPQLP_EHIP;
+}
+
+pbpqlp_status pbpqlp_mlp_forward(const pbpqlp_model* md, const float* X, int64_t ldx, int batch,
+                                 float* Z, int64_t ldz, void* stream) {
+  if (!md || !X || !Z || batch < 1 || ldx < NI || ldz < NO) return PBPQLP_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  float* H = nullptr;
+  if (hipMallocAsync((void**)&H, (size_t)batch * 2 * NH * sizeof(float), st) != hipSuccess) return PBPQLP_ENOMEM;
+  const hipError_t e = forward_pass(md->theta(), X, ldx, batch, H, H + (size_t)batch * NH, Z, ldz, st);
+  (void)hipFreeAsync(H, st);
+  return e == hipSuccess ? PBPQLP_OK : PBPQLP_EHIP;
+}
+
+pbpqlp_status pbpqlp_mlp_loss_grad(pbpqlp_model* md, const float* X, int64_t ldx, const int* q,
+                                   const float* logk, int batch, float* d_loss, float* d_grad,
+                                   void* stream) {
+  if (!md || !X || !q || !logk || batch < 1 || ldx < NI) return PBPQLP_EINVAL;
+  pbpqlp_status s = ensure_act(md, batch);
+  if (s) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t B = (size_t)batch;
+  float* H1 = md->act;
+  float* H2 = H1 + B * NH;
+  float* Z = H2 + B * NH;
+  float* dZ = Z + B * NO;
+  float* dH2 = dZ + B * NO;
+  float* dH1 = dH2 + B * NH;
+  float* th = md->theta();
+  float* g = md->grad();
+  PBQ_TRY(forward_pass(th, X, ldx, batch, H1, H2, Z, NO, st));
+  hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, st, Z, (int64_t)NO, q, logk, batch, dZ,
+                     (int64_t)NO, d_loss);
+  PBQ_TRY(hipGetLastError());
+  // layer 3: Z = H2 W3^T + b3
+  PBQ_TRY(layer_backward(dZ, NO, batch, NO, H2, NH, NH, th + OW3, g + OW3, g + OB3, dH2, NH, H2, st));
+  // layer 2: H2 = relu(H1 W2^T + b2)
+  PBQ_TRY(layer_backward(dH2, NH, batch, NH, H1, NH, NH, th + OW2, g + OW2, g + OB2, dH1, NH, H1, st));
+  // layer 1: H1 = relu(X W1^T + b1); no gradient for the input
+  PBQ_TRY(layer_backward(dH1, NH, batch, NH, X, ldx, NI, th + OW1, g + OW1, g + OB1, nullptr, 0,
+                         nullptr, st));
+  if (d_grad) PBQ_TRY(hipMemcpyAsync(d_grad, g, (size_t)NP * 4, hipMemcpyDeviceToDevice, st));
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_mlp_adam_step(pbpqlp_model* md, float lr, void* stream) {
+  if (!md || !(lr > 0.f)) return PBPQLP_EINVAL;
+  md->t += 1;
+  const double c1 = 1.0 / (1.0 - std::pow(0.9, (double)md->t));
+  const double c2 = 1.0 / (1.0 - std::pow(0.999, (double)md->t));
+  hipLaunchKernelGGL(adam_kernel, dim3((NP + 255) / 256), dim3(256), 0, (hipStream_t)stream, md->theta(),
+                     md->grad(), md->mom1(), md->mom2(), NP, lr, (float)c1, (float)c2);
+  return hipGetLastError() == hipSuccess ? PBPQLP_OK : PBPQLP_EHIP;
+}
+
+pbpqlp_status pbpqlp_mlp_train_step(pbpqlp_model* md, const float* X, int64_t ldx, const int* q,
+                                    const float* logk, int batch, float lr, float* d_loss,
+                                    void* stream) {
+  if (!(lr > 0.f)) return PBPQLP_EINVAL;
+  pbpqlp_status s = pbpqlp_mlp_loss_grad(md, X, ldx, q, logk, batch, d_loss, nullptr, stream);
+  if (s) return s;
+  return pbpqlp_mlp_adam_step(md, lr, stream);
+}
+
+pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t m, int64_t n,
+                                 int64_t lda, pbpqlp_dtype dt, int p, uint64_t seed, int k_max,
+                                 double tau, void* Q, int64_t ldq, double* L, int64_t ldl,
+                                 void* P, int64_t ldp, const pbpqlp_opts* opts,
+                                 pbpqlp_info* d_info, pbpqlp_auto_result* result, void* stream) {
+  if (!md || !A || !Q || !L || !P || !(tau > 0.0) || p < 0 || k_max < 1) return PBPQLP_EINVAL;
+  if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
+  const int64_t mn = m < n ? m : n;
+  const int lprobe = PBPQLP_PROBE_K + PBPQLP_PROBE_P;
+  const int lmax = k_max + p;
+  if (mn < lprobe || lmax > mn || ldq < lmax || ldl < lmax || ldp < lmax) return PBPQLP_EINVAL;
+  if (lmax > 256) return PBPQLP_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  pbpqlp_opts o;
+  pbpqlp_default_opts(&o);
+  if (opts) o = *opts;
+  o.workspace = nullptr;        // every call below sizes its own workspace
+  o.workspace_bytes = 0;
+  const size_t el = dt == PBPQLP_F64 ? 8 : 4;
+  // probe outputs, features, network outputs and a result record
+  const size_t szQ = (size_t)m * lprobe * el, szP = (size_t)n * lprobe * el;
+  const size_t szL = (size_t)lprobe * lprobe * 8;
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t total = up(szQ) + up(szP) + up(szL) + up(NI * 4) + up(NO * 4) + up(sizeof(pbpqlp_info));
+  char* scratch = nullptr;
+  if (hipMallocAsync((void**)&scratch, total, st) != hipSuccess) return PBPQLP_ENOMEM;
+  struct Free {
+    char* p;
+    hipStream_t s;
+    ~Free() { (void)hipFreeAsync(p, s); }
+  } guard{scratch, st};
+  char* c = scratch;
+  void* Qp = c; c += up(szQ);
+  void* Pp = c; c += up(szP);
+  double* Lp = (double*)c; c += up(szL);
+  float* f = (float*)c; c += up(NI * 4);
+  float* z = (float*)c; c += up(NO * 4);
+  pbpqlp_info* own = (pbpqlp_info*)c;
+  pbpqlp_info* info = d_info ? d_info : own;
+
+  pbpqlp_status s = pbpqlp_factor(A, m, n, lda, dt, PBPQLP_PROBE_K, PBPQLP_PROBE_P, 0, seed, Qp, lprobe,
+                                  Lp, lprobe, Pp, lprobe, &o, own, stream);
+  if (s) return s;
+  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NI), 0, st, (const double*)Lp, (int64_t)lprobe, f);
+  PBQ_TRY(hipGetLastError());
+  hipLaunchKernelGGL(infer_kernel, dim3(1), dim3(NH), 0, st, (const float*)md->theta(), (const float*)f, z);
+  PBQ_TRY(hipGetLastError());
+  float hz[NO];
+  PBQ_TRY(hipMemcpyAsync(hz, z, sizeof(hz), hipMemcpyDeviceToHost, st));
+  PBQ_TRY(hipStreamSynchronize(st));
+  bool finite = true;
+  for (int i = 0; i < NO; ++i) finite = finite && std::isfinite(hz[i]);
+  int qh = 3, kh = k_max;
+  if (finite) {
+    qh = 0;
+    for (int i = 1; i < NQ; ++i)
+      if (hz[i] > hz[qh]) qh = i;
+    const double kr = std::floor(std::exp(std::fmin((double)hz[NQ], 30.0)) + 0.5);
+    kh = kr < 1.0 ? 1 : (kr > (double)k_max ? k_max : (int)kr);
+  }
+  pbpqlp_auto_result r{};
+  r.q_pred = qh;
+  r.k_pred = kh;
+  auto run = [&](int qq, double* resid, int* flags) -> pbpqlp_status {
+    pbpqlp_status s2 = pbpqlp_factor(A, m, n, lda, dt, kh, p, qq, seed, Q, ldq, L, ldl, P, ldp, &o, info, stream);
+    if (s2) return s2;
+    pbpqlp_info hi;
+    PBQ_TRY(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, st));
+    PBQ_TRY(hipStreamSynchronize(st));
+    *resid = hi.resid_rel_est;
+    *flags = hi.status_flags;
+    return PBPQLP_OK;
+  };
+  double r1 = 0.0;
+  int fl1 = 0;
+  s = run(qh, &r1, &fl1);
+  if (s) return s;
+  r.resid_first = r1;
+  r.resid_final = r1;
+  r.q_used = qh;
+  r.k_used = kh;
+  const bool bad = !(r1 <= tau) || (fl1 & PBPQLP_FLAG_NONFINITE);
+  if (bad && qh < 3) {
+    double r2 = 0.0;
+    int fl2 = 0;
+    s = run(3, &r2, &fl2);
+    if (s) return s;
+    r.fell_back = 1;
+    r.q_used = 3;
+    r.resid_final = r2;
+  }
+  if (result) *result = r;
+  return PBPQLP_OK;
+}
+
+}  // extern "C"

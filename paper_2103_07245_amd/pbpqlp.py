@@ -13,6 +13,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Tuple
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,6 +66,16 @@ class ProblemStruct(ctypes.Structure):
                 ("ldq", ctypes.c_int64), ("L", ctypes.c_void_p), ("ldl", ctypes.c_int64),
                 ("P", ctypes.c_void_p), ("ldp", ctypes.c_int64), ("info", ctypes.c_void_p)]
 
+
+class AutoResult(ctypes.Structure):
+    _fields_ = [("q_pred", ctypes.c_int), ("k_pred", ctypes.c_int), ("q_used", ctypes.c_int),
+                ("k_used", ctypes.c_int), ("fell_back", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("resid_first", ctypes.c_double), ("resid_final", ctypes.c_double)]
+
+
+MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 64, 128, 6, 25606
+PROBE_K, PROBE_P = 56, 8
+
 _LIB = None
 
 
@@ -112,6 +123,33 @@ def _lib():
         lib.pbpqlp_factor_batched.restype = i32
         lib.pbpqlp_factor_batched.argtypes = [i32, ctypes.POINTER(ProblemStruct), i32,
                                               ctypes.POINTER(Opts), vp]
+        f32 = ctypes.c_float
+        lib.pbpqlp_model_create.restype = i32
+        lib.pbpqlp_model_create.argtypes = [vp, ctypes.POINTER(vp)]
+        lib.pbpqlp_model_load.restype = i32
+        lib.pbpqlp_model_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(vp)]
+        lib.pbpqlp_model_save.restype = i32
+        lib.pbpqlp_model_save.argtypes = [vp, ctypes.c_char_p]
+        lib.pbpqlp_model_get_params.restype = i32
+        lib.pbpqlp_model_get_params.argtypes = [vp, vp]
+        lib.pbpqlp_model_steps.restype = i64
+        lib.pbpqlp_model_steps.argtypes = [vp]
+        lib.pbpqlp_model_free.restype = None
+        lib.pbpqlp_model_free.argtypes = [vp]
+        lib.pbpqlp_probe_features.restype = i32
+        lib.pbpqlp_probe_features.argtypes = [vp, i64, vp, vp]
+        lib.pbpqlp_mlp_forward.restype = i32
+        lib.pbpqlp_mlp_forward.argtypes = [vp, vp, i64, i32, vp, i64, vp]
+        lib.pbpqlp_mlp_loss_grad.restype = i32
+        lib.pbpqlp_mlp_loss_grad.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp]
+        lib.pbpqlp_mlp_adam_step.restype = i32
+        lib.pbpqlp_mlp_adam_step.argtypes = [vp, f32, vp]
+        lib.pbpqlp_mlp_train_step.restype = i32
+        lib.pbpqlp_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, i32, f32, vp, vp]
+        lib.pbpqlp_factor_auto.restype = i32
+        lib.pbpqlp_factor_auto.argtypes = [vp, vp, i64, i64, i64, i32, i32, u64, i32, ctypes.c_double,
+                                           vp, i64, dp, i64, vp, i64, ctypes.POINTER(Opts), vp,
+                                           ctypes.POINTER(AutoResult), vp]
         lib.pbpqlp_trace_enable.argtypes = [i32]
         lib.pbpqlp_trace_reset.argtypes = []
         lib.pbpqlp_trace_count.restype = i32
@@ -402,3 +440,149 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Learned choice of q and k
+# ---------------------------------------------------------------------------
+def _f32dev(x, device, name):
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(np.asarray(x, dtype=np.float32))
+    x = x.to(device=device, dtype=torch.float32)
+    if x.dim() != 2 or x.shape[1] != MLP_IN:
+        raise ValueError(f"{name} must be batch x {MLP_IN}")
+    return x.contiguous()
+
+
+class Model:
+    """The q/k network on the device (pbpqlp_model): parameters, gradient and
+    Adam state.  ``params`` is a host array of 25606 floats (None = zeros)."""
+
+    def __init__(self, params=None, device="cuda", _handle=None):
+        self.device = torch.device(device)
+        if _handle is not None:
+            self._h = _handle
+            return
+        h = ctypes.c_void_p()
+        buf = None
+        if params is not None:
+            buf = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+            if buf.shape != (MLP_PARAMS,):
+                raise ValueError(f"expected {MLP_PARAMS} parameters")
+        _check(_lib().pbpqlp_model_create(None if buf is None else buf.ctypes.data, ctypes.byref(h)),
+               "pbpqlp_model_create")
+        self._h = h
+
+    @classmethod
+    def load(cls, path, device="cuda"):
+        h = ctypes.c_void_p()
+        _check(_lib().pbpqlp_model_load(os.fsencode(path), ctypes.byref(h)), "pbpqlp_model_load")
+        return cls(device=device, _handle=h)
+
+    def save(self, path):
+        _check(_lib().pbpqlp_model_save(self._h, os.fsencode(path)), "pbpqlp_model_save")
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_PARAMS, dtype=np.float32)
+        _check(_lib().pbpqlp_model_get_params(self._h, out.ctypes.data), "pbpqlp_model_get_params")
+        return out
+
+    @property
+    def steps(self) -> int:
+        return int(_lib().pbpqlp_model_steps(self._h))
+
+    def forward(self, X) -> torch.Tensor:
+        X = _f32dev(X, self.device, "X")
+        Z = torch.empty((X.shape[0], MLP_OUT), dtype=torch.float32, device=self.device)
+        _check(_lib().pbpqlp_mlp_forward(self._h, ctypes.c_void_p(X.data_ptr()), MLP_IN, X.shape[0],
+                                         ctypes.c_void_p(Z.data_ptr()), MLP_OUT, _stream(self.device)),
+               "pbpqlp_mlp_forward")
+        return Z
+
+    def _labels(self, X, q, logk):
+        X = _f32dev(X, self.device, "X")
+        q = torch.as_tensor(q).to(device=self.device, dtype=torch.int32).contiguous()
+        logk = torch.as_tensor(logk).to(device=self.device, dtype=torch.float32).contiguous()
+        if q.shape != (X.shape[0],) or logk.shape != (X.shape[0],):
+            raise ValueError("one label per row")
+        return X, q, logk
+
+    def loss_grad(self, X, q, logk):
+        """(loss, gradient) of a batch; the gradient also stays in the model
+        for adam_step()."""
+        X, q, logk = self._labels(X, q, logk)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        g = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        _check(_lib().pbpqlp_mlp_loss_grad(self._h, ctypes.c_void_p(X.data_ptr()), MLP_IN,
+                                           ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(logk.data_ptr()),
+                                           X.shape[0], ctypes.c_void_p(loss.data_ptr()),
+                                           ctypes.c_void_p(g.data_ptr()), _stream(self.device)),
+               "pbpqlp_mlp_loss_grad")
+        return loss, g
+
+    def adam_step(self, lr: float):
+        _check(_lib().pbpqlp_mlp_adam_step(self._h, float(lr), _stream(self.device)), "pbpqlp_mlp_adam_step")
+
+    def train_step(self, X, q, logk, lr: float) -> torch.Tensor:
+        X, q, logk = self._labels(X, q, logk)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(_lib().pbpqlp_mlp_train_step(self._h, ctypes.c_void_p(X.data_ptr()), MLP_IN,
+                                            ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(logk.data_ptr()),
+                                            X.shape[0], float(lr), ctypes.c_void_p(loss.data_ptr()),
+                                            _stream(self.device)), "pbpqlp_mlp_train_step")
+        return loss
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            _lib().pbpqlp_model_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def probe_features(L: torch.Tensor) -> torch.Tensor:
+    """Features (64 floats) from the diagonal of a probe's L (64 x 64 FP64)."""
+    if L.dtype != torch.float64 or L.dim() != 2 or L.shape[0] < MLP_IN or L.shape[1] < MLP_IN:
+        raise ValueError("L must be an FP64 matrix of at least 64 x 64")
+    if L.stride(1) != 1:
+        L = L.contiguous()
+    f = torch.empty(MLP_IN, dtype=torch.float32, device=L.device)
+    _check(_lib().pbpqlp_probe_features(ctypes.c_void_p(L.data_ptr()), L.stride(0),
+                                        ctypes.c_void_p(f.data_ptr()), _stream(L.device)),
+           "pbpqlp_probe_features")
+    return f
+
+
+def probe(A: torch.Tensor, seed: int, plan="native"):
+    """The q = 0, l = 64 probe factorization and its features: (f, L, info)."""
+    Q, L, P, info = factor(A, PROBE_K, PROBE_P, 0, seed, plan=plan)
+    return probe_features(L), L, info
+
+
+def factor_auto(model: Model, A: torch.Tensor, p: int, seed: int, k_max: int, tau: float,
+                plan="native"):
+    """pbpqlp_factor_auto: returns (Q, L, P, result dict, info); Q, L, P are
+    cut to the l = k_used + p columns the chosen run produced."""
+    A = _rowmajor(A, "A")
+    m, n = A.shape
+    lmax = k_max + p
+    Q = torch.empty((m, lmax), dtype=A.dtype, device=A.device)
+    P = torch.empty((n, lmax), dtype=A.dtype, device=A.device)
+    L = torch.empty((lmax, lmax), dtype=torch.float64, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    res = AutoResult()
+    o = make_opts(plan)
+    _check(_lib().pbpqlp_factor_auto(model._h, ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0), _dt(A),
+                                     p, ctypes.c_uint64(seed), k_max, float(tau),
+                                     ctypes.c_void_p(Q.data_ptr()), lmax, ctypes.c_void_p(L.data_ptr()),
+                                     lmax, ctypes.c_void_p(P.data_ptr()), lmax, ctypes.byref(o),
+                                     ctypes.c_void_p(info.data_ptr()), ctypes.byref(res),
+                                     _stream(A.device)), "pbpqlp_factor_auto")
+    l = res.k_used + p
+    r = {f: getattr(res, f) for f, _ in AutoResult._fields_ if f != "reserved"}
+    return Q[:, :l], L[:l, :l], P[:, :l], r, Info.from_device(info)

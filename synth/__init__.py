@@ -5,3 +5,4 @@ seeds).  It contains none of the factorization's arithmetic, so the oracle and
 the GPU path can both consume its matrices without sharing method code.
 """
 from .matrices import *  # noqa: F401,F403
+from .learned import *  # noqa: F401,F403

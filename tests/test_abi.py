@@ -110,3 +110,38 @@ def test_batch_rejects_empty():
     lib = B.library()
     h = ctypes.c_void_p()
     assert lib.pbpqlp_batch_create(0, None, B.F32, None, ctypes.byref(h)) == B.EINVAL
+
+
+def test_auto_result_layout():
+    assert ctypes.sizeof(B.AutoResult) == 40
+
+
+def test_model_file_errors_before_any_device_work(tmp_path):
+    lib = B.library()
+    h = ctypes.c_void_p()
+    assert lib.pbpqlp_model_load(os.fsencode(str(tmp_path / "missing.bin")), ctypes.byref(h)) == B.EINVAL
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTAMODEL" + bytes(64))
+    assert lib.pbpqlp_model_load(os.fsencode(str(bad)), ctypes.byref(h)) == B.EINVAL
+    # right magic, wrong dimensions
+    import struct
+    wrong = tmp_path / "wrong.bin"
+    wrong.write_bytes(b"PBQMLP01" + struct.pack("<4iq", 32, 128, 6, 0, 0))
+    assert lib.pbpqlp_model_load(os.fsencode(str(wrong)), ctypes.byref(h)) == B.EINVAL
+    # truncated parameters
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"PBQMLP01" + struct.pack("<4iq", 64, 128, 6, 0, 0) + bytes(1000))
+    assert lib.pbpqlp_model_load(os.fsencode(str(short)), ctypes.byref(h)) == B.EINVAL
+
+
+def test_learned_entry_points_reject_null_arguments():
+    lib = B.library()
+    assert lib.pbpqlp_model_create(None, None) == B.EINVAL
+    assert lib.pbpqlp_probe_features(None, 64, None, None) == B.EINVAL
+    assert lib.pbpqlp_mlp_forward(None, None, 64, 1, None, 6, None) == B.EINVAL
+    assert lib.pbpqlp_mlp_loss_grad(None, None, 64, None, None, 1, None, None, None) == B.EINVAL
+    assert lib.pbpqlp_mlp_adam_step(None, 1e-3, None) == B.EINVAL
+    res = B.AutoResult()
+    assert lib.pbpqlp_factor_auto(None, None, 1000, 1000, 1000, B.F32, 8, 1, 56, 0.1, None, 64,
+                                  None, 64, None, 64, None, None, ctypes.byref(res), None) == B.EINVAL
+    assert B.MLP_PARAMS == 64 * 128 + 128 + 128 * 128 + 128 + 6 * 128 + 6

@@ -63,3 +63,68 @@ def test_wrong_omega_index_order_is_caught(monkeypatch):
     monkeypatch.setattr(R, "omega", O.omega)
     with pytest.raises(AssertionError):
         test_omega_box_muller_by_hand()
+
+
+# ---- the learned q/k head's oracle --------------------------------------
+import oracle.qk_mlp_oracle as QK
+import tests.test_oracle_mlp as PQ
+
+
+def _fails(check):
+    try:
+        check()
+    except AssertionError:
+        return True
+    return False
+
+
+def test_mlp_pins_pass_unbroken():
+    for check in (PQ.test_gradient_matches_central_differences,
+                  PQ.test_all_active_network_is_the_composed_affine_map,
+                  PQ.test_relabelling_hidden_units_leaves_outputs_unchanged,
+                  PQ.test_adam_constant_gradient_steps, PQ.test_adam_sign_flip_second_step):
+        assert not _fails(check)
+
+
+def test_mlp_transposed_hidden_weights_are_caught(monkeypatch):
+    real = QK.forward
+
+    def fwd_t(theta, X):
+        W1, b1, W2, b2, W3, b3 = QK.unpack(theta)
+        return real(QK.pack(W1, b1, W2.T, b2, W3, b3), X)
+    monkeypatch.setattr(QK, "forward", fwd_t)
+    assert _fails(PQ.test_all_active_network_is_the_composed_affine_map)
+    assert _fails(PQ.test_relabelling_hidden_units_leaves_outputs_unchanged)
+
+
+def test_mlp_missing_relu_mask_in_backward_is_caught(monkeypatch):
+    # backward without the ReLU derivative: treat every unit as active
+    def grad_linear(theta, X, q, logk):
+        W1, b1, W2, b2, W3, b3 = QK.unpack(theta)
+        X = np.asarray(X, dtype=np.float64)
+        B = X.shape[0]
+        z, (h1, h2) = QK.forward(theta, X)
+        mx = z[:, :5].max(axis=1, keepdims=True)
+        ls = z[:, :5] - mx - np.log(np.exp(z[:, :5] - mx).sum(axis=1, keepdims=True))
+        err = z[:, 5] - logk
+        loss = float(np.mean(-ls[np.arange(B), q]) + np.mean(err * err))
+        dz = np.zeros_like(z)
+        dz[:, :5] = np.exp(ls)
+        dz[np.arange(B), q] -= 1.0
+        dz[:, :5] /= B
+        dz[:, 5] = 2.0 * err / B
+        dh2 = dz @ W3
+        dh1 = dh2 @ W2
+        return loss, QK.pack(dh1.T @ X, dh1.sum(0), dh2.T @ h1, dh2.sum(0), dz.T @ h2, dz.sum(0))
+    monkeypatch.setattr(QK, "loss_and_grad", grad_linear)
+    assert _fails(PQ.test_gradient_matches_central_differences)
+
+
+def test_adam_without_bias_correction_is_caught(monkeypatch):
+    def adam_nobc(theta, g, st, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        st.t += 1
+        st.m = beta1 * st.m + (1 - beta1) * g
+        st.v = beta2 * st.v + (1 - beta2) * g * g
+        return theta - lr * st.m / (np.sqrt(st.v) + eps)
+    monkeypatch.setattr(QK, "adam_step", adam_nobc)
+    assert _fails(PQ.test_adam_constant_gradient_steps)
