@@ -130,6 +130,22 @@ pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pb
                             void* Q, int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
                             const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream);
 
+/* The same factorization with a caller-supplied sketch matrix in place of the
+ * generated one (eq. (c) with Phi given; Algorithm 1 from its first product):
+ *   Omega : n x l, dtype dt, row-major, ldo >= l, device; read only.
+ * Everything else as pbpqlp_factor.  Passing the P of an earlier factorization
+ * of the same A as Omega continues its power iterations: the earlier
+ * projection A^T Q is the first half of the next iteration, so
+ * pbpqlp_factor_sketch(Omega = P of a q-iteration run, q = j) spans the same
+ * subspaces as pbpqlp_factor with q + 1 + j iterations, at 2 + 2 j more passes
+ * over A.  Errors: as pbpqlp_factor; EINVAL for a NULL, misaligned or aliased
+ * Omega or ldo < l. */
+pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t lda,
+                                   pbpqlp_dtype dt, const void* Omega, int64_t ldo, int k, int p,
+                                   int q, void* Q, int64_t ldq, double* L, int64_t ldl, void* P,
+                                   int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
+                                   void* stream);
+
 /* ---- single steps of the method, for validation against the oracle ---- */
 
 /* The sketch matrix of eq. (c) / Algorithm 1 (randn): Omega (n x l, row-major,
@@ -292,27 +308,38 @@ pbpqlp_status pbpqlp_mlp_train_step(pbpqlp_model* model, const float* X, int64_t
 
 /* What pbpqlp_factor_auto chose and measured (host struct). */
 typedef struct {
-  int q_pred, k_pred;        /* the network's choice                                  */
-  int q_used, k_used;        /* what the returned factorization used                  */
-  int fell_back;             /* 1: the first residual was above tau, rerun with q = 3 */
-  int reserved;
-  double resid_first;        /* resid_rel_est of the predicted run                    */
-  double resid_final;        /* resid_rel_est of the returned run                     */
+  int q_pred, k_pred;        /* the network's choice                                   */
+  int q_used, k_used;        /* what the returned factorization used                   */
+  int fell_back;             /* 1: the predicted run's residual was above tau          */
+  int passes;                /* passes over A in total, the probe's two included       */
+  double resid_first;        /* residual estimate of the predicted choice              */
+  double resid_final;        /* residual estimate of the returned factorization        */
 } pbpqlp_auto_result;
 
-/* Learned factorization: probe (k = 56, p = 8, q = 0) -> features -> network ->
- * q_hat = argmax of the logits (lowest index on ties), k_hat = exp(output_6)
- * rounded to the nearest integer and clamped to [1, k_max] -> pbpqlp_factor
- * with (q_hat, k_hat, p) -> if its resid_rel_est exceeds tau (or a non-finite
- * input was flagged) the fallback pbpqlp_factor with (q = 3, k_hat, p).
- *   A, dt, lda, seed, opts as for pbpqlp_factor (seed also drives the probe);
- *   requires min(m, n) >= 64 and k_max + p <= min(m, n), k_max + p <= 256.
- *   Q (m x (k_used + p)), L, P (n x (k_used + p)) are written as pbpqlp_factor
- *   writes them, so ldq, ldl, ldp must be >= k_max + p.
- * Synchronizes `stream` twice (to read the prediction and the residual), so
- * it cannot be captured in a graph.  The probe's buffers are allocated and
+/* Learned factorization.  The probe (k = 56, p = 8, q = 0, l = 64) is also the
+ * first stage of the answer:
+ *   probe -> features -> network -> q_hat = argmax of the logits (lowest index
+ *   on ties), k_hat = exp(output_6) rounded to the nearest integer, clamped
+ *   to [1, k_max];
+ *   if q_hat > 0 the probe's power iterations are continued to q_hat
+ *   (pbpqlp_factor_sketch with Omega = the current P), 2 passes per iteration;
+ *   the answer is the rank-(k_hat + p) leading part of the l = 64
+ *   factorization: Q and P cut to their first k_hat + p columns and L to its
+ *   leading block (A ~= Q' L'^T P'^T; since Q'^T A P' = L'^T, its residual is
+ *   sqrt(||A||^2 - ||L'||^2) / ||A||, which is the estimate checked);
+ *   if that estimate exceeds tau (or a non-finite input was flagged) the
+ *   fallback continues to q = 3 (when q_hat < 3) and returns k = k_max.
+ * A plain run with q iterations costs 2 q + 2 passes; this path costs
+ * 2 max(q_hat, 1 if fell back then 3) + 2, the probe included.
+ *   A, dt, lda, seed, opts as for pbpqlp_factor (opts.workspace is ignored);
+ *   requires min(m, n) >= 64, 1 <= k_max and k_max + p <= 64.
+ *   Q (m x (k_used + p), ldq >= k_max + p), L ((k_used + p)^2, ldl >= k_max + p),
+ *   P (n x (k_used + p), ldp >= k_max + p) as pbpqlp_factor writes them;
+ *   d_info (may be NULL) describes the returned factorization (l = k_used + p).
+ * Synchronizes `stream` (it reads the prediction and the residual on the
+ * host), so it cannot be captured in a graph; its buffers are allocated and
  * freed stream-ordered.  Errors: as pbpqlp_factor, and EINVAL for a NULL
- * model, tau <= 0 or bad k_max. */
+ * model, tau <= 0, or k_max, p outside the limits above. */
 pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* model, const void* A, int64_t m, int64_t n,
                                  int64_t lda, pbpqlp_dtype dt, int p, uint64_t seed, int k_max,
                                  double tau, void* Q, int64_t ldq, double* L, int64_t ldl,

@@ -3,9 +3,9 @@
 The computation lives in libpbpqlp.so (HIP kernels behind the C ABI of
 include/pbpqlp.h); this package only binds it.  See pbpqlp.py.
 """
-from .pbpqlp import (Batch, Factorizer, Info, Model, PbpqlpError, PLANS, factor, factor_auto,
+from .pbpqlp import (Batch, Factorizer, Info, Model, PbpqlpError, PLANS, factor, factor_auto, factor_sketch,
                      library, matmul, omega, orth, probe, probe_features, small_qr, workspace_size)
 
-__all__ = ["Batch", "Factorizer", "Info", "Model", "PbpqlpError", "PLANS", "factor", "factor_auto",
+__all__ = ["Batch", "Factorizer", "Info", "Model", "PbpqlpError", "PLANS", "factor", "factor_auto", "factor_sketch",
            "library", "matmul", "omega", "orth", "probe", "probe_features", "small_qr",
            "workspace_size"]

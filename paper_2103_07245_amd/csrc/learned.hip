@@ -472,25 +472,24 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
                                  double tau, void* Q, int64_t ldq, double* L, int64_t ldl,
                                  void* P, int64_t ldp, const pbpqlp_opts* opts,
                                  pbpqlp_info* d_info, pbpqlp_auto_result* result, void* stream) {
+  constexpr int LP = PBPQLP_PROBE_K + PBPQLP_PROBE_P;  // the probe's width
   if (!md || !A || !Q || !L || !P || !(tau > 0.0) || p < 0 || k_max < 1) return PBPQLP_EINVAL;
   if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
-  const int64_t mn = m < n ? m : n;
-  const int lprobe = PBPQLP_PROBE_K + PBPQLP_PROBE_P;
   const int lmax = k_max + p;
-  if (mn < lprobe || lmax > mn || ldq < lmax || ldl < lmax || ldp < lmax) return PBPQLP_EINVAL;
-  if (lmax > 256) return PBPQLP_EUNSUPPORTED;
+  if ((m < n ? m : n) < LP || lmax > LP || ldq < lmax || ldl < lmax || ldp < lmax) return PBPQLP_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   pbpqlp_opts o;
   pbpqlp_default_opts(&o);
   if (opts) o = *opts;
-  o.workspace = nullptr;        // every call below sizes its own workspace
+  o.workspace = nullptr;        // every run below sizes its own workspace
   o.workspace_bytes = 0;
   const size_t el = dt == PBPQLP_F64 ? 8 : 4;
-  // probe outputs, features, network outputs and a result record
-  const size_t szQ = (size_t)m * lprobe * el, szP = (size_t)n * lprobe * el;
-  const size_t szL = (size_t)lprobe * lprobe * 8;
+  // two l = 64 factorizations (the current one and the next), features,
+  // network outputs and a result record
+  const size_t szQ = (size_t)m * LP * el, szP = (size_t)n * LP * el, szL = (size_t)LP * LP * 8;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  const size_t total = up(szQ) + up(szP) + up(szL) + up(NI * 4) + up(NO * 4) + up(sizeof(pbpqlp_info));
+  const size_t one = up(szQ) + up(szP) + up(szL);
+  const size_t total = 2 * one + up(NI * 4) + up(NO * 4) + up(sizeof(pbpqlp_info));
   char* scratch = nullptr;
   if (hipMallocAsync((void**)&scratch, total, st) != hipSuccess) return PBPQLP_ENOMEM;
   struct Free {
@@ -498,19 +497,26 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
     hipStream_t s;
     ~Free() { (void)hipFreeAsync(p, s); }
   } guard{scratch, st};
-  char* c = scratch;
-  void* Qp = c; c += up(szQ);
-  void* Pp = c; c += up(szP);
-  double* Lp = (double*)c; c += up(szL);
-  float* f = (float*)c; c += up(NI * 4);
-  float* z = (float*)c; c += up(NO * 4);
-  pbpqlp_info* own = (pbpqlp_info*)c;
-  pbpqlp_info* info = d_info ? d_info : own;
+  void* Qb[2];
+  void* Pb[2];
+  double* Lb[2];
+  for (int i = 0; i < 2; ++i) {
+    char* c = scratch + i * one;
+    Qb[i] = c;
+    Pb[i] = c + up(szQ);
+    Lb[i] = (double*)(c + up(szQ) + up(szP));
+  }
+  float* f = (float*)(scratch + 2 * one);
+  float* z = (float*)(scratch + 2 * one + up(NI * 4));
+  pbpqlp_info* dinf = (pbpqlp_info*)(scratch + 2 * one + up(NI * 4) + up(NO * 4));
 
-  pbpqlp_status s = pbpqlp_factor(A, m, n, lda, dt, PBPQLP_PROBE_K, PBPQLP_PROBE_P, 0, seed, Qp, lprobe,
-                                  Lp, lprobe, Pp, lprobe, &o, own, stream);
+  pbpqlp_auto_result r{};
+  int cur = 0, qcur = 0, flags = 0, ndep = 0;
+  pbpqlp_status s = pbpqlp_factor(A, m, n, lda, dt, PBPQLP_PROBE_K, PBPQLP_PROBE_P, 0, seed, Qb[0], LP,
+                                  Lb[0], LP, Pb[0], LP, &o, dinf, stream);
   if (s) return s;
-  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NI), 0, st, (const double*)Lp, (int64_t)lprobe, f);
+  r.passes = 2;
+  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(NI), 0, st, (const double*)Lb[0], (int64_t)LP, f);
   PBQ_TRY(hipGetLastError());
   hipLaunchKernelGGL(infer_kernel, dim3(1), dim3(NH), 0, st, (const float*)md->theta(), (const float*)f, z);
   PBQ_TRY(hipGetLastError());
@@ -527,36 +533,71 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
     const double kr = std::floor(std::exp(std::fmin((double)hz[NQ], 30.0)) + 0.5);
     kh = kr < 1.0 ? 1 : (kr > (double)k_max ? k_max : (int)kr);
   }
-  pbpqlp_auto_result r{};
   r.q_pred = qh;
   r.k_pred = kh;
-  auto run = [&](int qq, double* resid, int* flags) -> pbpqlp_status {
-    pbpqlp_status s2 = pbpqlp_factor(A, m, n, lda, dt, kh, p, qq, seed, Q, ldq, L, ldl, P, ldp, &o, info, stream);
+  pbpqlp_info hi{};
+  // continue the current factorization's power iterations up to q = to
+  auto advance = [&](int to) -> pbpqlp_status {
+    if (to <= qcur) return PBPQLP_OK;
+    const int nx = cur ^ 1;
+    pbpqlp_status s2 = pbpqlp_factor_sketch(A, m, n, lda, dt, Pb[cur], LP, PBPQLP_PROBE_K,
+                                            PBPQLP_PROBE_P, to - qcur - 1, Qb[nx], LP, Lb[nx], LP,
+                                            Pb[nx], LP, &o, dinf, stream);
     if (s2) return s2;
-    pbpqlp_info hi;
-    PBQ_TRY(hipMemcpyAsync(&hi, info, sizeof(hi), hipMemcpyDeviceToHost, st));
-    PBQ_TRY(hipStreamSynchronize(st));
-    *resid = hi.resid_rel_est;
-    *flags = hi.status_flags;
+    r.passes += 2 * (to - qcur);
+    cur = nx;
+    qcur = to;
     return PBPQLP_OK;
   };
-  double r1 = 0.0;
-  int fl1 = 0;
-  s = run(qh, &r1, &fl1);
-  if (s) return s;
+  double hL[LP * LP];
+  // residual estimate of the leading rank-lt part of the current factorization
+  auto resid = [&](int lt, double* out, double* nl2) -> pbpqlp_status {
+    PBQ_TRY(hipMemcpyAsync(hL, Lb[cur], sizeof(hL), hipMemcpyDeviceToHost, st));
+    PBQ_TRY(hipMemcpyAsync(&hi, dinf, sizeof(hi), hipMemcpyDeviceToHost, st));
+    PBQ_TRY(hipStreamSynchronize(st));
+    double s2 = 0.0;
+    for (int i = 0; i < lt; ++i)
+      for (int j = 0; j <= i; ++j) s2 += hL[i * LP + j] * hL[i * LP + j];
+    const double a2 = hi.norm_a_fro2;
+    *out = a2 > 0.0 ? std::sqrt(std::fmax(a2 - s2, 0.0) / a2) : 0.0;
+    *nl2 = s2;
+    flags |= hi.status_flags;
+    ndep += hi.n_dependent;
+    return PBPQLP_OK;
+  };
+  if ((s = advance(qh))) return s;
+  int kout = kh;
+  double r1 = 0.0, nl2 = 0.0;
+  if ((s = resid(kh + p, &r1, &nl2))) return s;
   r.resid_first = r1;
-  r.resid_final = r1;
-  r.q_used = qh;
-  r.k_used = kh;
-  const bool bad = !(r1 <= tau) || (fl1 & PBPQLP_FLAG_NONFINITE);
-  if (bad && qh < 3) {
-    double r2 = 0.0;
-    int fl2 = 0;
-    s = run(3, &r2, &fl2);
-    if (s) return s;
+  double rf = r1;
+  const bool bad = !(r1 <= tau) || (flags & PBPQLP_FLAG_NONFINITE);
+  if (bad) {
     r.fell_back = 1;
-    r.q_used = 3;
-    r.resid_final = r2;
+    if ((s = advance(3))) return s;
+    kout = k_max;
+    if ((s = resid(kout + p, &rf, &nl2))) return s;
+  }
+  r.q_used = qcur;
+  r.k_used = kout;
+  r.resid_final = rf;
+  const int lo = kout + p;
+  PBQ_TRY(hipMemcpy2DAsync(Q, (size_t)ldq * el, Qb[cur], (size_t)LP * el, (size_t)lo * el, (size_t)m,
+                           hipMemcpyDeviceToDevice, st));
+  PBQ_TRY(hipMemcpy2DAsync(P, (size_t)ldp * el, Pb[cur], (size_t)LP * el, (size_t)lo * el, (size_t)n,
+                           hipMemcpyDeviceToDevice, st));
+  PBQ_TRY(hipMemcpy2DAsync(L, (size_t)ldl * 8, Lb[cur], (size_t)LP * 8, (size_t)lo * 8, (size_t)lo,
+                           hipMemcpyDeviceToDevice, st));
+  if (d_info) {
+    pbpqlp_info out = hi;
+    out.status_flags = flags;
+    out.n_dependent = ndep;
+    out.l = lo;
+    out.q = qcur;
+    out.norm_l_fro2 = nl2;
+    out.resid_rel_est = rf;
+    PBQ_TRY(hipMemcpyAsync(d_info, &out, sizeof(out), hipMemcpyHostToDevice, st));
+    PBQ_TRY(hipStreamSynchronize(st));   // `out` lives on this frame
   }
   if (result) *result = r;
   return PBPQLP_OK;

@@ -154,6 +154,8 @@ struct Ctx {
   int forced_split = 0;
   int gram_target = 512;   // Gram workgroups to aim at (fewer per problem in a batch)
   uint64_t seed = 0;
+  const void* omega_in = nullptr;  // caller's sketch matrix (row-major n x l), or generated
+  int64_t ldo_in = 0;
   // splits: the sketch pass's grid sizes the ||A||_F^2 partials
   int k1_blocks = 0, k1_splits = 1;
   size_t part_bytes = 0;
@@ -373,11 +375,15 @@ pbpqlp_status small_qr(Ctx& c, const double* Rrow, int64_t ldr, void* info, hipS
 pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L, int64_t ldl,
                          void* P, int64_t ldp, pbpqlp_info* info, hipStream_t st) {
   PBQ_CHECK(launch_info_init(info, c.l, c.q, st));
-  // S0: sketch matrix, column-major (lp32 x ldn)
-  PBQ_CHECK(launch_omega_cm(c.f64, c.n, c.l, c.lp32, c.seed, c.Om, c.ldn, st));
+  // S0: sketch matrix, column-major (lp32 x ldn): generated, or the caller's
+  if (c.omega_in)
+    PBQ_CHECK(launch_rm_to_cm(c.f64, c.omega_in, c.ldo_in, c.n, c.l, c.lp32, c.Om, c.ldn, st));
+  else
+    PBQ_CHECK(launch_omega_cm(c.f64, c.n, c.l, c.lp32, c.seed, c.Om, c.ldn, st));
   // S1: Y = A Omega (+ ||A||_F^2)
   pbpqlp_status s;
-  s = stream_pass(c, false, c.mode_sketch, A, c.Om, c.ldn, c.n, false, c.Y, c.ldm, c.normA, st);
+  s = stream_pass(c, false, c.mode_sketch, A, c.Om, c.ldn, c.n, c.omega_in != nullptr, c.Y, c.ldm,
+                  c.normA, st);
   if (s) return s;
   s = orth(c, c.f64, c.Y, c.ldm, c.m, c.q == 0 ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
   if (s) return s;
@@ -533,10 +539,14 @@ pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_d
   return PBPQLP_OK;
 }
 
-pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
-                            int k, int p, int q, uint64_t seed, void* Q, int64_t ldq, double* L,
-                            int64_t ldl, void* P, int64_t ldp, const pbpqlp_opts* opts,
-                            pbpqlp_info* d_info, void* stream) {
+}  // extern "C"
+
+namespace {
+
+pbpqlp_status factor_impl(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                          const void* Omega, int64_t ldo, int k, int p, int q, uint64_t seed,
+                          void* Q, int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
+                          const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream) {
   if (!A || !Q || !L || !P) return PBPQLP_EINVAL;
   Ctx c;
   pbpqlp_status s = setup(c, m, n, lda, dt, k, p, q, opts);
@@ -545,6 +555,12 @@ pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pb
   if (Q == A || P == A || (const void*)L == A || Q == P) return PBPQLP_EINVAL;
   if (!aligned(A, c.el) || !aligned(Q, c.el) || !aligned(P, c.el) || !aligned(L, 8))
     return PBPQLP_EINVAL;
+  if (Omega) {
+    if (ldo < c.l || !aligned(Omega, c.el) || Omega == Q || Omega == P || Omega == (const void*)L)
+      return PBPQLP_EINVAL;
+    c.omega_in = Omega;
+    c.ldo_in = ldo;
+  }
   c.seed = seed;
   hipStream_t st = (hipStream_t)stream;
   const bool n16 = needs16(c);
@@ -572,6 +588,29 @@ pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pb
   if ((size_t)(b.base + b.off - base) > avail) return PBPQLP_ENOMEM;
   pbpqlp_info* info = d_info ? d_info : own;
   return run_factor(c, A, Q, ldq, L, ldl, P, ldp, info, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                            int k, int p, int q, uint64_t seed, void* Q, int64_t ldq, double* L,
+                            int64_t ldl, void* P, int64_t ldp, const pbpqlp_opts* opts,
+                            pbpqlp_info* d_info, void* stream) {
+  return factor_impl(A, m, n, lda, dt, nullptr, 0, k, p, q, seed, Q, ldq, L, ldl, P, ldp, opts,
+                     d_info, stream);
+}
+
+pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t lda,
+                                   pbpqlp_dtype dt, const void* Omega, int64_t ldo, int k, int p,
+                                   int q, void* Q, int64_t ldq, double* L, int64_t ldl, void* P,
+                                   int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
+                                   void* stream) {
+  if (!Omega) return PBPQLP_EINVAL;
+  // the seed still drives the completion of dependent columns
+  return factor_impl(A, m, n, lda, dt, Omega, ldo, k, p, q, 0x5EEDull, Q, ldq, L, ldl, P, ldp,
+                     opts, d_info, stream);
 }
 
 pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt, void* Omega,

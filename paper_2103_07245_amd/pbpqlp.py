@@ -69,7 +69,7 @@ class ProblemStruct(ctypes.Structure):
 
 class AutoResult(ctypes.Structure):
     _fields_ = [("q_pred", ctypes.c_int), ("k_pred", ctypes.c_int), ("q_used", ctypes.c_int),
-                ("k_used", ctypes.c_int), ("fell_back", ctypes.c_int), ("reserved", ctypes.c_int),
+                ("k_used", ctypes.c_int), ("fell_back", ctypes.c_int), ("passes", ctypes.c_int),
                 ("resid_first", ctypes.c_double), ("resid_final", ctypes.c_double)]
 
 
@@ -146,6 +146,9 @@ def _lib():
         lib.pbpqlp_mlp_adam_step.argtypes = [vp, f32, vp]
         lib.pbpqlp_mlp_train_step.restype = i32
         lib.pbpqlp_mlp_train_step.argtypes = [vp, vp, i64, vp, vp, i32, f32, vp, vp]
+        lib.pbpqlp_factor_sketch.restype = i32
+        lib.pbpqlp_factor_sketch.argtypes = [vp, i64, i64, i64, i32, vp, i64, i32, i32, i32, vp, i64,
+                                             dp, i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
         lib.pbpqlp_factor_auto.restype = i32
         lib.pbpqlp_factor_auto.argtypes = [vp, vp, i64, i64, i64, i32, i32, u64, i32, ctypes.c_double,
                                            vp, i64, dp, i64, vp, i64, ctypes.POINTER(Opts), vp,
@@ -280,6 +283,29 @@ def factor(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", sp
                    gram_wg)
     Q, L, P = f(A, seed)
     return Q, L, P, f.info()
+
+
+def factor_sketch(A: torch.Tensor, Omega: torch.Tensor, k: int, p: int, q: int, plan="native"):
+    """pbpqlp_factor_sketch: the factorization with a given sketch matrix
+    Omega (n x l, the dtype of A).  Returns (Q, L, P, info)."""
+    A = _rowmajor(A, "A")
+    Omega = _rowmajor(Omega, "Omega")
+    m, n = A.shape
+    l = k + p
+    if Omega.shape != (n, l) or Omega.dtype != A.dtype:
+        raise ValueError("Omega must be n x (k + p) in the dtype of A")
+    Q = torch.empty((m, l), dtype=A.dtype, device=A.device)
+    P = torch.empty((n, l), dtype=A.dtype, device=A.device)
+    L = torch.empty((l, l), dtype=torch.float64, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    o = make_opts(plan)
+    _check(_lib().pbpqlp_factor_sketch(ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0), _dt(A),
+                                       ctypes.c_void_p(Omega.data_ptr()), Omega.stride(0), k, p, q,
+                                       ctypes.c_void_p(Q.data_ptr()), l, ctypes.c_void_p(L.data_ptr()), l,
+                                       ctypes.c_void_p(P.data_ptr()), l, ctypes.byref(o),
+                                       ctypes.c_void_p(info.data_ptr()), _stream(A.device)),
+           "pbpqlp_factor_sketch")
+    return Q, L, P, Info.from_device(info)
 
 
 def omega(n: int, l: int, seed: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
@@ -584,5 +610,5 @@ def factor_auto(model: Model, A: torch.Tensor, p: int, seed: int, k_max: int, ta
                                      ctypes.c_void_p(info.data_ptr()), ctypes.byref(res),
                                      _stream(A.device)), "pbpqlp_factor_auto")
     l = res.k_used + p
-    r = {f: getattr(res, f) for f, _ in AutoResult._fields_ if f != "reserved"}
+    r = {f: getattr(res, f) for f, _ in AutoResult._fields_}
     return Q[:, :l], L[:l, :l], P[:, :l], r, Info.from_device(info)

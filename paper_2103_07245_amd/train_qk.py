@@ -9,15 +9,18 @@ pbpqlp_probe_features, and training runs pbpqlp_mlp_train_step (the forward,
 backward and Adam kernels).  PyTorch holds device memory and builds the
 synthetic matrices.
 
-Labels of one matrix with planted singular values sigma (sigma_1 = 1):
+Labels of one matrix with planted singular values sigma (sigma_1 = 1) follow
+what pbpqlp_factor_auto returns -- the leading rank-(k + p) part of the l = 64
+factorization whose power iterations continue the probe's:
   k* = the smallest k with sigma_{k+1} <= 1e-3 sigma_1, capped at the probe's
        k = 56;
-  r(q) = resid_rel_est of pbpqlp_factor(A in FP64, k*, p = 8, q) for q = 0..4
-       (the relative Frobenius residual of A ~ Q L^T P^T, which equals that
-       of the projection Q Q^T A because the QLP stage is exact);
+  r(q) = sqrt(||A||^2 - ||L'||^2) / ||A|| for the leading (k* + p) block L' of
+       L after q iterations, q = 0..4, in FP64 (the probe, then four
+       pbpqlp_factor_sketch continuations with Omega = the previous P: ten
+       passes over A in all);
   q* = the smallest q with r(q) <= 1.05 r_opt(k* + p), else 4, where r_opt(l)
        is the best rank-l residual sqrt(sum_{i>l} sigma_i^2) / ||sigma||.
-Features come from the q = 0, l = 64 probe of the same matrix stored in FP32.
+Features come from the probe of the same matrix stored in FP32.
 """
 from __future__ import annotations
 
@@ -81,16 +84,26 @@ def make_matrix(spec, device) -> torch.Tensor:
     return (U * sig) @ V.T
 
 
+def truncated_residual(L: torch.Tensor, norm_a2: float, lt: int) -> float:
+    """Residual estimate of the leading rank-lt part of a factorization."""
+    Lh = L[:lt, :lt].double().cpu().numpy()
+    s2 = float(np.sum(Lh * Lh))
+    return math.sqrt(max(norm_a2 - s2, 0.0) / norm_a2) if norm_a2 > 0 else 0.0
+
+
 def label_matrix(A64: torch.Tensor, sigma: np.ndarray, seed: int, plan="native"):
     """(features, q*, k*, r(q) list, r_opt) of one matrix."""
     A32 = A64.float().contiguous()
     f, _, _ = B.probe(A32, seed, plan)
     ks = k_star(sigma)
+    lt = ks + P_OVER
     rs = []
+    _, L, P, info = B.factor(A64, B.PROBE_K, B.PROBE_P, 0, seed)
     for q in range(Q_MAX + 1):
-        _, _, _, info = B.factor(A64, ks, P_OVER, q, seed)
-        rs.append(float(info.resid_rel_est))
-    rb = r_opt(sigma, ks + P_OVER)
+        if q > 0:
+            _, L, P, info = B.factor_sketch(A64, P, B.PROBE_K, B.PROBE_P, 0)
+        rs.append(truncated_residual(L, info.norm_a_fro2, lt))
+    rb = r_opt(sigma, lt)
     return f.cpu().numpy(), q_star(rs, rb), ks, rs, rb
 
 

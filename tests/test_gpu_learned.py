@@ -121,6 +121,17 @@ def _const_model(q_logits, k):
     return B.Model(O.pack(W1, b1, W2, b2, W3, b3).astype(np.float32))
 
 
+def _chain(At, seed, stops):
+    """The probe continued to each iteration count in `stops` in turn (one
+    pbpqlp_factor_sketch call per stop), by plain calls."""
+    Q, L, P, info = B.factor(At, 56, 8, 0, seed)
+    q = 0
+    for to in stops:
+        Q, L, P, info = B.factor_sketch(At, P, 56, 8, to - q - 1)
+        q = to
+    return Q, L, P, info
+
+
 @pytest.mark.parametrize("tau,expect_fallback", [(1.0, False), (1e-9, True)])
 def test_factor_auto_choice_and_fallback(tau, expect_fallback):
     print(f"factor_auto tau={tau}", flush=True)
@@ -130,12 +141,47 @@ def test_factor_auto_choice_and_fallback(tau, expect_fallback):
     Q, L, P, res, info = B.factor_auto(md, At, 8, spec.seed_omega, 40, tau)
     assert res["q_pred"] == 1 and res["k_pred"] == 9
     assert res["fell_back"] == int(expect_fallback)
-    q_used = 3 if expect_fallback else 1
-    assert res["q_used"] == q_used and res["k_used"] == 9
-    Qr, Lr, Pr, infr = B.factor(At, 9, 8, q_used, spec.seed_omega)
-    assert torch.equal(Q, Qr) and torch.equal(L, Lr) and torch.equal(P, Pr)
-    assert res["resid_final"] == infr.resid_rel_est
+    q_used, k_used = (3, 40) if expect_fallback else (1, 9)
+    assert res["q_used"] == q_used and res["k_used"] == k_used
+    assert res["passes"] == 2 + 2 * q_used
+    assert info.q == q_used and info.l == k_used + 8
+    # the answer is the leading part of the continued l = 64 factorization
+    Qc, Lc, Pc, infc = _chain(At, spec.seed_omega, [1, 3] if expect_fallback else [1])
+    lt = k_used + 8
+    assert torch.equal(Q, Qc[:, :lt]) and torch.equal(P, Pc[:, :lt]) and torch.equal(L, Lc[:lt, :lt])
+    r = T.truncated_residual(Lc, infc.norm_a_fro2, lt)
+    assert res["resid_final"] == pytest.approx(r, rel=1e-12, abs=1e-15)
+    assert info.resid_rel_est == pytest.approx(r, rel=1e-12, abs=1e-15)
     md.close()
+
+
+def test_continued_sketch_equals_more_iterations():
+    """factor_sketch(Omega = P of a q-iteration run, q = 0) spans the subspaces
+    of a (q + 1)-iteration run: in FP64 both give the same L and Q Q^T."""
+    spec = synth.qk_spec(3, 45, (350, 350), (280, 280), 200, family="exp")
+    At = torch.from_numpy(synth.qk_matrix(spec)).to(DEV)
+    seed = spec.seed_omega
+    Q0, L0, P0, _ = B.factor(At, 20, 8, 0, seed)
+    Q1, L1, P1, i1 = B.factor_sketch(At, P0, 20, 8, 0)
+    Qr, Lr, Pr, ir = B.factor(At, 20, 8, 1, seed)
+    assert torch.allclose(L1, Lr, rtol=0, atol=1e-10 * float(Lr.abs().max()))
+    assert torch.allclose(Q1 @ Q1.T, Qr @ Qr.T, atol=1e-9)
+    assert i1.resid_rel_est == pytest.approx(ir.resid_rel_est, rel=1e-8)
+
+
+def test_factor_sketch_matches_oracle_with_the_same_sketch():
+    from oracle import pbpqlp as oracle_pbpqlp
+    spec = synth.qk_spec(4, 46, (260, 260), (190, 190), 150, family="step")
+    A = synth.qk_matrix(spec)
+    At = torch.from_numpy(A).to(DEV)
+    rng = np.random.default_rng(9)
+    Om = rng.standard_normal((190, 30))
+    for q in (0, 2):
+        Q, L, P, info = B.factor_sketch(At, torch.from_numpy(Om).to(DEV), 22, 8, q)
+        ref = oracle_pbpqlp(A, 22, 8, q, Omega=Om)
+        assert np.abs(L.cpu().numpy() - ref.L).max() <= 1e-10 * np.abs(ref.L).max()
+        assert np.abs(Q.cpu().numpy() - ref.Q).max() <= 1e-8
+        assert np.abs(P.cpu().numpy() - ref.P).max() <= 1e-8
 
 
 def test_factor_auto_prediction_equals_batched_forward():
