@@ -86,7 +86,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-baseline", choices=["full", "none"], default="full",
                     help="time the FP64 oracle on one factorization of the same matrix")
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2")
+    ap.add_argument("--model", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                    "paper_2103_07245_amd", "weights", "qk_mlp.bin"),
+                    help="c5: trained q/k network")
     ap.add_argument("--plan", default="native", help="precision plan of the c4 batch")
     ap.add_argument("--count", type=int, default=1024, help="c4 batch size")
     ap.add_argument("--skip-per-matrix", action="store_true", help="c4: skip the per-matrix timing")
@@ -113,6 +116,8 @@ def main():
     B.library()
     if args.workload == "c4":
         return bench_c4(args, torch, np, synth, B, dev)
+    if args.workload == "c5":
+        return bench_c5(args, torch, np, synth, B, dev)
 
     t = time.time()
     w = synth.config2()
@@ -307,6 +312,65 @@ def bench_c4(args, torch, np, synth, B, dev):
         "algorithmic_gb": abytes / 1e9, "achieved_gbs": round(abytes / (ms_batch * 1e-3) / 1e9, 1),
         "hbm_frac": round(abytes / (ms_batch * 1e-3) / 8e12, 4),
         "max_abs_dr_vs_fp64_oracle_sample": max(errs),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_c5(args, torch, np, synth, B, dev):
+    """Learned q/k choice on 8192 x 8192 FP32 matrices with mixed spectra:
+    pbpqlp_factor_auto against the plain method with q = 3 and the true
+    epsilon-rank k*, both judged by tau = 1.05 r_opt(k* + p)."""
+    from paper_2103_07245_amd import train_qk as T
+    count = args.count if args.count != 1024 else 12
+    size = 8192
+    model = B.Model.load(args.model)
+    p = 8
+    rows = []
+    t_all = time.time()
+    for i in range(count + 1):                   # matrix 0 is a warm-up
+        spec = synth.qk_spec(i, 777, (size, size), (size, size), 512)
+        A = T.make_matrix(spec, dev).float().contiguous()
+        ks = T.k_star(spec.sigma)
+        tau = T.Q_SLACK * T.r_opt(spec.sigma, ks + p)
+        fplain = B.Factorizer(size, size, ks, p, 3, torch.float32, args.plan, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, _, _, res, info = B.factor_auto(model, A, p, spec.seed_omega, B.PROBE_K, tau, plan=args.plan)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fplain(A, spec.seed_omega)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        r_plain = fplain.info().resid_rel_est
+        if i > 0:
+            rows.append({"family": spec.family, "k_star": ks, "tau": tau, "q_pred": res["q_pred"],
+                         "k_pred": res["k_pred"], "q_used": res["q_used"], "k_used": res["k_used"],
+                         "fell_back": res["fell_back"], "passes": res["passes"],
+                         "r_learned": res["resid_final"], "r_plain": r_plain,
+                         "ms_learned": (t1 - t0) * 1e3, "ms_plain": (t2 - t1) * 1e3})
+            log(f"matrix {i}: {spec.family:4s} k*={ks:2d} q_hat={res['q_pred']} k_hat={res['k_pred']:2d} "
+                f"passes {res['passes']:2d} fell_back={res['fell_back']} "
+                f"r {res['resid_final']:.3e} / plain {r_plain:.3e} (tau {tau:.3e}) "
+                f"ms {rows[-1]['ms_learned']:.2f} / {rows[-1]['ms_plain']:.2f}")
+        del A, fplain
+    ml = float(np.mean([r["ms_learned"] for r in rows]))
+    mp = float(np.mean([r["ms_plain"] for r in rows]))
+    ok_l = float(np.mean([r["r_learned"] <= r["tau"] for r in rows]))
+    ok_p = float(np.mean([r["r_plain"] <= r["tau"] for r in rows]))
+    line = {
+        "metric": "learned q/k: ms per factorization of 8192x8192 FP32, learned vs plain q=3",
+        "value": round(ml, 3), "unit": "ms/factorization", "n_gpus": 1, "steps": len(rows),
+        "warmup": 1, "ms_per_step": round(ml, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.plan == "native" else "bf16", "data": "synthetic",
+        "config": {"workload": f"{len(rows)} FP32 {size}x{size} matrices, spectra step/poly/exp, "
+                               "planted rank <= 512, p=8, probe l=64", "plan": args.plan},
+        "plain_q3_ms": round(mp, 3), "speedup_vs_plain_q3": round(mp / ml, 3),
+        "passes_learned_mean": float(np.mean([r["passes"] for r in rows])), "passes_plain": 8,
+        "success_learned": ok_l, "success_plain_q3": ok_p,
+        "fallback_rate": float(np.mean([r["fell_back"] for r in rows])),
+        "k_hat_abs_log_err": float(np.mean([abs(math.log(r["k_pred"] / r["k_star"])) for r in rows])),
+        "q_hat_hist": np.bincount([r["q_pred"] for r in rows], minlength=5).tolist(),
+        "wall_s": round(time.time() - t_all, 1),
     }
     print(json.dumps(line), flush=True)
 

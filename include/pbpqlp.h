@@ -72,9 +72,13 @@ typedef struct {
   int sketch_prec;          /* pass Y = A Omega                                   */
   int power_prec;           /* the 2q passes of the power iterations              */
   int proj_prec;            /* pass B^T = A^T Q                                   */
-  int split_k;              /* 0 = automatic; else forced split count of each pass */
-  int gram_workgroups;      /* 0 = automatic; else the workgroups each Gram aims at
-                               (contraction splits x column-block pairs)          */
+  int split_k;              /* contraction splits of each A-streaming pass:
+                               0 = automatic (the autotuned plan of the problem's
+                               shape class if one is cached, else the built-in
+                               heuristic), -1 = the built-in heuristic, > 0 forced */
+  int gram_workgroups;      /* workgroups each Gram aims at (contraction splits x
+                               column-block pairs): 0 = automatic (cached plan,
+                               else 512; in a batch a count-based default), > 0 forced */
   double fp16_scale_a;      /* power of two applied to A in FP16 passes (0 -> 1)  */
   void* workspace;          /* device memory owned by the caller, or NULL: then the
                                library allocates stream-ordered and frees it after */
@@ -146,11 +150,31 @@ pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t 
                                    int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
                                    void* stream);
 
+/* The approximation A_hat = Q L^T P^T (eq. (Ahat), for A^T) of a factorization:
+ *   Q (m x l), P (n x l) in dtype dt, L (l x l FP64, lower triangular), all
+ *   device, row-major; Ahat (m x n, dt, ldh >= n) is written.
+ * Forms W = P L in FP64 (stored in dt), then the m x n product in tiles with
+ * accumulation in dt.  Errors: EINVAL; ENOMEM (stream-ordered scratch). */
+pbpqlp_status pbpqlp_reconstruct(const void* Q, int64_t ldq, const double* L, int64_t ldl, const void* P,
+                                 int64_t ldp, int64_t m, int64_t n, int l, pbpqlp_dtype dt, void* Ahat,
+                                 int64_t ldh, void* stream);
+/* Explicit relative residual ||A - Q L^T P^T||_F / ||A||_F (one pass over A,
+ * A_hat never stored): squares summed in FP64 per tile, tiles summed in a
+ * fixed order; the product itself accumulates in dt, so for FP32 the result
+ * is meaningful down to about 1e-6.  d_r: device, one double.  Cross-checks
+ * the estimate of pbpqlp_info (sqrt(||A||^2 - ||L||^2) / ||A||), which needs
+ * orthonormal Q and P.  Errors: EINVAL; ENOMEM. */
+pbpqlp_status pbpqlp_residual(const void* A, int64_t lda, const void* Q, int64_t ldq, const double* L,
+                              int64_t ldl, const void* P, int64_t ldp, int64_t m, int64_t n, int l,
+                              pbpqlp_dtype dt, double* d_r, void* stream);
+
 /* ---- single steps of the method, for validation against the oracle ---- */
 
 /* The sketch matrix of eq. (c) / Algorithm 1 (randn): Omega (n x l, row-major,
  * ldo >= l) in dtype dt; element (i, j) is the Box-Muller normal of flat index
- * i*l + j under `seed`, rounded to bfloat16 with |x| < 2^-14 flushed to 0. */
+ * i*l + j under `seed`, rounded to bfloat16 with |x| < 2^-14 flushed to 0.
+ * Runs the factorization's own generator (into stream-ordered scratch) and
+ * copies it out.  Errors: EINVAL; EUNSUPPORTED for l > 256; ENOMEM. */
 pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt,
                            void* Omega, int64_t ldo, void* stream);
 
@@ -232,6 +256,46 @@ void pbpqlp_batch_destroy(pbpqlp_batch* b);
 /* create + run + synchronize `stream` + destroy. */
 pbpqlp_status pbpqlp_factor_batched(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
                                     const pbpqlp_opts* opts, void* stream);
+
+/* ---- autotuning of the launch plan per shape class ----
+ * A shape class is (dtype, the three pass precisions, l rounded up to 32,
+ * ceil(log2 m), ceil(log2 n), batched or not); its plan is the contraction
+ * split of the A-streaming passes and the Gram workgroup target.  The tuners
+ * time candidate plans on `stream` (one warm-up and the median of three runs
+ * each, HIP events), synchronize, and store the fastest in a process-wide
+ * cache that calls with automatic options consult.  Workspace sizes depend on
+ * the plan: query pbpqlp_workspace_size after tuning. */
+typedef struct {
+  int split_k;              /* -1 = the built-in heuristic, else the forced split     */
+  int gram_workgroups;
+  double ms;                /* measured time of the plan (one call or one batch run) */
+} pbpqlp_tune_plan;
+
+/* Tune one problem's class by factorizing A (read only) with each of the
+ * candidate plans (split: heuristic, 1, 2, 4, 8, 16; Gram target: 512, 64,
+ * 256, 1024) into library-allocated outputs.  opts: precision plan (its split
+ * and Gram fields are ignored).  out may be NULL.  Errors: as pbpqlp_factor. */
+pbpqlp_status pbpqlp_tune_factor(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                                 int k, int p, int q, uint64_t seed, const pbpqlp_opts* opts,
+                                 pbpqlp_tune_plan* out, void* stream);
+/* Tune the Gram target of a batch (candidates 4, 16, 64, 256 workgroups per
+ * problem; the split is always 1) by creating and running a plan for each;
+ * the problems' outputs are overwritten.  The choice is stored for the class
+ * of problems[0], marked batched.  Errors: as pbpqlp_batch_create. */
+pbpqlp_status pbpqlp_tune_batch(int count, const pbpqlp_problem* problems, pbpqlp_dtype dt,
+                                const pbpqlp_opts* opts, pbpqlp_tune_plan* out, void* stream);
+/* The cached plan of a class (batched = 0 or 1); EINVAL if none is cached. */
+pbpqlp_status pbpqlp_tune_lookup(int64_t m, int64_t n, int k, int p, pbpqlp_dtype dt,
+                                 const pbpqlp_opts* opts, int batched, pbpqlp_tune_plan* out);
+/* Forget every cached plan. */
+void pbpqlp_tune_clear(void);
+/* Write the cache as text: a header line "# pbpqlp autotune v1 ...", then one
+ * line per class: dt sketch power proj lp32 log2m log2n batched split_k
+ * gram_workgroups ms.  Errors: EINVAL if the file cannot be written. */
+pbpqlp_status pbpqlp_tune_save(const char* path);
+/* Merge a file written by pbpqlp_tune_save into the cache (all or nothing).
+ * Errors: EINVAL if the file cannot be read or a line does not parse. */
+pbpqlp_status pbpqlp_tune_load(const char* path);
 
 /* ---- learned choice of q and k (project extension; the paper has none) ----
  *
@@ -325,12 +389,16 @@ typedef struct {
  *   (pbpqlp_factor_sketch with Omega = the current P), 2 passes per iteration;
  *   the answer is the rank-(k_hat + p) leading part of the l = 64
  *   factorization: Q and P cut to their first k_hat + p columns and L to its
- *   leading block (A ~= Q' L'^T P'^T; since Q'^T A P' = L'^T, its residual is
- *   sqrt(||A||^2 - ||L'||^2) / ||A||, which is the estimate checked);
- *   if that estimate exceeds tau (or a non-finite input was flagged) the
- *   fallback continues to q = 3 (when q_hat < 3) and returns k = k_max.
+ *   leading block (A ~= Q' L'^T P'^T);
+ *   its residual is checked against tau by the estimate
+ *   sqrt(||A||^2 - ||L'||^2) / ||A|| (exact for orthonormal factors, since
+ *   Q'^T A P' = L'^T); for FP32, whose estimate carries an error of order
+ *   1e-3, an estimate closer to tau than its error bound (2 sqrt(m + n) FP32
+ *   units on r^2) is replaced by the explicit pbpqlp_residual pass;
+ *   if it exceeds tau (or a non-finite input was flagged) the fallback
+ *   continues to q = 3 (when q_hat < 3) and returns k = k_max.
  * A plain run with q iterations costs 2 q + 2 passes; this path costs
- * 2 max(q_hat, 1 if fell back then 3) + 2, the probe included.
+ * 2 q_used + 2, the probe included, plus one pass per explicit check.
  *   A, dt, lda, seed, opts as for pbpqlp_factor (opts.workspace is ignored);
  *   requires min(m, n) >= 64, 1 <= k_max and k_max + p <= 64.
  *   Q (m x (k_used + p), ldq >= k_max + p), L ((k_used + p)^2, ldl >= k_max + p),

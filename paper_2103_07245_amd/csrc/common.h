@@ -64,6 +64,25 @@ __device__ __forceinline__ double normal_at(uint64_t t, uint32_t s2, uint32_t s3
   return (e & 1) ? r * sin(th) : r * cos(th);
 }
 
+// All four normals of Philox block `blk` in stream (s2, s3): the same values
+// normal_at gives for t = 4 blk + e, e = 0..3, with one generator call and one
+// logarithm and square root per Box-Muller pair.
+__device__ __forceinline__ void normals4_at(uint64_t blk, uint32_t s2, uint32_t s3, uint64_t seed,
+                                            double out[4]) {
+  uint32_t c0 = (uint32_t)blk, c1 = (uint32_t)(blk >> 32), c2 = s2, c3 = s3;
+  philox4x32_10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const double s = 2.3283064365386962890625e-10;  // 2^-32
+  const uint32_t xa[2] = {c0, c2}, xb[2] = {c1, c3};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double ua = ((double)xa[h] + 0.5) * s, ub = ((double)xb[h] + 0.5) * s;
+    const double r = sqrt(-2.0 * log(ua));
+    const double th = 6.283185307179586 * ub;
+    out[2 * h] = r * cos(th);
+    out[2 * h + 1] = r * sin(th);
+  }
+}
+
 // Round a double to the nearest bfloat16 value (ties to even), kept as double.
 __device__ __forceinline__ double bf16_rne_f64(double x) {
   uint64_t b = (uint64_t)__double_as_longlong(x);

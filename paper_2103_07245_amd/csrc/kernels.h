@@ -33,8 +33,7 @@ int stream_kc(int mode);
 hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot,
                            int64_t ld, hipStream_t s);
 // Omega row-major n x l (ldo)
-hipError_t launch_omega_rm(bool f64, int64_t n, int l, uint64_t seed, void* O, int64_t ldo,
-                           hipStream_t s);
+
 // FP32 column-major operand -> compute type (mode BF16/FP16/BF16X3), zero padded
 hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int l, int lp32,
                           float scale, void* hi, void* lo, hipStream_t s);

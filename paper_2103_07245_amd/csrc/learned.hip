@@ -489,7 +489,7 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
   const size_t szQ = (size_t)m * LP * el, szP = (size_t)n * LP * el, szL = (size_t)LP * LP * 8;
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t one = up(szQ) + up(szP) + up(szL);
-  const size_t total = 2 * one + up(NI * 4) + up(NO * 4) + up(sizeof(pbpqlp_info));
+  const size_t total = 2 * one + up(NI * 4) + up(NO * 4) + up(sizeof(pbpqlp_info)) + up(8);
   char* scratch = nullptr;
   if (hipMallocAsync((void**)&scratch, total, st) != hipSuccess) return PBPQLP_ENOMEM;
   struct Free {
@@ -509,6 +509,12 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
   float* f = (float*)(scratch + 2 * one);
   float* z = (float*)(scratch + 2 * one + up(NI * 4));
   pbpqlp_info* dinf = (pbpqlp_info*)(scratch + 2 * one + up(NI * 4) + up(NO * 4));
+  double* dres = (double*)((char*)dinf + up(sizeof(pbpqlp_info)));
+  // FP32 factors leave sqrt(||A||^2 - ||L'||^2) with an error of order 1e-3
+  // (||L'||^2 carries the products' FP32 rounding), so an FP32 answer whose
+  // estimate lies within that error of tau is judged by the explicit residual
+  // pass instead (one more pass over A)
+  const bool explicit_check = dt == PBPQLP_F32;
 
   pbpqlp_auto_result r{};
   int cur = 0, qcur = 0, flags = 0, ndep = 0;
@@ -561,6 +567,20 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
     const double a2 = hi.norm_a_fro2;
     *out = a2 > 0.0 ? std::sqrt(std::fmax(a2 - s2, 0.0) / a2) : 0.0;
     *nl2 = s2;
+    // FP32: the estimate decides when it is farther from tau than its error
+    // bound on r^2 (2 sqrt(m + n) units of FP32 rounding); otherwise the
+    // explicit pass decides
+    const double r2 = a2 > 0.0 ? (a2 - s2) / a2 : 0.0;
+    const double bound = 2.0 * std::sqrt((double)(m + n)) * 5.9604644775390625e-8;
+    const bool decided = r2 + bound <= tau * tau || r2 - bound > tau * tau;
+    if (explicit_check && !decided) {
+      pbpqlp_status s3 = pbpqlp_residual(A, lda, Qb[cur], LP, Lb[cur], LP, Pb[cur], LP, m, n, lt, dt, dres,
+                                         stream);
+      if (s3) return s3;
+      PBQ_TRY(hipMemcpyAsync(out, dres, sizeof(double), hipMemcpyDeviceToHost, st));
+      PBQ_TRY(hipStreamSynchronize(st));
+      r.passes += 1;
+    }
     flags |= hi.status_flags;
     ndep += hi.n_dependent;
     return PBPQLP_OK;

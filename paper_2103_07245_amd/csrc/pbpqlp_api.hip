@@ -17,6 +17,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
+#include "tune.h"
 
 using namespace pbq;
 
@@ -242,7 +243,7 @@ bool valid_args(int64_t m, int64_t n, int k, int p, int q) {
 }
 
 pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, int k, int p,
-                    int q, const pbpqlp_opts* opts) {
+                    int q, const pbpqlp_opts* opts, bool batched = false) {
   if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
   if (!valid_args(m, n, k, p, q) || lda < n) return PBPQLP_EINVAL;
   const int l = k + p;
@@ -261,9 +262,17 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
   c.mode_proj = resolve_mode(dt, o.proj_prec, &ok3);
   if (!ok1 || !ok2 || !ok3) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
   c.fp16_scale = (float)(o.fp16_scale_a > 0 ? o.fp16_scale_a : 1.0);
-  c.forced_split = o.split_k;
-  if (o.split_k < 0 || o.gram_workgroups < 0) return PBPQLP_EINVAL;
-  if (o.gram_workgroups > 0) c.gram_target = o.gram_workgroups;
+  if (o.split_k < -1 || o.gram_workgroups < 0) return PBPQLP_EINVAL;
+  int split = o.split_k, gram = o.gram_workgroups;
+  if (!batched && (split == 0 || gram == 0)) {
+    TunePlan t;
+    if (tune_lookup(tune_key((int)dt, o.sketch_prec, o.power_prec, o.proj_prec, l, m, n, false), &t)) {
+      if (split == 0) split = t.split_k;
+      if (gram == 0) gram = t.gram_wg;
+    }
+  }
+  c.forced_split = split > 0 ? split : 0;
+  if (gram > 0) c.gram_target = gram;
   c.plan_buffers(true, q > 0, q > 0, true);
   return PBPQLP_OK;
 }
@@ -617,7 +626,18 @@ pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt, voi
                            int64_t ldo, void* stream) {
   if (!Omega || n < 1 || l < 1 || ldo < l) return PBPQLP_EINVAL;
   if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
-  PBQ_CHECK(launch_omega_rm(dt == PBPQLP_F64, n, l, seed, Omega, ldo, (hipStream_t)stream));
+  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  const bool f64 = dt == PBPQLP_F64;
+  if (!aligned(Omega, f64 ? 8 : 4)) return PBPQLP_EINVAL;
+  // the factorization's own generator (column-major), then the caller's layout
+  hipStream_t st = (hipStream_t)stream;
+  const int lp32 = (int)rup(l, 32);
+  const int64_t ld = rup(n, 64);
+  ScratchGuard g;
+  pbpqlp_status s = alloc_scratch(g, (size_t)lp32 * ld * (f64 ? 8 : 4), st);
+  if (s) return s;
+  PBQ_CHECK(launch_omega_cm(f64, n, l, lp32, seed, g.p, ld, st));
+  PBQ_CHECK(launch_cm_to_rm(f64, g.p, ld, n, l, Omega, ldo, st));
   return PBPQLP_OK;
 }
 
@@ -814,11 +834,20 @@ pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbp
   std::vector<Ctx> ctx((size_t)count);
   std::vector<size_t> off((size_t)count);
   size_t total = 0;
+  // a batch tuned for the class of its first problem
+  int tuned_gram = 0;
+  if (o.gram_workgroups == 0) {
+    TunePlan t;
+    const pbpqlp_problem& p0 = problems[0];
+    if (tune_lookup(tune_key((int)dt, o.sketch_prec, o.power_prec, o.proj_prec, p0.k + p0.p, p0.m,
+                             p0.n, true), &t))
+      tuned_gram = t.gram_wg;
+  }
   for (int i = 0; i < count; ++i) {
     const pbpqlp_problem& pr = problems[i];
     if (!pr.A || !pr.Q || !pr.L || !pr.P) return PBPQLP_EINVAL;
     Ctx& c = ctx[(size_t)i];
-    pbpqlp_status s = setup(c, pr.m, pr.n, pr.lda, dt, pr.k, pr.p, pr.q, &o);
+    pbpqlp_status s = setup(c, pr.m, pr.n, pr.lda, dt, pr.k, pr.p, pr.q, &o, true);
     if (s) return s;
     if (pr.ldq < c.l || pr.ldl < c.l || pr.ldp < c.l) return PBPQLP_EINVAL;
     if (pr.Q == pr.A || pr.P == pr.A || pr.Q == pr.P) return PBPQLP_EINVAL;
@@ -826,7 +855,7 @@ pbpqlp_status pbpqlp_batch_create(int count, const pbpqlp_problem* problems, pbp
         !aligned(pr.L, 8))
       return PBPQLP_EINVAL;
     c.seed = pr.seed;
-    if (o.gram_workgroups == 0) c.gram_target = batch_gram_target(count);
+    if (o.gram_workgroups == 0) c.gram_target = tuned_gram > 0 ? tuned_gram : batch_gram_target(count);
     Bump sizer;
     c.carve(sizer, needs16(c));
     sizer.take(sizeof(pbpqlp_info));

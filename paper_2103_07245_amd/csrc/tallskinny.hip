@@ -32,49 +32,52 @@ struct OmegaP {
   PBQ_GRID;
 };
 
+// One block per kOmegaRows rows of Omega: every Philox block that touches those
+// rows is generated once (four normals per call), staged row-major in LDS and
+// written column-major with rows contiguous; padding rows and columns get 0.
+constexpr int kOmegaRows = 32;
+
 template <typename T, bool B>
-__global__ void omega_cm_kernel(const OmegaP* pb, OmegaP ps) {
+__global__ __launch_bounds__(256) void omega_cm_kernel(const OmegaP* pb, OmegaP ps) {
   bool past;
   const OmegaP p = kparams<B>(pb, ps, past);
   if (past) return;
-  const int c = blockIdx.y;
-  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  __shared__ T tile[kOmegaRows * kMaxL];
+  const int64_t i0 = (int64_t)blockIdx.x * kOmegaRows;
   if (i0 >= p.ld) return;
-  T* Ot = (T*)p.Ot;
+  const int64_t rows = min((int64_t)kOmegaRows, max((int64_t)0, p.n - i0));
+  const uint64_t t0 = (uint64_t)i0 * (uint64_t)p.l;
+  const uint64_t t1 = t0 + (uint64_t)rows * (uint64_t)p.l;   // flat indices [t0, t1)
+  if (t1 > t0) {
+    const uint64_t b0 = t0 >> 2, b1 = (t1 + 3) >> 2;
+    for (uint64_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+      double v[4];
+      normals4_at(b, 0u, 0u, p.seed, v);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t i = i0 + e;
-    T v = 0;
-    if (c < p.l && i < p.n) v = (T)omega_elem(i, c, p.l, p.seed);
-    if (i < p.ld) Ot[(int64_t)c * p.ld + i] = v;
+      for (int e = 0; e < 4; ++e) {
+        const uint64_t t = 4 * b + e;
+        if (t >= t0 && t < t1) tile[t - t0] = (T)sketch_value(v[e]);
+      }
+    }
   }
-}
-
-template <typename T>
-__global__ void omega_rm_kernel(int64_t n, int l, uint64_t seed, T* __restrict__ O, int64_t ldo) {
-  const int64_t i = blockIdx.y;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= l || i >= n) return;
-  O[i * ldo + c] = (T)omega_elem(i, c, l, seed);
+  __syncthreads();
+  T* Ot = (T*)p.Ot;
+  for (int q = threadIdx.x; q < p.lp32 * kOmegaRows; q += blockDim.x) {
+    const int c = q / kOmegaRows, r = q % kOmegaRows;
+    const int64_t i = i0 + r;
+    if (i >= p.ld) continue;
+    Ot[(int64_t)c * p.ld + i] = (c < p.l && r < rows) ? tile[r * p.l + c] : T(0);
+  }
 }
 
 hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot,
                            int64_t ld, hipStream_t s) {
-  dim3 grid((unsigned)((ld / 4 + 255) / 256), (unsigned)lp32);
+  dim3 grid((unsigned)((ld + kOmegaRows - 1) / kOmegaRows));
   OmegaP p{n, l, lp32, seed, Ot, ld};
   if (f64) return launch_k(omega_cm_kernel<double, false>, omega_cm_kernel<double, true>, grid, dim3(256), s, p);
   return launch_k(omega_cm_kernel<float, false>, omega_cm_kernel<float, true>, grid, dim3(256), s, p);
 }
 
-hipError_t launch_omega_rm(bool f64, int64_t n, int l, uint64_t seed, void* O, int64_t ldo,
-                           hipStream_t s) {
-  dim3 grid((unsigned)((l + 63) / 64), (unsigned)n);
-  if (f64)
-    hipLaunchKernelGGL(omega_rm_kernel<double>, grid, dim3(64), 0, s, n, l, seed, (double*)O, ldo);
-  else
-    hipLaunchKernelGGL(omega_rm_kernel<float>, grid, dim3(64), 0, s, n, l, seed, (float*)O, ldo);
-  return hipGetLastError();
-}
 
 // ---------------------------------------------------------------------------
 // FP32 operand -> 16-bit compute type (hi, and lo = x - hi for BF16X3).

@@ -73,6 +73,10 @@ class AutoResult(ctypes.Structure):
                 ("resid_first", ctypes.c_double), ("resid_final", ctypes.c_double)]
 
 
+class TunePlanStruct(ctypes.Structure):
+    _fields_ = [("split_k", ctypes.c_int), ("gram_workgroups", ctypes.c_int), ("ms", ctypes.c_double)]
+
+
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 64, 128, 6, 25606
 PROBE_K, PROBE_P = 56, 8
 
@@ -153,6 +157,25 @@ def _lib():
         lib.pbpqlp_factor_auto.argtypes = [vp, vp, i64, i64, i64, i32, i32, u64, i32, ctypes.c_double,
                                            vp, i64, dp, i64, vp, i64, ctypes.POINTER(Opts), vp,
                                            ctypes.POINTER(AutoResult), vp]
+        lib.pbpqlp_reconstruct.restype = i32
+        lib.pbpqlp_reconstruct.argtypes = [vp, i64, dp, i64, vp, i64, i64, i64, i32, i32, vp, i64, vp]
+        lib.pbpqlp_residual.restype = i32
+        lib.pbpqlp_residual.argtypes = [vp, i64, vp, i64, dp, i64, vp, i64, i64, i64, i32, i32, vp, vp]
+        tp = ctypes.POINTER(TunePlanStruct)
+        lib.pbpqlp_tune_factor.restype = i32
+        lib.pbpqlp_tune_factor.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, u64,
+                                           ctypes.POINTER(Opts), tp, vp]
+        lib.pbpqlp_tune_batch.restype = i32
+        lib.pbpqlp_tune_batch.argtypes = [i32, ctypes.POINTER(ProblemStruct), i32, ctypes.POINTER(Opts),
+                                          tp, vp]
+        lib.pbpqlp_tune_lookup.restype = i32
+        lib.pbpqlp_tune_lookup.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(Opts), i32, tp]
+        lib.pbpqlp_tune_clear.restype = None
+        lib.pbpqlp_tune_clear.argtypes = []
+        lib.pbpqlp_tune_save.restype = i32
+        lib.pbpqlp_tune_save.argtypes = [ctypes.c_char_p]
+        lib.pbpqlp_tune_load.restype = i32
+        lib.pbpqlp_tune_load.argtypes = [ctypes.c_char_p]
         lib.pbpqlp_trace_enable.argtypes = [i32]
         lib.pbpqlp_trace_reset.argtypes = []
         lib.pbpqlp_trace_count.restype = i32
@@ -308,6 +331,32 @@ def factor_sketch(A: torch.Tensor, Omega: torch.Tensor, k: int, p: int, q: int, 
     return Q, L, P, Info.from_device(info)
 
 
+def reconstruct(Q: torch.Tensor, L: torch.Tensor, P: torch.Tensor) -> torch.Tensor:
+    """A_hat = Q L^T P^T on the device (pbpqlp_reconstruct)."""
+    Q, P = _rowmajor(Q, "Q"), _rowmajor(P, "P")
+    L = L.contiguous()
+    m, l = Q.shape
+    n = P.shape[0]
+    Ah = torch.empty((m, n), dtype=Q.dtype, device=Q.device)
+    _check(_lib().pbpqlp_reconstruct(ctypes.c_void_p(Q.data_ptr()), Q.stride(0), ctypes.c_void_p(L.data_ptr()),
+                                     L.stride(0), ctypes.c_void_p(P.data_ptr()), P.stride(0), m, n, l, _dt(Q),
+                                     ctypes.c_void_p(Ah.data_ptr()), n, _stream(Q.device)), "pbpqlp_reconstruct")
+    return Ah
+
+
+def residual(A: torch.Tensor, Q: torch.Tensor, L: torch.Tensor, P: torch.Tensor) -> float:
+    """Explicit ||A - Q L^T P^T||_F / ||A||_F on the device (pbpqlp_residual)."""
+    A, Q, P = _rowmajor(A, "A"), _rowmajor(Q, "Q"), _rowmajor(P, "P")
+    L = L.contiguous()
+    m, n = A.shape
+    r = torch.empty(1, dtype=torch.float64, device=A.device)
+    _check(_lib().pbpqlp_residual(ctypes.c_void_p(A.data_ptr()), A.stride(0), ctypes.c_void_p(Q.data_ptr()),
+                                  Q.stride(0), ctypes.c_void_p(L.data_ptr()), L.stride(0),
+                                  ctypes.c_void_p(P.data_ptr()), P.stride(0), m, n, Q.shape[1], _dt(A),
+                                  ctypes.c_void_p(r.data_ptr()), _stream(A.device)), "pbpqlp_residual")
+    return float(r.item())
+
+
 def omega(n: int, l: int, seed: int, dtype=torch.float64, device="cuda") -> torch.Tensor:
     out = torch.empty((n, l), dtype=dtype, device=device)
     _check(_lib().pbpqlp_omega(n, l, ctypes.c_uint64(seed), _dt(out), ctypes.c_void_p(out.data_ptr()),
@@ -423,6 +472,7 @@ class Batch:
             pr.P = self.P[i].data_ptr(); pr.ldp = self.ls[i]
             pr.info = self.info_buf[i].data_ptr()
         opts = make_opts(plan, gram_wg=gram_wg)
+        self._probs, self._opts = probs, opts
         handle = ctypes.c_void_p()
         _check(_lib().pbpqlp_batch_create(cnt, probs, _dt(self.mats[0]), ctypes.byref(opts),
                                           ctypes.byref(handle)), "pbpqlp_batch_create")
@@ -442,6 +492,15 @@ class Batch:
         ws = ctypes.c_size_t(0)
         _check(_lib().pbpqlp_batch_stats(self._h, ctypes.byref(n), ctypes.byref(ws)), "pbpqlp_batch_stats")
         return {"launches": n.value, "workspace_bytes": ws.value}
+
+    def tune(self) -> dict:
+        """pbpqlp_tune_batch over this batch's problems (their outputs are
+        overwritten); later batches of the same class with an automatic Gram
+        target use the choice.  This plan keeps its own."""
+        t = TunePlanStruct()
+        _check(_lib().pbpqlp_tune_batch(self.count, self._probs, _dt(self.mats[0]), ctypes.byref(self._opts),
+                                        ctypes.byref(t), _stream(self.device)), "pbpqlp_tune_batch")
+        return {"split_k": t.split_k, "gram_wg": t.gram_workgroups, "ms": t.ms}
 
     def problem_plan(self, i: int):
         """(split_k, gram_wg) the plan uses for problem i: factor() with these
@@ -612,3 +671,41 @@ def factor_auto(model: Model, A: torch.Tensor, p: int, seed: int, k_max: int, ta
     l = res.k_used + p
     r = {f: getattr(res, f) for f, _ in AutoResult._fields_}
     return Q[:, :l], L[:l, :l], P[:, :l], r, Info.from_device(info)
+
+
+# ---------------------------------------------------------------------------
+# Autotuning
+# ---------------------------------------------------------------------------
+def tune_factor(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native") -> dict:
+    """pbpqlp_tune_factor: time the candidate plans on A and cache the fastest
+    for A's shape class; returns {split_k, gram_wg, ms}."""
+    A = _rowmajor(A, "A")
+    t = TunePlanStruct()
+    o = make_opts(plan)
+    _check(_lib().pbpqlp_tune_factor(ctypes.c_void_p(A.data_ptr()), A.shape[0], A.shape[1], A.stride(0),
+                                     _dt(A), k, p, q, ctypes.c_uint64(seed), ctypes.byref(o),
+                                     ctypes.byref(t), _stream(A.device)), "pbpqlp_tune_factor")
+    return {"split_k": t.split_k, "gram_wg": t.gram_workgroups, "ms": t.ms}
+
+
+def tune_lookup(m: int, n: int, k: int, p: int, dtype=torch.float32, plan="native", batched=False):
+    """The cached plan of a shape class, or None."""
+    t = TunePlanStruct()
+    o = make_opts(plan)
+    st = _lib().pbpqlp_tune_lookup(m, n, k, p, F64 if dtype == torch.float64 else F32, ctypes.byref(o),
+                                   1 if batched else 0, ctypes.byref(t))
+    if st != OK:
+        return None
+    return {"split_k": t.split_k, "gram_wg": t.gram_workgroups, "ms": t.ms}
+
+
+def tune_clear():
+    _lib().pbpqlp_tune_clear()
+
+
+def tune_save(path):
+    _check(_lib().pbpqlp_tune_save(os.fsencode(str(path))), "pbpqlp_tune_save")
+
+
+def tune_load(path):
+    _check(_lib().pbpqlp_tune_load(os.fsencode(str(path))), "pbpqlp_tune_load")

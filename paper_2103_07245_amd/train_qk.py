@@ -25,6 +25,7 @@ Features come from the probe of the same matrix stored in FP32.
 from __future__ import annotations
 
 import argparse
+import json
 import math
 import os
 import sys
@@ -108,7 +109,7 @@ def label_matrix(A64: torch.Tensor, sigma: np.ndarray, seed: int, plan="native")
 
 
 def make_dataset(count: int, seed: int, device, m_range=(512, 2048), n_range=(512, 2048),
-                 rank_cap: int = 256, log=_log):
+                 rank_cap: int = 256, log=_log, checkpoint=None):
     X = np.zeros((count, B.MLP_IN), dtype=np.float32)
     qs = np.zeros(count, dtype=np.int32)
     ks = np.zeros(count, dtype=np.int32)
@@ -125,6 +126,9 @@ def make_dataset(count: int, seed: int, device, m_range=(512, 2048), n_range=(51
         if (i + 1) % 128 == 0 or i + 1 == count:
             log(f"  {i + 1}/{count} matrices labelled ({time.time() - t0:.0f} s); "
                 f"q* histogram {np.bincount(qs[:i + 1], minlength=5).tolist()}")
+        if checkpoint and ((i + 1) % 1024 == 0):
+            checkpoint({"X": X[:i + 1], "q": qs[:i + 1], "k": ks[:i + 1], "r_q": rq[:i + 1],
+                        "r_opt": ro[:i + 1], "family": np.array(fams)})
     return {"X": X, "q": qs, "k": ks, "r_q": rq, "r_opt": ro, "family": np.array(fams)}
 
 
@@ -135,6 +139,39 @@ def evaluate(model: B.Model, X: np.ndarray, q: np.ndarray, k: np.ndarray, device
     kh = np.clip(np.floor(np.exp(np.minimum(Z[:, 5], 30.0)) + 0.5), 1, K_MAX)
     return {"q_acc": float(np.mean(qh == q)), "q_safe": float(np.mean(qh >= q)),
             "logk_mae": float(np.mean(np.abs(np.log(kh) - np.log(k))))}
+
+
+def expected_passes(q_hat: np.ndarray, q_true: np.ndarray) -> np.ndarray:
+    """Passes over A that pbpqlp_factor_auto spends for a prediction, counting
+    one residual check per answer: 2 q_hat + 3 when q_hat >= q* or q_hat >= 3
+    (no fallback), else 10 (the fallback to q = 3 and a second check)."""
+    ok = q_hat >= q_true
+    return np.where(ok, 2 * q_hat + 3, np.where(q_hat < 3, 10, 2 * q_hat + 3))
+
+
+def calibrate(model: B.Model, X: np.ndarray, q: np.ndarray, device, log=_log):
+    """Cost-sensitive calibration of the five q logits: offsets d_q added to
+    the output biases (so q_hat stays the argmax of the network's logits)
+    chosen by coordinate descent to minimize the expected passes on held-out
+    samples.  Returns a new model with the shifted biases."""
+    Z = model.forward(torch.as_tensor(X, device=device)).cpu().numpy().astype(np.float64)[:, :5]
+    d = np.zeros(5)
+    cost = lambda dd: float(np.mean(expected_passes(np.argmax(Z + dd, axis=1), q)))
+    best = cost(d)
+    base = best
+    grid = np.linspace(-4.0, 4.0, 81)
+    for _ in range(4):
+        for c in range(1, 5):
+            for g in grid:
+                t = d.copy()
+                t[c] = g
+                v = cost(t)
+                if v < best - 1e-12:
+                    best, d = v, t
+    theta = model.params().astype(np.float64)
+    theta[-6:-1] += d
+    log(f"  calibration offsets {np.round(d, 2).tolist()}: expected passes {base:.3f} -> {best:.3f}")
+    return B.Model(theta.astype(np.float32), device=device), d
 
 
 def train(data: dict, epochs: int, batch: int, lr: float, seed: int, device, val_frac=0.125,
@@ -168,6 +205,19 @@ def train(data: dict, epochs: int, batch: int, lr: float, seed: int, device, val
             hist.append({"epoch": ep + 1, "train_loss": tr, **ev})
             log(f"  epoch {ep + 1}: train loss {tr:.4f}  val q acc {ev['q_acc']:.3f}  "
                 f"q_hat>=q* {ev['q_safe']:.3f}  |dln k| {ev['logk_mae']:.3f}")
+    # calibrate on the first half of the held-out samples, report on the second
+    half = ntr + nval // 2
+    steps_done = model.steps
+    model, offs = calibrate(model, X[ntr:half], q[ntr:half], device, log)
+    ev = evaluate(model, X[half:], q[half:], k[half:], device)
+    Z = model.forward(torch.as_tensor(X[half:], device=device)).cpu().numpy()
+    ev["expected_passes"] = float(np.mean(expected_passes(np.argmax(Z[:, :5], axis=1), q[half:])))
+    ev["expected_passes_oracle_q"] = float(np.mean(expected_passes(q[half:], q[half:])))
+    ev["calibration_offsets"] = offs.tolist()
+    ev["adam_steps"] = steps_done
+    hist.append({"epoch": "calibrated", **ev})
+    log(f"  calibrated: q acc {ev['q_acc']:.3f}  q_hat>=q* {ev['q_safe']:.3f}  expected passes "
+        f"{ev['expected_passes']:.3f} (exact q*: {ev['expected_passes_oracle_q']:.3f}, plain q=3: 8)")
     return model, hist
 
 
@@ -181,7 +231,7 @@ def main(argv=None):
     d.add_argument("--m-max", type=int, default=2048)
     d.add_argument("--out", required=True)
     t = sub.add_parser("train")
-    t.add_argument("--data", required=True)
+    t.add_argument("--data", required=True, nargs="+")
     t.add_argument("--epochs", type=int, default=400)
     t.add_argument("--batch", type=int, default=256)
     t.add_argument("--lr", type=float, default=2e-3)
@@ -191,18 +241,22 @@ def main(argv=None):
     dev = torch.device("cuda:0")
     if a.cmd == "data":
         t0 = time.time()
-        data = make_dataset(a.count, a.seed, dev, (a.m_min, a.m_max), (a.m_min, a.m_max))
+        data = make_dataset(a.count, a.seed, dev, (a.m_min, a.m_max), (a.m_min, a.m_max),
+                            checkpoint=lambda d: np.savez(a.out, **d))
         np.savez(a.out, **data)
         print(f"wrote {a.count} samples to {a.out} in {time.time() - t0:.0f} s", flush=True)
     else:
-        z = np.load(a.data, allow_pickle=False)
-        data = {key: z[key] for key in z.files}
+        parts = [np.load(f, allow_pickle=False) for f in a.data]
+        data = {key: np.concatenate([z[key] for z in parts]) for key in parts[0].files}
         t0 = time.time()
         model, hist = train(data, a.epochs, a.batch, a.lr, a.seed, dev)
         torch.cuda.synchronize()
         model.save(a.out)
-        print(f"trained {model.steps} Adam steps in {time.time() - t0:.1f} s; wrote {a.out}", flush=True)
+        print(f"trained {hist[-1]['adam_steps']} Adam steps on {len(data['q'])} samples in "
+              f"{time.time() - t0:.1f} s; wrote {a.out}", flush=True)
         print("final", hist[-1], flush=True)
+        with open(a.out + ".json", "w") as fh:
+            json.dump({"samples": int(len(data["q"])), "history": hist}, fh, indent=1)
 
 
 if __name__ == "__main__":

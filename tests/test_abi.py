@@ -145,3 +145,39 @@ def test_learned_entry_points_reject_null_arguments():
     assert lib.pbpqlp_factor_auto(None, None, 1000, 1000, 1000, B.F32, 8, 1, 56, 0.1, None, 64,
                                   None, 64, None, 64, None, None, ctypes.byref(res), None) == B.EINVAL
     assert B.MLP_PARAMS == 64 * 128 + 128 + 128 * 128 + 128 + 6 * 128 + 6
+
+
+def test_tune_cache_file_roundtrip(tmp_path):
+    B.tune_clear()
+    assert B.tune_lookup(1000, 800, 20, 5) is None
+    path = tmp_path / "tune.txt"
+    # two classes written by hand in the documented format
+    path.write_text("# pbpqlp autotune v1: dt sketch power proj lp32 log2m log2n batched split_k gram_wg ms\n"
+                    "1 0 0 0 32 10 10 0 4 256 1.25\n"
+                    "1 0 0 0 32 10 10 1 1 16 3.5\n")
+    B.tune_load(path)
+    # 1000 -> ceil(log2) = 10, 800 -> 10; l = 25 -> lp32 = 32
+    assert B.tune_lookup(1000, 800, 20, 5) == {"split_k": 4, "gram_wg": 256, "ms": 1.25}
+    assert B.tune_lookup(1000, 800, 20, 5, batched=True)["gram_wg"] == 16
+    assert B.tune_lookup(1025, 800, 20, 5) is None          # next size bucket
+    assert B.tune_lookup(1000, 800, 20, 5, plan="bf16") is None
+    out = tmp_path / "again.txt"
+    B.tune_save(out)
+    B.tune_clear()
+    assert B.tune_lookup(1000, 800, 20, 5) is None
+    B.tune_load(out)
+    assert B.tune_lookup(1000, 800, 20, 5)["split_k"] == 4
+    B.tune_clear()
+
+
+def test_tune_load_rejects_malformed_files(tmp_path):
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a tune file\n")
+    with pytest.raises(B.PbpqlpError):
+        B.tune_load(bad)
+    bad.write_text("# pbpqlp autotune v1\n1 0 0 0 32 10\n")
+    with pytest.raises(B.PbpqlpError):
+        B.tune_load(bad)
+    with pytest.raises(B.PbpqlpError):
+        B.tune_load(tmp_path / "missing.txt")
+    B.tune_clear()

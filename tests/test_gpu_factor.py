@@ -192,3 +192,26 @@ def test_paper_matrix4_rank100_band():
     Q, L, P, _ = _run(w.A, 100, 0, 2, w.seed)
     err = np.linalg.norm(w.A - Q @ L.T @ P.T, 2)
     assert 101.0 ** -2 * (1 - 1e-9) <= err <= 2 * 1.144e-4
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_reconstruct_and_explicit_residual(dtype):
+    """pbpqlp_reconstruct equals Q L^T P^T formed on the host, and
+    pbpqlp_residual equals the oracle's row-streamed FP64 residual of the same
+    factors (and, for orthonormal factors, the record's estimate)."""
+    from oracle import rel_residual
+    rng = synth.rng_for(303)
+    m, n, k, p = 333, 270, 14, 6
+    A = synth.planted(rng, m, n, 0.8 ** np.arange(120), 1e-7, np.float64).astype(
+        np.float64 if dtype == torch.float64 else np.float32)
+    At = torch.from_numpy(A).to(DEV)
+    Q, L, P, info = B.factor(At, k, p, 1, 17)
+    Ah = B.reconstruct(Q, L, P).cpu().numpy().astype(np.float64)
+    Qh, Lh, Ph = (x.cpu().numpy().astype(np.float64) for x in (Q, L, P))
+    ref = Qh @ Lh.T @ Ph.T
+    tol = 1e-13 if dtype == torch.float64 else 2e-6
+    assert np.abs(Ah - ref).max() <= tol * np.abs(ref).max()
+    r = B.residual(At, Q, L, P)
+    r_host = rel_residual(A.astype(np.float64), Qh, Lh, Ph)
+    assert abs(r - r_host) <= (1e-12 if dtype == torch.float64 else 1e-6)
+    assert abs(r - info.resid_rel_est) <= (1e-10 if dtype == torch.float64 else 1e-4)

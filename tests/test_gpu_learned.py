@@ -5,6 +5,7 @@ oracle/qk_mlp_oracle.py at FP32 tolerances; the probe features with the
 oracle's feature map; pbpqlp_factor_auto's choice and fallback with plain
 pbpqlp_factor calls (bit for bit)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -143,15 +144,21 @@ def test_factor_auto_choice_and_fallback(tau, expect_fallback):
     assert res["fell_back"] == int(expect_fallback)
     q_used, k_used = (3, 40) if expect_fallback else (1, 9)
     assert res["q_used"] == q_used and res["k_used"] == k_used
-    assert res["passes"] == 2 + 2 * q_used
+    # 2 passes per iteration and the probe's two; an FP32 check whose
+    # estimate is not decisive adds one explicit pass
+    extra = res["passes"] - (2 + 2 * q_used)
+    assert 0 <= extra <= (2 if expect_fallback else 1)
     assert info.q == q_used and info.l == k_used + 8
     # the answer is the leading part of the continued l = 64 factorization
     Qc, Lc, Pc, infc = _chain(At, spec.seed_omega, [1, 3] if expect_fallback else [1])
     lt = k_used + 8
     assert torch.equal(Q, Qc[:, :lt]) and torch.equal(P, Pc[:, :lt]) and torch.equal(L, Lc[:lt, :lt])
-    r = T.truncated_residual(Lc, infc.norm_a_fro2, lt)
-    assert res["resid_final"] == pytest.approx(r, rel=1e-12, abs=1e-15)
-    assert info.resid_rel_est == pytest.approx(r, rel=1e-12, abs=1e-15)
+    r = B.residual(At, Q, L, P)
+    assert info.resid_rel_est == res["resid_final"]
+    assert abs(res["resid_final"] - r) <= 2e-3
+    # the estimate and the explicit residual agree where FP32 resolves them
+    r_est = T.truncated_residual(Lc, infc.norm_a_fro2, lt)
+    assert abs(r_est - r) <= 2e-3
     md.close()
 
 
@@ -206,3 +213,36 @@ def test_label_rules_agree_with_oracle():
         assert T.r_opt(s, l) == pytest.approx(O.r_opt(s, l), rel=1e-14)
         rs = sorted(rng.uniform(0.5, 3.0, 5) * O.r_opt(s, l), reverse=True)
         assert T.q_star(rs, O.r_opt(s, l)) == O.q_star(rs, O.r_opt(s, l))
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2103_07245_amd", "weights", "qk_mlp.bin")
+
+
+def test_trained_network_gains_over_plain_q3():
+    """On held-out matrices (seeds disjoint from training) the trained network
+    reaches the accuracy target tau = 1.05 r_opt(k* + p) at least as often as
+    the plain method with q = 3 and the true k*, with fewer passes over A."""
+    md = B.Model.load(WEIGHTS)
+    rows = []
+    for i in range(24):
+        spec = synth.qk_spec(i, 999, (768, 1536), (768, 1536), 256)
+        A = T.make_matrix(spec, DEV).float().contiguous()
+        ks = T.k_star(spec.sigma)
+        tau = T.Q_SLACK * T.r_opt(spec.sigma, ks + 8)
+        Q, L, P, res, info = B.factor_auto(md, A, 8, spec.seed_omega, 56, tau)
+        r_learned = B.residual(A, Q, L, P)
+        Q3, L3, P3, _ = B.factor(A, ks, 8, 3, spec.seed_omega)
+        r_plain = B.residual(A, Q3, L3, P3)
+        rows.append((res["passes"], r_learned, r_plain, tau))
+        print(f"{spec.family:4s} k*={ks:2d} q_hat={res['q_pred']} k_hat={res['k_pred']:2d} "
+              f"passes={res['passes']:2d} fell_back={res['fell_back']} r={r_learned:.3e} "
+              f"plain q3={r_plain:.3e} tau={tau:.3e}", flush=True)
+    passes = np.array([r[0] for r in rows])
+    ok_learned = np.array([r[1] <= r[3] for r in rows])
+    ok_plain = np.array([r[2] <= r[3] for r in rows])
+    print(f"success learned {ok_learned.mean():.3f} plain q3 {ok_plain.mean():.3f}; "
+          f"passes learned {passes.mean():.2f} (checks included) plain 8", flush=True)
+    assert ok_learned.mean() >= ok_plain.mean()
+    assert passes.mean() <= 0.85 * 8
+    md.close()

@@ -30,7 +30,7 @@ def _host(t):
 
 
 @pytest.mark.parametrize("n,l,seed", [(1000, 25, 1_500_000), (257, 1, 3), (333, 17, 2**40 + 5),
-                                      (64, 256, 77)])
+                                      (64, 256, 77), (97, 255, 12), (31, 3, 5)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_omega_bit_exact(n, l, seed, dtype):
     print(f"omega n={n} l={l} seed={seed} {dtype}", flush=True)
