@@ -449,6 +449,263 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
 }
 
 // ---------------------------------------------------------------------------
+// K1 (Y = A X) with two stages of A in flight per wave.  Rows of A are
+// 16-byte aligned; each stage's A tile of a wave is NAR 16-byte loads per
+// lane.  Even stages land in registers; odd stages go from HBM straight into
+// a per-wave LDS slot (global_load_lds, no register cost) and are read back
+// when used.  The steady state (all stages full) runs two stages per
+// iteration as straight-line code, so the wait counts stay exact: a wave
+// waits for the stage it is about to use, never for the one behind it.
+// Stage barriers order only LDS (the X ring); the slot is private to its
+// wave and guarded by that wave's own vmcnt / lgkmcnt waits.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ring_barrier() {
+  // LDS writes of this wave complete, then the workgroup barrier; no wait on
+  // vector memory (the next stages' loads stay in flight)
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int MODE, int NT, bool NORM, bool B>
+__global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const StreamParams* pb,
+                                                                       StreamParams ps) {
+  bool past;
+  const StreamParams p = kparams<B>(pb, ps, past);
+  if (past) return;
+  typedef Tr<MODE> TR;
+  typedef typename TR::TA TA;
+  typedef typename TR::TC TC;
+  typedef typename TR::TACC TACC;
+  typedef typename AccOf<TACC>::type ACC;
+  constexpr int V = TR::V, KS = 4 * V, KC = 2 * KS, RT = TR::RT;
+  static_assert(TR::XN == 1, "split-BF16x3 keeps the general kernel");
+  constexpr int NW = TR::NW, NTH = 64 * NW;
+  constexpr int XCH = (NT * 128 + NTH - 1) / NTH;
+  constexpr int EA = 16 / (int)sizeof(TA);
+  constexpr int NLA = (V * (int)sizeof(TA)) / 16;
+  constexpr int NAR = 2 * RT * NLA;
+  static_assert(NLA <= 2, "a fragment is at most two 16-byte loads");
+  // every thread moves XCH chunks; chunks past the NT * 16 live columns re-read
+  // the last column into padding columns of the ring (no divergent branch)
+  constexpr int XCOLS = XCH * NTH / 8;
+  __shared__ __attribute__((aligned(16))) char xs[2][XCOLS * kPitch];
+  __shared__ __attribute__((aligned(16))) u32x4 aslot[NW * NAR * 64];
+
+  const TA* __restrict__ A = (const TA*)p.A;
+  const TC* __restrict__ Xc = (const TC*)p.X;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  u32x4* const myslot = &aslot[wave * NAR * 64];
+  const int64_t a0 = ((int64_t)blockIdx.x * NW + wave) * (16 * RT);
+  const int64_t kb = (int64_t)blockIdx.y * p.chunk;
+  const int64_t ke = min(p.n, kb + p.chunk);
+  const int nst = (int)((ke - kb + KC - 1) / KC);
+  const int nfull = (int)((ke - kb) / KC);
+  int64_t arow[RT];
+  bool rowok[RT];
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int64_t r = a0 + 16 * rt + li;
+    rowok[rt] = r < p.m;
+    arow[rt] = rowok[rt] ? r : p.m - 1;
+  }
+  // NORM: the sketch pass also accumulates ||A||_F^2 (p.normA set)
+  constexpr bool want_norm = NORM;
+  ACC acc[RT][NT];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[r][c] = ACC{0, 0, 0, 0};
+  u32x4 an[NAR];
+  u32x4 xn[XCH];
+  double nrm = 0.0;
+
+  auto load_x = [&](int64_t k0, bool full) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < XCH; ++j) {
+      const int q = tid + NTH * j;
+      const int c = min(q >> 3, NT * 16 - 1), part = q & 7;
+      constexpr int EX = 16 / (int)sizeof(TC);
+      const int64_t k = k0 + part * EX;
+      const TC* src = Xc + (int64_t)c * p.ldx + k;
+      if (full) {
+        xn[j] = ld16(src);
+      } else {
+        union { u32x4 v; TC e[EX]; } u;
+#pragma unroll
+        for (int e = 0; e < EX; ++e) u.e[e] = (k + e < ke) ? src[e] : TC(0);
+        xn[j] = u.v;
+      }
+    }
+  };
+  auto a_src = [&](int rt, int st, int h, int64_t k0) __attribute__((always_inline)) {
+    return A + arow[rt] * p.lda + k0 + st * KS + lg * V + h * EA;
+  };
+  auto load_a = [&](int64_t k0, bool full, u32x4* dst) __attribute__((always_inline)) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int h = 0; h < NLA; ++h) {
+          const TA* src = a_src(rt, st, h, k0);
+          u32x4& d = dst[(rt * 2 + st) * NLA + h];
+          if (full) {
+            d = ld16(src);
+          } else {
+            const int64_t k = k0 + st * KS + lg * V + h * EA;
+            union { u32x4 v; TA e[EA]; } u;
+#pragma unroll
+            for (int e = 0; e < EA; ++e) u.e[e] = (k + e < ke) ? src[e] : TA(0);
+            d = u.v;
+          }
+        }
+  };
+  auto dma_a = [&](int64_t k0) __attribute__((always_inline)) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int st = 0; st < 2; ++st)
+#pragma unroll
+        for (int h = 0; h < NLA; ++h)
+          __builtin_amdgcn_global_load_lds(
+              (const void*)a_src(rt, st, h, k0),
+              (__attribute__((address_space(3))) void*)(myslot + 64 * ((rt * 2 + st) * NLA + h)), 16, 0, 0);
+  };
+  auto store_x = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int j = 0; j < XCH; ++j) {
+      const int q = tid + NTH * j;
+      const int c = q >> 3, part = q & 7;
+      st16(&xs[buf][c * kPitch + part * 16], xn[j]);
+    }
+  };
+  u32x4 ahi[RT][2], alo[RT][2];
+  auto convert = [&](auto get) __attribute__((always_inline)) {
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+        const u32x4 g0 = get((rt * 2 + st) * NLA);
+        const u32x4 g1 = NLA > 1 ? get((rt * 2 + st) * NLA + NLA - 1) : g0;
+        if (want_norm) {
+          // rows past the edge repeat the last row: weight 0
+          const double wgt = rowok[rt] ? 1.0 : 0.0;
+          if constexpr (sizeof(TA) == 8) {
+            union { u32x4 v; double d[2]; } u;
+            u.v = g0;
+            nrm += wgt * (u.d[0] * u.d[0] + u.d[1] * u.d[1]);
+          } else {
+#pragma unroll
+            for (int h = 0; h < NLA; ++h) {
+              const u32x4 v = h == 0 ? g0 : g1;
+              const double x0 = u2f(v.x), x1 = u2f(v.y), x2 = u2f(v.z), x3 = u2f(v.w);
+              nrm += wgt * (x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
+            }
+          }
+        }
+        if constexpr (MODE == M_F64 || MODE == M_F32) {
+          ahi[rt][st] = g0;
+          alo[rt][st] = g0;
+        } else {
+          to16<MODE>(g0, g1, p.a_scale, ahi[rt][st], alo[rt][st]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+  };
+  auto compute = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+#pragma unroll
+      for (int ct = 0; ct < NT; ++ct) {
+        if (ct % kGroup == 0 && (ct > 0 || st > 0)) __builtin_amdgcn_sched_barrier(0);
+        const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
+        const u32x4 xhi = *(const u32x4*)&xs[buf][boff];
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) step_mma<MODE>(ahi[rt][st], alo[rt][st], xhi, xhi, acc[rt][ct]);
+      }
+    }
+  };
+  auto from_regs = [&](int j) { return an[j]; };
+  auto from_slot = [&](int j) { return myslot[64 * j + lane]; };
+
+  // prologue: X(0), A(0) -> registers; A(1) -> slot when full
+  if (nst > 0) {
+    load_x(kb, nfull > 0);
+    load_a(kb, nfull > 0, an);
+    if (nfull > 1) dma_a(kb + KC);
+  }
+  int s = 0;
+  // steady state: stages s (registers) and s + 1 (slot) full, and the two
+  // stages prefetched here (s + 2 into registers, s + 3 into the slot) full
+  for (; s + 3 < nfull; s += 2) {
+    const int64_t k0 = kb + (int64_t)s * KC;
+    // even stage s
+    store_x(0);
+    convert(from_regs);
+    load_x(k0 + KC, true);
+    load_a(k0 + 2 * KC, true, an);
+    ring_barrier();
+    compute(0);
+    // odd stage s + 1: its slot loads are older than the NAR loads of A(s + 2)
+    store_x(1);
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(NAR) : "memory");
+    convert(from_slot);
+    load_x(k0 + 2 * KC, true);
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // slot read before it refills
+    dma_a(k0 + 3 * KC);
+    ring_barrier();
+    compute(1);
+  }
+  // remaining stages, one at a time: stage t's A sits in the registers (even
+  // t), in the slot (odd t, full) or is loaded now (odd t, ragged)
+  for (; s < nst; ++s) {
+    const int64_t k0 = kb + (int64_t)s * KC;
+    const int buf = s & 1;
+    store_x(buf);
+    if ((s & 1) == 0) {
+      convert(from_regs);
+    } else if (s < nfull) {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      convert(from_slot);
+    } else {
+      u32x4 tail[NAR];
+      load_a(k0, false, tail);
+      convert([&](int j) { return tail[j]; });
+    }
+    if (s + 1 < nst) load_x(k0 + KC, s + 1 < nfull);
+    if (s + 2 < nst) {
+      if ((s & 1) == 0) {
+        load_a(k0 + 2 * KC, s + 2 < nfull, an);
+      } else if (s + 2 < nfull) {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        dma_a(k0 + 2 * KC);
+      }
+    }
+    ring_barrier();
+    compute(buf);
+  }
+
+  TACC* out = (TACC*)p.out + (int64_t)blockIdx.y * p.split_stride;
+  const int Tst = p.lp >> 4;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+    for (int ct = 0; ct < NT; ++ct)
+      if (ct < Tst) store_rows<TACC>(out, p.ldo, 16 * ct + li, a0 + 16 * rt, lg, p.m, acc[rt][ct], p.out_scale);
+  if (want_norm) {
+    __shared__ double red[NW];
+    nrm = wave_sum(nrm);
+    if (lane == 0) red[wave] = nrm;
+    lds_barrier();
+    if (tid == 0) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) t += red[w];
+      p.normA[blockIdx.y * p.gx + blockIdx.x] = t;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 template <int MODE, int NT, bool TRANS>
@@ -463,6 +720,18 @@ static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   p.out = a.out; p.ldo = a.ldo; p.split_stride = a.split_stride; p.chunk = a.chunk;
   p.normA = TRANS ? nullptr : a.normA;
   p.a_scale = a.a_scale; p.out_scale = a.out_scale;
+  // the two-stage K1 where its registers fit (measured per instantiation)
+  constexpr bool two = MODE == M_F64 || (MODE == M_BF16 && NT <= 14) || (MODE == M_F16 && NT <= 10) ||
+                       (MODE == M_F32 && NT <= 14);
+  constexpr bool two_norm = two && !(MODE == M_F32 && NT == 14);
+  if constexpr (!TRANS && TR::XN == 1 && two) {
+    if (vec && p.normA && two_norm)
+      return launch_k(stream_k1_kernel<MODE, NT, true, false>, stream_k1_kernel<MODE, NT, true, true>, grid,
+                      dim3(64 * TR::NW), s, p);
+    if (vec && !p.normA)
+      return launch_k(stream_k1_kernel<MODE, NT, false, false>, stream_k1_kernel<MODE, NT, false, true>, grid,
+                      dim3(64 * TR::NW), s, p);
+  }
   if (vec || !TRANS)
     return launch_k(stream_kernel<MODE, NT, TRANS, true, false>, stream_kernel<MODE, NT, TRANS, true, true>,
                     grid, dim3(64 * TR::NW), s, p);
@@ -491,8 +760,11 @@ template <int MODE>
 static hipError_t dispatch_dir(bool trans, const StreamArgs& a, hipStream_t s) {
   typedef Tr<MODE> TR;
   if (((uintptr_t)a.A % sizeof(typename TR::TA)) != 0) return hipErrorInvalidValue;
-  // K2 pairs columns: an odd last column takes the shifted-pair path
-  const bool vec = !trans || a.n % TR::RT == 0;
+  // K1: 16-byte aligned rows take the two-stage kernel (odd stages' A tiles
+  // through LDS), others the general one with element-aligned loads; K2
+  // pairs columns: an odd last column takes the shifted-pair path
+  const bool vec = trans ? a.n % TR::RT == 0
+                         : ((uintptr_t)a.A % 16 == 0 && (a.lda * (int64_t)sizeof(typename TR::TA)) % 16 == 0);
   return trans ? dispatch_nt<MODE, true>(a, vec, s) : dispatch_nt<MODE, false>(a, vec, s);
 }
 
