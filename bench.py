@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--plan", default="native", help="precision plan of the c4 batch")
     ap.add_argument("--count", type=int, default=1024, help="c4 batch size")
     ap.add_argument("--skip-per-matrix", action="store_true", help="c4: skip the per-matrix timing")
+    ap.add_argument("--no-tune", action="store_true", help="c4: use the built-in batch plan, not the autotuner's")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -244,10 +245,19 @@ def bench_c4(args, torch, np, synth, B, dev):
     log(f"generated {len(mats)} matrices on the GPU in {time.time() - t:.1f}s")
     abytes = sum((2 * q + 2) * a.shape[0] * a.shape[1] * 4 for a, q in zip(mats, qs))
 
+    tuned = None
+    if not args.no_tune:
+        # the project autotuner picks the batch's Gram plan for this shape class
+        t = time.time()
+        probe_bt = B.Batch(mats, ks, ps, qs, seeds, plan=args.plan)
+        tuned = probe_bt.tune()
+        probe_bt.close()
+        del probe_bt
+        log(f"autotuned the batch plan in {time.time() - t:.1f}s: {tuned}")
     t = time.time()
     bt = B.Batch(mats, ks, ps, qs, seeds, plan=args.plan)
     torch.cuda.synchronize()
-    log(f"planned the batch in {time.time() - t:.1f}s: {bt.stats()}")
+    log(f"planned the batch in {time.time() - t:.1f}s: {bt.stats()}, problem 0 plan {bt.problem_plan(0)}")
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -309,6 +319,7 @@ def bench_c4(args, torch, np, synth, B, dev):
         "grouped_no_graph_ms": round(ms_direct, 3),
         "speedup_vs_per_matrix": round(ms_single / ms_batch, 2) if ms_single else None,
         "launches_per_batch": bt.stats()["launches"],
+        "autotuned_plan": tuned,
         "algorithmic_gb": abytes / 1e9, "achieved_gbs": round(abytes / (ms_batch * 1e-3) / 1e9, 1),
         "hbm_frac": round(abytes / (ms_batch * 1e-3) / 8e12, 4),
         "max_abs_dr_vs_fp64_oracle_sample": max(errs),
