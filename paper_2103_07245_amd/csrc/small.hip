@@ -59,11 +59,6 @@ __device__ __forceinline__ double bcast_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Lane I of each row of 16 lanes, broadcast to its row (DPP row_newbcast).
-template <int I> __device__ __forceinline__ double row_bcast(double v) {
-  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + I, 0xF, 0xF, true);
-}
-
 // Lanes 16..31 (and 48..63) receive lanes 0..15 (32..47); the even rows keep
 // their values (v_permlane16_swap of a register with itself).
 __device__ __forceinline__ double dup_even_rows(double v) {
@@ -74,20 +69,15 @@ __device__ __forceinline__ double dup_even_rows(double v) {
   return __longlong_as_double(((unsigned long long)rh[0] << 32) | rl[0]);
 }
 
-// sqrt(x) and 1/sqrt(x) for x > 0 to about one rounding unit: hardware
-// reciprocal square root estimate, then two coupled Newton steps on
-// g ~ sqrt(x), h ~ 1/(2 sqrt(x)) (residual r = 1/2 - g h).
-__device__ __forceinline__ void sqrt_rsqrt(double x, double& g, double& y) {
-  const double y0 = __builtin_amdgcn_rsq(x);
-  g = x * y0;
-  double h = 0.5 * y0;
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    const double r = __builtin_fma(-g, h, 0.5);
-    g = __builtin_fma(g, r, g);
-    h = __builtin_fma(h, r, h);
-  }
-  y = h + h;
+// x -= s[lane I of the lane row] * v in one instruction: the 64-bit FMA takes
+// its first operand through a DPP row broadcast (v_fmac_f64 with
+// row_newbcast).  The caller orders the definition of s at least two wait
+// states before the first such read (the assembler block is opaque to the
+// compiler's hazard tracking).
+template <int I> __device__ __forceinline__ void fma_bcast(double& x, double s, double v) {
+  asm("v_fmac_f64_dpp %0, -%1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+      : "+v"(x)
+      : "v"(s), "v"(v), "n"(I));
 }
 
 // One wave factors the 16x16 residual diagonal tile.  Lane row 0 (lanes
@@ -96,71 +86,79 @@ __device__ __forceinline__ void sqrt_rsqrt(double x, double& g, double& y) {
 // r_ki times row k from row i) run on both, so lane row 1 ends with
 // M = R^-T of the apply form and W_J = M^T.  After each pivot the scaled
 // row k of the tile is copied into lane row 1 (one permlane swap), so one
-// DPP broadcast per row update serves both halves.  A dependent or padding
-// pivot zeroes row k of the tile and resets row k of M to e_k (M is then the
+// broadcast FMA per row serves both halves.  A dependent or padding pivot
+// zeroes row k of the tile and resets row k of M to e_k (M is then the
 // inverse transpose of the apply form).  Entries below the diagonal of the
 // tile are updated too and never read.
-// Each step updates row k+1 first and starts the next pivot's square root
-// before the remaining row updates, which then overlap that latency chain.
+//
+// The pivot chain runs on uniform scalars, apart from the row updates: with
+// a = T[k][k+1] and b = T[k+1][k+1] as updated through pivot k - 1 (read
+// from lane k + 1 once those two rows are updated), pivot k + 1 is
+// b - (a / r_kk)^2, so each step of the chain is a multiply, an FMA and the
+// reciprocal square root, while the fifteen row updates of a step overlap it.
+// The diagonal of the scaled tile row is T[k][k] / r_kk, i.e. r_kk to a
+// rounding.
 struct DiagState {
   double x[16];
-  double eps, gdv;
+  double thr;  // eps * G_cc of the lane's column
   int c, live;
   bool tile_lane;
   uint32_t depm;
 };
 
-// Rows I .. min(I + 3, 15) of step K: four broadcasts, then four FMAs, then
-// a pin.  Left to itself the compiler hoists all broadcasts of a step and
-// sinks their FMAs (30 extra VGPRs live next to the 136 of the register-
-// resident tiles); one pin per row would serialize every broadcast on one
-// temporary register.
-template <int K, int I>
-__device__ __forceinline__ void diag_rows(DiagState& d, double s, double v) {
+// 1/sqrt(x) for x > 0 to about one rounding unit: hardware estimate, then
+// two coupled Newton steps on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  const double y0 = __builtin_amdgcn_rsq(x);
+  double g = x * y0, h = 0.5 * y0;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double r = __builtin_fma(-g, h, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+  }
+  return h + h;
+}
+
+template <int I, int K>
+__device__ __forceinline__ void diag_rest(DiagState& d, double s, double v) {
   if constexpr (I < 16) {
-    constexpr int N = (16 - I) < 4 ? (16 - I) : 4;
-    double b[4];
-#pragma unroll
-    for (int u = 0; u < N; ++u) {
-      if (u == 0) b[u] = row_bcast<I>(s);
-      if (u == 1) b[u] = row_bcast<(I + 1) & 15>(s);
-      if (u == 2) b[u] = row_bcast<(I + 2) & 15>(s);
-      if (u == 3) b[u] = row_bcast<(I + 3) & 15>(s);
-    }
-#pragma unroll
-    for (int u = 0; u < N; ++u) d.x[I + u] = __builtin_fma(-b[u], v, d.x[I + u]);
-    if constexpr (N == 4) asm volatile("" : "+v"(d.x[I]), "+v"(d.x[I + 1]), "+v"(d.x[I + 2]), "+v"(d.x[I + 3]));
-    if constexpr (N == 3) asm volatile("" : "+v"(d.x[I]), "+v"(d.x[I + 1]), "+v"(d.x[I + 2]));
-    if constexpr (N == 2) asm volatile("" : "+v"(d.x[I]), "+v"(d.x[I + 1]));
-    if constexpr (N == 1) asm volatile("" : "+v"(d.x[I]));
-    diag_rows<K, I + N>(d, s, v);
+    fma_bcast<I>(d.x[I], s, v);
+    diag_rest<I + 1, K>(d, s, v);
   }
 }
 
-// pivot K: its value piv (uniform), sqrt g and 1/sqrt y (valid when the
-// pivot is live and independent)
+// step K: pivot value p (uniform) with its 1/sqrt y, and the two entries
+// a = T[K][K+1], b = T[K+1][K+1] for the next pivot
 template <int K>
-__device__ __forceinline__ void diag_steps(DiagState& d, double piv, double g, double y) {
+__device__ __forceinline__ void diag_steps(DiagState& d, double p, double y, double a, double b) {
   if constexpr (K < 16) {
-    const double gkk = bcast_f64(d.gdv, K);
-    const bool isdep = K < d.live && !(piv > d.eps * gkk);
-    const bool zero = K >= d.live || isdep;
-    d.depm |= isdep ? (1u << K) : 0u;
+    const double thr = bcast_f64(d.thr, K);
+    const bool zero = K >= d.live || !(p > thr);
     const double ys = zero ? 0.0 : y;
-    const double rkk = zero ? 0.0 : g;
     double v = d.x[K] * ys;
-    v = (d.tile_lane && d.c == K) ? rkk : v;
-    v = (zero && !d.tile_lane) ? ((d.c == K) ? 1.0 : 0.0) : v;
+    if (zero) {
+      d.depm |= K < d.live ? (1u << K) : 0u;
+      v = (!d.tile_lane && d.c == K) ? 1.0 : v;
+    }
     d.x[K] = v;
-    const double s = dup_even_rows(v);  // the scaled tile row K, in both lane rows
+    double s = dup_even_rows(v);  // the scaled tile row K, in both lane rows
+    asm volatile("s_nop 1" : "+v"(s));
     if constexpr (K + 1 < 16) {
-      d.x[K + 1] = __builtin_fma(-row_bcast<K + 1>(s), v, d.x[K + 1]);
-      asm volatile("" : "+v"(d.x[K + 1]));
-      const double pn = bcast_f64(d.x[K + 1], K + 1);
-      double gn, yn;
-      sqrt_rsqrt(pn > 0.0 ? pn : 1.0, gn, yn);
-      diag_rows<K, K + 2>(d, s, v);
-      diag_steps<K + 1>(d, pn, gn, yn);
+      // the chain: next pivot from a and b
+      const double t = a * ys;
+      const double pn = __builtin_fma(-t, t, b);
+      const double yn = rsqrt_nr(pn > 0.0 ? pn : 1.0);
+      double an = 0.0, bn = 0.0;
+      fma_bcast<K + 1>(d.x[K + 1], s, v);
+      if constexpr (K + 2 < 16) {
+        fma_bcast<K + 2>(d.x[K + 2], s, v);
+        asm volatile("s_nop 1" : "+v"(d.x[K + 1]), "+v"(d.x[K + 2]));
+        an = bcast_f64(d.x[K + 1], K + 2);
+        bn = bcast_f64(d.x[K + 2], K + 2);
+        diag_rest<K + 3, K>(d, s, v);
+      }
+      diag_steps<K + 1>(d, pn, yn, an, bn);
     }
   }
 }
@@ -173,14 +171,13 @@ __device__ __forceinline__ void diag_factor(CholShared& sh, int J, int l, double
   const bool ml = lane >= 16 && lane < 32;
 #pragma unroll
   for (int i = 0; i < 16; ++i) d.x[i] = d.tile_lane ? sh.dgt[i][d.c] : ((i == d.c) ? 1.0 : 0.0);
-  d.gdv = sh.gd[16 * J + d.c];
+  d.thr = eps * sh.gd[16 * J + d.c];
   d.live = l - 16 * J;
-  d.eps = eps;
   d.depm = 0;
+  asm volatile("s_nop 4" : "+v"(d.x[0]), "+v"(d.x[1]), "+v"(d.x[2]));
   const double p0 = bcast_f64(d.x[0], 0);
-  double g0, y0;
-  sqrt_rsqrt(p0 > 0.0 ? p0 : 1.0, g0, y0);
-  diag_steps<0>(d, p0, g0, y0);
+  const double y0 = rsqrt_nr(p0 > 0.0 ? p0 : 1.0);
+  diag_steps<0>(d, p0, y0, bcast_f64(d.x[0], 1), bcast_f64(d.x[1], 1));
   if (d.tile_lane) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) sh.dgt[i][d.c] = (i <= d.c) ? d.x[i] : 0.0;
