@@ -163,15 +163,19 @@ __device__ __forceinline__ void diag_steps(DiagState& d, double p, double y, dou
   }
 }
 
-__device__ __forceinline__ void diag_factor(CholShared& sh, int J, int l, double eps) {
+// Factor diagonal tile J (tin, 16 x 17) into R_JJ (rout, upper triangle,
+// zeros below) and W_J (wout[c][i]); flags of its dependent columns go to
+// sdep[16 J + c].  rout may alias tin.
+__device__ __forceinline__ void diag_factor(const double (*tin)[17], double (*rout)[17], double (*wout)[17],
+                                            const double* gd, int* sdep, int J, int l, double eps) {
   const int lane = threadIdx.x & 63;
   DiagState d;
   d.c = lane & 15;
   d.tile_lane = lane < 16;
   const bool ml = lane >= 16 && lane < 32;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) d.x[i] = d.tile_lane ? sh.dgt[i][d.c] : ((i == d.c) ? 1.0 : 0.0);
-  d.thr = eps * sh.gd[16 * J + d.c];
+  for (int i = 0; i < 16; ++i) d.x[i] = d.tile_lane ? tin[i][d.c] : ((i == d.c) ? 1.0 : 0.0);
+  d.thr = eps * gd[16 * J + d.c];
   d.live = l - 16 * J;
   d.depm = 0;
   asm volatile("s_nop 4" : "+v"(d.x[0]), "+v"(d.x[1]), "+v"(d.x[2]));
@@ -180,11 +184,11 @@ __device__ __forceinline__ void diag_factor(CholShared& sh, int J, int l, double
   diag_steps<0>(d, p0, y0, bcast_f64(d.x[0], 1), bcast_f64(d.x[1], 1));
   if (d.tile_lane) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) sh.dgt[i][d.c] = (i <= d.c) ? d.x[i] : 0.0;
-    sh.sdep[16 * J + d.c] = (d.depm >> d.c) & 1u;
+    for (int i = 0; i < 16; ++i) rout[i][d.c] = (i <= d.c) ? d.x[i] : 0.0;
+    sdep[16 * J + d.c] = (d.depm >> d.c) & 1u;
   } else if (ml) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) sh.winv[d.c][i] = d.x[i];
+    for (int i = 0; i < 16; ++i) wout[d.c][i] = d.x[i];
   }
 }
 
@@ -252,7 +256,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, Cho
 #pragma unroll
     for (int r = 0; r < 4; ++r) sh.dgt[acc_row<double>(lg, r)][li] = a ? t[0][r] : t[16][r];
     wave_lds_fence();
-    diag_factor(sh, J, l, eps);
+    diag_factor(sh.dgt, sh.dgt, sh.winv, sh.gd, sh.sdep, J, l, eps);
     wave_lds_fence();
     // value selects only: a store through a selected tile address would force
     // the tile array into scratch memory
@@ -399,11 +403,253 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, Cho
   }
 }
 
+// ---------------------------------------------------------------------------
+// The same factorization for lp <= 224 (at most 14 tile rows) with the
+// diagonal tiles factored by a wave of their own.  Waves 0..6 own tile rows
+// w and 13 - w (15 tiles each); wave 7 owns no tile.  Panel J:
+//   B. all eight waves: R_JK = W_J^T (G_JK - R_{J-1,J}^T R_{J-1,K}), K > J;
+//   C. wave 7 takes diagonal tile J + 1 as its owner left it (updated through
+//      panel J - 1), applies panel J (G -= R_{J,J+1}^T R_{J,J+1}) and factors
+//      it (R_{J+1,J+1} and W_{J+1} into LDS); meanwhile the owners apply the
+//      rank-16 updates of rows I > J + 1, the owner of row J + 2 hands its
+//      diagonal tile (now updated through panel J) to wave 7 for the next
+//      panel, and the owner of row J + 1 stages that row for the next B.
+// The owners' row work and the staging are off the chain of diagonal
+// factors, which is B, one barrier, the diagonal update and factor, and a
+// barrier per panel.  W_J of every panel stays in LDS and is written out at
+// the end.
+// ---------------------------------------------------------------------------
+constexpr int kDwRows = 14;
+
+struct CholSharedDW {
+  double gd[kMaxL];
+  int sdep[kMaxL];
+  double dgt[16][17];             // diagonal tile being factored
+  double dbuf[2][16][17];         // diagonal tile J from its owner (through panel J - 2)
+  double rjj[2][16][17];          // R_JJ for its owner
+  double wall[kDwRows][16][17];   // W_J of every panel
+  double pnl[2][16][kMaxL + 1];   // panel rows, double buffered: raw G_J,: in, R_J,: out
+  int sflag;
+};
+
+template <typename T, bool B>
+__global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, CholP ps) {
+  bool past;
+  const CholP prm = kparams<B>(pb, ps, past);
+  if (past) return;
+  const double* __restrict__ G = prm.G;
+  const int64_t ldg = prm.ldg;
+  const int l = prm.l, lp = prm.lp;
+  const double eps = prm.eps;
+  double* __restrict__ Rt = prm.Rt;
+  const int64_t ldr = prm.ldr;
+  T* __restrict__ Ra = (T*)prm.Ra;
+  T* __restrict__ Dinv = (T*)prm.Dinv;
+  int* __restrict__ dep = prm.dep;
+  pbpqlp_info* info = prm.info;
+  __shared__ CholSharedDW sh;
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  if (tid < kMaxL) {
+    sh.gd[tid] = (tid < l) ? G[(int64_t)tid * ldg + tid] : 0.0;
+    sh.sdep[tid] = 0;
+  }
+  if (tid == 0) sh.sflag = 0;
+  __syncthreads();
+  if (tid < l && !isfinite(sh.gd[tid])) atomicOr(&sh.sflag, 1);
+
+  // tile wave w owns rows RA = w and RB = 13 - w: slots 0..NA-1 hold
+  // (RA, RA + j), slots NA..13 hold (RB, j) and slot 14 the diagonal (RB, RB)
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const bool dw = w == 7;
+  const int Tn = lp >> 4;
+  constexpr int NS = 15;
+  f64x4 t[NS];
+  {
+    const int RA = w, RB = 13 - w, NA = 14 - w;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int I = j == 14 ? RB : (j < NA ? RA : RB);
+      const int K = j == 14 ? RB : (j < NA ? RA + j : j);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        t[j][r] = (!dw && K < Tn) ? G[(int64_t)(16 * I + acc_row<double>(lg, r)) * ldg + 16 * K + li] : 0.0;
+    }
+  }
+  // the owner's tile slot of diagonal tile R (R == RA or R == RB)
+  auto put_diag = [&](int R, int RA, double (*dst)[17]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[acc_row<double>(lg, r)][li] = R == RA ? t[0][r] : t[14][r];
+  };
+  // stage the tiles K > R of row R (R == RA or R == RB) into pn
+  auto stage_row = [&](int R, int RA, int NA, double (*pn)[kMaxL + 1]) {
+#pragma unroll
+    for (int j = 0; j < NS - 1; ++j) {
+      const int I = j < NA ? RA : 13 - RA;
+      const int K = j < NA ? RA + j : j;
+      if (I == R && K > R && K < Tn) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pn[acc_row<double>(lg, r)][16 * K + li] = t[j][r];
+      }
+    }
+  };
+
+  if (!dw) {
+    if (w == 0) {  // row 0: diagonal tile and panel 0
+      put_diag(0, 0, sh.dbuf[0]);
+      stage_row(0, 0, 14, sh.pnl[0]);
+    }
+    if (w == 1 && Tn > 1) put_diag(1, 1, sh.dbuf[1]);
+  }
+  lds_barrier();
+  if (dw) {
+    __builtin_amdgcn_s_setprio(3);
+    diag_factor(sh.dbuf[0], sh.rjj[0], sh.wall[0], sh.gd, sh.sdep, 0, l, eps);
+  }
+  lds_barrier();
+
+  for (int J = 0; J < Tn; ++J) {
+    // tile coordinates re-derived each panel from an opaque scalar copy of w
+    int wl;
+    asm volatile("s_mov_b32 %0, %1" : "=s"(wl) : "s"(w));
+    const int RA = wl, RB = 13 - wl, NA = 14 - wl;
+    auto tile_i = [&](int j) { return j == 14 ? RB : (j < NA ? RA : RB); };
+    auto tile_k = [&](int j) { return j == 14 ? RB : (j < NA ? RA + j : j); };
+    double(*pn)[kMaxL + 1] = sh.pnl[J & 1];
+    double(*pp)[kMaxL + 1] = sh.pnl[(J + 1) & 1];  // panel J - 1
+
+    // ---- B: K = J + 1 + wl, J + 9 + wl (all eight waves)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int K = J + 1 + wl + 8 * h;
+      if (K < Tn) {
+        f64x4 g;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g[r] = pn[acc_row<double>(lg, r)][16 * K + li];
+        if (J > 0) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int kk = acc_row<double>(lg, s4);
+            g = mma_f64(-pp[kk][16 * J + li], pp[kk][16 * K + li], g);
+          }
+        }
+        f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc = mma_f64(sh.wall[J][acc_row<double>(lg, s4)][li], g[s4], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = acc_row<double>(lg, r);
+          pn[row][16 * K + li] = sh.sdep[16 * J + row] ? 0.0 : acc[r];
+        }
+      }
+    }
+    lds_barrier();
+    const int J1 = J + 1, J2 = J + 2;
+    if (dw) {
+      // ---- C, diagonal wave: tile J + 1 gets panel J's update, then its factor
+      if (J1 < Tn) {
+        f64x4 d;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d[r] = sh.dbuf[J1 & 1][acc_row<double>(lg, r)][li];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int kk = acc_row<double>(lg, s4);
+          d = mma_f64(-pn[kk][16 * J1 + li], pn[kk][16 * J1 + li], d);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh.dgt[acc_row<double>(lg, r)][li] = d[r];
+        wave_lds_fence();
+        diag_factor(sh.dgt, sh.rjj[J1 & 1], sh.wall[J1], sh.gd, sh.sdep, J1, l, eps);
+      }
+    } else {
+      // the owner of row J keeps R_J,: in its registers (the factor's output)
+      if (J == RA || J == RB) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          const int I = tile_i(j), K = tile_k(j);
+          if (I == J && K > J && K < Tn) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[j][r] = pn[acc_row<double>(lg, r)][16 * K + li];
+          }
+        }
+        // R_JJ from the diagonal wave (value selects keep the tiles in registers)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const double v = sh.rjj[J & 1][acc_row<double>(lg, r)][li];
+          t[0][r] = J == RA ? v : t[0][r];
+          t[14][r] = J == RA ? t[14][r] : v;
+        }
+      }
+      // ---- C, tile waves: G_IK -= R_JI^T R_JK for rows I > J + 1
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        const int I = tile_i(j), K = tile_k(j);
+        if (I > J1 && K < Tn) {
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int kk = acc_row<double>(lg, s4);
+            t[j] = mma_f64(-pn[kk][16 * I + li], pn[kk][16 * K + li], t[j]);
+          }
+        }
+        if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
+      }
+      // hand-offs for the next panel
+      if (J2 < Tn && (J2 == RA || J2 == RB)) put_diag(J2, RA, sh.dbuf[J2 & 1]);
+      if (J1 < Tn && (J1 == RA || J1 == RB)) stage_row(J1, RA, NA, pp);
+    }
+    lds_barrier();
+  }
+  __syncthreads();
+  // write Rt (true factor) and Ra (apply factor); mirror tiles below the diagonal are zero
+  if (!dw) {
+    const int RA = w, RB = 13 - w, NA = 14 - w;
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+      const int I = j == 14 ? RB : (j < NA ? RA : RB);
+      const int K = j == 14 ? RB : (j < NA ? RA + j : j);
+      if (K < Tn) {
+        const int c = 16 * K + li;
+        const bool zc = c >= l || sh.sdep[c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = 16 * I + acc_row<double>(lg, r);
+          const double v = (i <= c) ? t[j][r] : 0.0;
+          Rt[(int64_t)i * ldr + c] = v;
+          const double a = (i == c) ? (zc ? 1.0 : v) : ((i < c && !zc) ? v : 0.0);
+          Ra[i * lp + c] = (T)a;
+          if (I != K) {
+            Rt[(int64_t)c * ldr + i] = 0.0;
+            Ra[c * lp + i] = T(0);
+          }
+        }
+      }
+    }
+  }
+  for (int e = tid; e < Tn * 256; e += kCholThreads) {
+    const int J = e >> 8, i = (e >> 4) & 15, c = e & 15;
+    Dinv[e] = (T)sh.wall[J][i][c];
+  }
+  if (tid < lp) dep[tid] = sh.sdep[tid];
+  if (tid == 0) {
+    int nd = 0;
+    for (int k = 0; k < l; ++k) nd += sh.sdep[k];
+    dep[lp] = nd;
+    if (nd && info) {
+      atomicAdd(&info->n_dependent, nd);
+      atomicOr(&info->status_flags, PBPQLP_FLAG_DEPENDENT);
+    }
+    if (sh.sflag && info) atomicOr(&info->status_flags, PBPQLP_FLAG_NONFINITE);
+  }
+}
+
 hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
                        hipStream_t s) {
   if (lp > kMaxL || (lp & 15)) return hipErrorInvalidValue;
   CholP p{G, ldg, l, lp, eps_dep, Rt, ldr, Ra, Dinv, dep, (pbpqlp_info*)info};
+  if (lp <= 16 * kDwRows) {
+    if (f64) return launch_k(chol_dw_kernel<double, false>, chol_dw_kernel<double, true>, dim3(1), dim3(kCholThreads), s, p);
+    return launch_k(chol_dw_kernel<float, false>, chol_dw_kernel<float, true>, dim3(1), dim3(kCholThreads), s, p);
+  }
   if (f64) return launch_k(chol_kernel<double, false>, chol_kernel<double, true>, dim3(1), dim3(kCholThreads), s, p);
   return launch_k(chol_kernel<float, false>, chol_kernel<float, true>, dim3(1), dim3(kCholThreads), s, p);
 }
