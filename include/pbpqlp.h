@@ -102,6 +102,8 @@ typedef struct {
                                     that column was replaced by a seeded random vector,
                                     its R row/diagonal is 0 (rank-deficient sketch)   */
 #define PBPQLP_FLAG_NONFINITE 2  /* a Gram matrix held NaN or Inf (non-finite input)   */
+#define PBPQLP_FLAG_INTERNAL 4   /* a bounded wait inside a kernel gave up (should never
+                                    happen): the results of that call are not valid   */
 
 /* Human-readable name of a status code (static storage). */
 const char* pbpqlp_status_string(pbpqlp_status s);

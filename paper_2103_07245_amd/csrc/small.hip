@@ -407,17 +407,20 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, Cho
 // The same factorization for lp <= 224 (at most 14 tile rows) with the
 // diagonal tiles factored by a wave of their own.  Waves 0..6 own tile rows
 // w and 13 - w (15 tiles each); wave 7 owns no tile.  Panel J:
-//   B. all eight waves: R_JK = W_J^T (G_JK - R_{J-1,J}^T R_{J-1,K}), K > J;
-//   C. wave 7 takes diagonal tile J + 1 as its owner left it (updated through
-//      panel J - 1), applies panel J (G -= R_{J,J+1}^T R_{J,J+1}) and factors
-//      it (R_{J+1,J+1} and W_{J+1} into LDS); meanwhile the owners apply the
-//      rank-16 updates of rows I > J + 1, the owner of row J + 2 hands its
-//      diagonal tile (now updated through panel J) to wave 7 for the next
-//      panel, and the owner of row J + 1 stages that row for the next B.
-// The owners' row work and the staging are off the chain of diagonal
-// factors, which is B, one barrier, the diagonal update and factor, and a
-// barrier per panel.  W_J of every panel stays in LDS and is written out at
-// the end.
+//   wave 7: R_{J,J+1} = W_J^T (G_{J,J+1} - R_{J-1,J}^T R_{J-1,J+1}) (B for
+//      one tile), then diagonal tile J + 1 as its owner left it (updated
+//      through panel J - 1) gets panel J's update G -= R_{J,J+1}^T R_{J,J+1}
+//      and is factored (R_{J+1,J+1} and W_{J+1} into LDS);
+//   waves 0..6: B for the tiles K >= J + 2 of row J, a meeting of these
+//      seven waves on an LDS counter (wave 7 does not wait for it), then the
+//      rank-16 updates of rows I > J + 1; the owner of row J + 2 hands its
+//      diagonal tile (updated through panel J) to wave 7 for the next panel
+//      and the owner of row J + 1 stages that row for the next B.
+// The chain of diagonal factors is thus one B tile, the diagonal update and
+// the factor per panel, with one workgroup barrier at the panel's end.
+// The updates of rows I > J + 1 never read R_{J,J+1}; its row owner picks it
+// up in the next panel.  W_J of every panel stays in LDS and is written out
+// at the end.
 // ---------------------------------------------------------------------------
 constexpr int kDwRows = 14;
 
@@ -430,7 +433,18 @@ struct CholSharedDW {
   double wall[kDwRows][16][17];   // W_J of every panel
   double pnl[2][16][kMaxL + 1];   // panel rows, double buffered: raw G_J,: in, R_J,: out
   int sflag;
+  int bcnt;                       // B tiles done: 7 per panel, one per tile wave
 };
+
+// Spin until *p >= target (LDS, workgroup scope).  The wait is bounded: after
+// about 2^22 polls it gives up and returns false (the caller flags it).
+__device__ __forceinline__ bool lds_wait_geq(int* p, int target) {
+  for (int it = 0; it < (1 << 22); ++it) {
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) >= target) return true;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  return false;
+}
 
 template <typename T, bool B>
 __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, CholP ps) {
@@ -453,7 +467,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
     sh.gd[tid] = (tid < l) ? G[(int64_t)tid * ldg + tid] : 0.0;
     sh.sdep[tid] = 0;
   }
-  if (tid == 0) sh.sflag = 0;
+  if (tid == 0) {
+    sh.sflag = 0;
+    sh.bcnt = 0;
+  }
   __syncthreads();
   if (tid < l && !isfinite(sh.gd[tid])) atomicOr(&sh.sflag, 1);
 
@@ -516,57 +533,119 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
     auto tile_k = [&](int j) { return j == 14 ? RB : (j < NA ? RA + j : j); };
     double(*pn)[kMaxL + 1] = sh.pnl[J & 1];
     double(*pp)[kMaxL + 1] = sh.pnl[(J + 1) & 1];  // panel J - 1
-
-    // ---- B: K = J + 1 + wl, J + 9 + wl (all eight waves)
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int K = J + 1 + wl + 8 * h;
-      if (K < Tn) {
-        f64x4 g;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) g[r] = pn[acc_row<double>(lg, r)][16 * K + li];
-        if (J > 0) {
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            const int kk = acc_row<double>(lg, s4);
-            g = mma_f64(-pp[kk][16 * J + li], pp[kk][16 * K + li], g);
-          }
-        }
-        f64x4 acc = {0, 0, 0, 0};
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) acc = mma_f64(sh.wall[J][acc_row<double>(lg, s4)][li], g[s4], acc);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = acc_row<double>(lg, r);
-          pn[row][16 * K + li] = sh.sdep[16 * J + row] ? 0.0 : acc[r];
-        }
-      }
-    }
-    lds_barrier();
     const int J1 = J + 1, J2 = J + 2;
     if (dw) {
-      // ---- C, diagonal wave: tile J + 1 gets panel J's update, then its factor
+      // ---- the diagonal wave: B for K = J + 1, panel J's update of diagonal
+      // tile J + 1, its factor
       if (J1 < Tn) {
-        f64x4 d;
+        f64x4 g, dd;
+        double ar[4], bq[4], wv[4];
+        int dm[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) d[r] = sh.dbuf[J1 & 1][acc_row<double>(lg, r)][li];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-          const int kk = acc_row<double>(lg, s4);
-          d = mma_f64(-pn[kk][16 * J1 + li], pn[kk][16 * J1 + li], d);
+        for (int r = 0; r < 4; ++r) {
+          const int kk = acc_row<double>(lg, r);
+          g[r] = pn[kk][16 * J1 + li];
+          ar[r] = -pp[kk][16 * J + li];
+          bq[r] = pp[kk][16 * J1 + li];
+          wv[r] = sh.wall[J][kk][li];
+          dm[r] = sh.sdep[16 * J + kk];
+          dd[r] = sh.dbuf[J1 & 1][kk][li];
         }
+        __builtin_amdgcn_sched_barrier(0);
+        if (J > 0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sh.dgt[acc_row<double>(lg, r)][li] = d[r];
+          for (int s4 = 0; s4 < 4; ++s4) g = mma_f64(ar[s4], bq[s4], g);
+        }
+        f64x4 c = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) c = mma_f64(wv[s4], g[s4], c);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          c[r] = dm[r] ? 0.0 : c[r];
+          pn[acc_row<double>(lg, r)][16 * J1 + li] = c[r];  // R_{J,J+1} for the owner of row J
+        }
+        // accumulator register s of R_{J,J+1} is the operand of step s
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) dd = mma_f64(-c[s4], c[s4], dd);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sh.dgt[acc_row<double>(lg, r)][li] = dd[r];
         wave_lds_fence();
         diag_factor(sh.dgt, sh.rjj[J1 & 1], sh.wall[J1], sh.gd, sh.sdep, J1, l, eps);
       }
     } else {
+      // the owner of row J - 1 takes R_{J-1,J}, the diagonal wave's B tile
+      if (J > 0 && (J - 1 == RA || J - 1 == RB)) {
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+          if (tile_i(j) == J - 1 && tile_k(j) == J) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) t[j][r] = pp[acc_row<double>(lg, r)][16 * J + li];
+          }
+        }
+      }
+      // ---- B: K = J + 2 + wl, J + 9 + wl (the operands are read up front;
+      // no scheduling barrier: the resident tiles leave too few registers)
+      {
+        const int K0 = J + 2 + wl, K1 = K0 + 7;
+        const bool v0 = K0 < Tn, v1 = K1 < Tn;
+        const int C0 = min(K0, Tn - 1), C1 = min(K1, Tn - 1);  // clamped: in bounds, unused
+        f64x4 g0, g1;
+        double ar[4], b0[4], b1[4], wv[4];
+        int dm[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int kk = acc_row<double>(lg, r);
+          g0[r] = pn[kk][16 * C0 + li];
+          g1[r] = pn[kk][16 * C1 + li];
+          ar[r] = -pp[kk][16 * J + li];
+          b0[r] = pp[kk][16 * C0 + li];
+          b1[r] = pp[kk][16 * C1 + li];
+          wv[r] = sh.wall[J][kk][li];
+          dm[r] = sh.sdep[16 * J + kk];
+        }
+        // the updated tile is the B operand as it stands: accumulator
+        // register r of lane group g holds row g + 4 r, the contraction index
+        // that lane group takes in step r
+        f64x4 c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+        if (v1) {  // two tiles, chains interleaved
+          if (J > 0) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              g0 = mma_f64(ar[s4], b0[s4], g0);
+              g1 = mma_f64(ar[s4], b1[s4], g1);
+            }
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            c0 = mma_f64(wv[s4], g0[s4], c0);
+            c1 = mma_f64(wv[s4], g1[s4], c1);
+          }
+        } else if (v0) {
+          if (J > 0) {
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) g0 = mma_f64(ar[s4], b0[s4], g0);
+          }
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) c0 = mma_f64(wv[s4], g0[s4], c0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int kk = acc_row<double>(lg, r);
+          if (v0) pn[kk][16 * K0 + li] = dm[r] ? 0.0 : c0[r];
+          if (v1) pn[kk][16 * K1 + li] = dm[r] ? 0.0 : c1[r];
+        }
+      }
+      // the seven tile waves meet (the diagonal wave does not wait for them)
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+      if (lane == 0) atomicAdd(&sh.bcnt, 1);
+      if (!lds_wait_geq(&sh.bcnt, 7 * (J + 1)) && lane == 0) atomicOr(&sh.sflag, 4);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
       // the owner of row J keeps R_J,: in its registers (the factor's output)
       if (J == RA || J == RB) {
 #pragma unroll
         for (int j = 0; j < NS; ++j) {
           const int I = tile_i(j), K = tile_k(j);
-          if (I == J && K > J && K < Tn) {
+          if (I == J && K > J1 && K < Tn) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) t[j][r] = pn[acc_row<double>(lg, r)][16 * K + li];
           }
@@ -592,7 +671,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
         }
         if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
       }
-      // hand-offs for the next panel
+      // hand-offs for the next panel (the staged columns K > J + 2 of pp are
+      // disjoint from the two the diagonal wave reads there next panel)
       if (J2 < Tn && (J2 == RA || J2 == RB)) put_diag(J2, RA, sh.dbuf[J2 & 1]);
       if (J1 < Tn && (J1 == RA || J1 == RB)) stage_row(J1, RA, NA, pp);
     }
@@ -637,7 +717,8 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
       atomicAdd(&info->n_dependent, nd);
       atomicOr(&info->status_flags, PBPQLP_FLAG_DEPENDENT);
     }
-    if (sh.sflag && info) atomicOr(&info->status_flags, PBPQLP_FLAG_NONFINITE);
+    if ((sh.sflag & 1) && info) atomicOr(&info->status_flags, PBPQLP_FLAG_NONFINITE);
+    if ((sh.sflag & 4) && info) atomicOr(&info->status_flags, PBPQLP_FLAG_INTERNAL);
   }
 }
 

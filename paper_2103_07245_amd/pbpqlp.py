@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libpbpqlp.so")
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 F64, F32 = 0, 1
 PREC = {"native": 0, "bf16": 1, "fp16": 2, "bf16x3": 3}
-FLAG_DEPENDENT, FLAG_NONFINITE = 1, 2
+FLAG_DEPENDENT, FLAG_NONFINITE, FLAG_INTERNAL = 1, 2, 4
 
 # named precision plans: (sketch pass, power-iteration passes, projection pass)
 PLANS = {
