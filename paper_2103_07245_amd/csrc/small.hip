@@ -86,10 +86,9 @@ template <int I> __device__ __forceinline__ void fma_bcast(double& x, double s, 
 // r_ki times row k from row i) run on both, so lane row 1 ends with
 // M = R^-T of the apply form and W_J = M^T.  After each pivot the scaled
 // row k of the tile is copied into lane row 1 (one permlane swap), so one
-// broadcast FMA per row serves both halves.  A dependent or padding pivot
-// zeroes row k of the tile and resets row k of M to e_k (M is then the
-// inverse transpose of the apply form).  Entries below the diagonal of the
-// tile are updated too and never read.
+// broadcast FMA per row serves both halves.  A dependent or padding pivot zeroes row k of the tile and resets
+// row k of M to e_k (M is then the inverse transpose of the apply form).
+// Entries below the diagonal of the tile are updated too and never read.
 //
 // The pivot chain runs on uniform scalars, apart from the row updates: with
 // a = T[k][k+1] and b = T[k+1][k+1] as updated through pivot k - 1 (read
@@ -97,7 +96,8 @@ template <int I> __device__ __forceinline__ void fma_bcast(double& x, double s, 
 // b - (a / r_kk)^2, so each step of the chain is a multiply, an FMA and the
 // reciprocal square root, while the fifteen row updates of a step overlap it.
 // The diagonal of the scaled tile row is T[k][k] / r_kk, i.e. r_kk to a
-// rounding.
+// rounding.  The dependence test of all sixteen columns is one compare and
+// a ballot, so the step needs no lane reads for it.
 struct DiagState {
   double x[16];
   double thr;  // eps * G_cc of the lane's column
@@ -107,17 +107,17 @@ struct DiagState {
 };
 
 // 1/sqrt(x) for x > 0 to about one rounding unit: hardware estimate, then
-// two coupled Newton steps on g ~ sqrt(x), h ~ 1/(2 sqrt(x))
+// two Newton steps y <- y (3/2 - (x/2) y^2).  Non-positive x gives a
+// non-finite y, which the caller never uses (such a pivot is dependent).
 __device__ __forceinline__ double rsqrt_nr(double x) {
-  const double y0 = __builtin_amdgcn_rsq(x);
-  double g = x * y0, h = 0.5 * y0;
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
-    const double r = __builtin_fma(-g, h, 0.5);
-    g = __builtin_fma(g, r, g);
-    h = __builtin_fma(h, r, h);
+    const double r = __builtin_fma(-(hx * y), y, 0.5);
+    y = __builtin_fma(y, r, y);
   }
-  return h + h;
+  return y;
 }
 
 template <int I, int K>
@@ -133,22 +133,24 @@ __device__ __forceinline__ void diag_rest(DiagState& d, double s, double v) {
 template <int K>
 __device__ __forceinline__ void diag_steps(DiagState& d, double p, double y, double a, double b) {
   if constexpr (K < 16) {
-    const double thr = bcast_f64(d.thr, K);
-    const bool zero = K >= d.live || !(p > thr);
-    const double ys = zero ? 0.0 : y;
-    double v = d.x[K] * ys;
+    // dependence test of every lane's column at once; bit K decides
+    const uint64_t dm = __builtin_amdgcn_ballot_w64(!(p > d.thr));
+    const bool zero = K >= d.live || ((dm >> K) & 1);
+    double ys = y;
+    double v = d.x[K] * y;
     if (zero) {
       d.depm |= K < d.live ? (1u << K) : 0u;
-      v = (!d.tile_lane && d.c == K) ? 1.0 : v;
+      ys = 0.0;
+      v = (!d.tile_lane && d.c == K) ? 1.0 : 0.0;
     }
     d.x[K] = v;
     double s = dup_even_rows(v);  // the scaled tile row K, in both lane rows
-    asm volatile("s_nop 1" : "+v"(s));
+    asm volatile("s_nop 4" : "+v"(s));
     if constexpr (K + 1 < 16) {
       // the chain: next pivot from a and b
       const double t = a * ys;
       const double pn = __builtin_fma(-t, t, b);
-      const double yn = rsqrt_nr(pn > 0.0 ? pn : 1.0);
+      const double yn = rsqrt_nr(pn);
       double an = 0.0, bn = 0.0;
       fma_bcast<K + 1>(d.x[K + 1], s, v);
       if constexpr (K + 2 < 16) {
@@ -180,7 +182,7 @@ __device__ __forceinline__ void diag_factor(const double (*tin)[17], double (*ro
   d.depm = 0;
   asm volatile("s_nop 4" : "+v"(d.x[0]), "+v"(d.x[1]), "+v"(d.x[2]));
   const double p0 = bcast_f64(d.x[0], 0);
-  const double y0 = rsqrt_nr(p0 > 0.0 ? p0 : 1.0);
+  const double y0 = rsqrt_nr(p0);
   diag_steps<0>(d, p0, y0, bcast_f64(d.x[0], 1), bcast_f64(d.x[1], 1));
   if (d.tile_lane) {
 #pragma unroll
