@@ -68,12 +68,15 @@ int resolve_mode(pbpqlp_dtype dt, int prec, bool* ok) {
 
 // Relative pivot threshold below which a Cholesky column counts as
 // dependent: the larger of (32 u_data)^2 (a residual below 32 rounding units
-// of the data is noise) and 16 l u_64 (the cancellation level of a pivot
-// computed from an FP64 Gram).
-double dep_eps(bool f64, int l) {
+// of the data is noise) and max(16 l, 4 len) u_64, the noise level of a
+// pivot computed from an FP64 Gram: each Gram entry sums len products, and
+// the pivot of an exactly dependent column carries that rounding (up to
+// about 2 len u_64 relative to its diagonal, depending on the summation order).
+double dep_eps(bool f64, int l, int64_t len) {
   const double u64 = 1.1102230246251565e-16, u32 = 5.9604644775390625e-08;
   const double ud = f64 ? u64 : u32;
-  const double a = (32.0 * ud) * (32.0 * ud), b = 16.0 * l * u64;
+  const double n = 16.0 * l > 4.0 * (double)len ? 16.0 * l : 4.0 * (double)len;
+  const double a = (32.0 * ud) * (32.0 * ud), b = n * u64;
   return a > b ? a : b;
 }
 
@@ -341,7 +344,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
 pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes,
                    void* out, void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm,
                    void* info, hipStream_t st) {
-  const double eps = dep_eps(f64, c.l);
+  const double eps = dep_eps(f64, c.l, len);
   void* Ra = f64 ? c.Ra64 : c.Ra;
   void* Dv = f64 ? c.Dinv64 : c.Dinv;
   const void* src = X;

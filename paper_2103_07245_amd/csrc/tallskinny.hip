@@ -189,8 +189,12 @@ hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int 
 // ---------------------------------------------------------------------------
 // Gram G = X X^T of a column-major lp x len operand, accumulated in FP64 on
 // the FP64 matrix cores (FP32 inputs are exact in FP64).  Grid: (upper
-// triangle of 32x32 blocks) x (contraction splits); each wave owns one 16x16
-// tile; partials are summed by gram_reduce in a fixed order.
+// triangle of 32x32 blocks) x (contraction splits).  Each of the four waves
+// computes the whole 32x32 block (four 16x16 tiles, three on the diagonal)
+// over every fourth slice of the split, so one load of the two row panels
+// feeds four products and the next two slices are in flight while the
+// current one is multiplied; the waves' blocks are then summed through LDS in a fixed
+// order.  Partials are summed by gram_reduce in a fixed order.
 // ---------------------------------------------------------------------------
 __host__ __device__ inline int npairs_of(int nb) { return nb * (nb + 1) / 2; }
 
@@ -227,19 +231,21 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
   const int64_t ld = prm.ld, len = prm.len;
   const int lp = prm.lp;
   constexpr int VV = 16 / sizeof(T);
+  constexpr int STEP = 4 * VV;  // contraction indices per slice (four lane groups)
   const int p = blockIdx.x;
   int bj = 0;
   while ((bj + 1) * (bj + 2) / 2 <= p) ++bj;
   const int bi = p - bj * (bj + 1) / 2;
+  const bool dg = bi == bj;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int ti = wave >> 1, tj = wave & 1;
-  const int rI = 32 * bi + 16 * ti + li, rJ = 32 * bj + 16 * tj + li;
   const int64_t kb = (int64_t)blockIdx.y * prm.kchunk, ke = min(len, kb + prm.kchunk);
-  const T* pI = X + (int64_t)rI * ld;
-  const T* pJ = X + (int64_t)rJ * ld;
-  const bool okI = rI < lp, okJ = rJ < lp;
-  f64x4 acc0 = {0, 0, 0, 0}, acc1 = {0, 0, 0, 0};
-  auto ld_slice = [&](const T* base, bool ok, int64_t k, T out[VV]) {
+  const int r0 = 32 * bi + li, r1 = r0 + 16, c0 = 32 * bj + li, c1 = c0 + 16;
+  const T* pI0 = X + (int64_t)r0 * ld;
+  const T* pI1 = X + (int64_t)r1 * ld;
+  const T* pJ0 = X + (int64_t)c0 * ld;
+  const T* pJ1 = X + (int64_t)c1 * ld;
+  const bool okI0 = r0 < lp, okI1 = r1 < lp, okJ0 = c0 < lp, okJ1 = c1 < lp;
+  auto ld_slice = [&](const T* base, bool ok, int64_t k, T out[VV]) __attribute__((always_inline)) {
     if (ok && k + VV <= ke) {
       union { u32x4 v; T e[VV]; } u;
       u.v = ld16(base + k);
@@ -250,24 +256,57 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
       for (int e = 0; e < VV; ++e) out[e] = (ok && k + e < ke) ? base[k + e] : T(0);
     }
   };
-  constexpr int STEP = 4 * VV;
+  f64x4 a00 = {0, 0, 0, 0}, a01 = a00, a10 = a00, a11 = a00;
+  // slices in flight: the current one and the next two of this wave
+  T cur[4][VV], nx[4][VV], nn[4][VV];
+  auto load4 = [&](int64_t at, T (*dst)[VV]) __attribute__((always_inline)) {
+    const int64_t k = at + lg * VV;
+    ld_slice(pI0, okI0, k, dst[0]);
+    ld_slice(pI1, okI1, k, dst[1]);
+    ld_slice(pJ0, okJ0, k, dst[2]);
+    ld_slice(pJ1, okJ1, k, dst[3]);
+  };
   // wave-uniform trip count: lanes past the end load zeros
-  for (int64_t base = kb; base < ke; base += 2 * STEP) {
-    const int64_t k = base + lg * VV;
-    T a0[VV], b0[VV], a1[VV], b1[VV];
-    ld_slice(pI, okI, k, a0);
-    ld_slice(pJ, okJ, k, b0);
-    ld_slice(pI, okI, k + STEP, a1);
-    ld_slice(pJ, okJ, k + STEP, b1);
+  int64_t base = kb + (int64_t)wave * STEP;
+  if (base < ke) load4(base, cur);
+  if (base + 4 * STEP < ke) load4(base + 4 * STEP, nx);
+  for (; base < ke; base += 4 * STEP) {
+    if (base + 8 * STEP < ke) load4(base + 8 * STEP, nn);
 #pragma unroll
-    for (int e = 0; e < VV; ++e) acc0 = mma_f64((double)a0[e], (double)b0[e], acc0);
+    for (int e = 0; e < VV; ++e) {
+      const double x0 = (double)cur[0][e], x1 = (double)cur[1][e];
+      const double y0 = (double)cur[2][e], y1 = (double)cur[3][e];
+      a00 = mma_f64(x0, y0, a00);
+      a01 = mma_f64(x0, y1, a01);
+      if (!dg) a10 = mma_f64(x1, y0, a10);
+      a11 = mma_f64(x1, y1, a11);
+    }
 #pragma unroll
-    for (int e = 0; e < VV; ++e) acc1 = mma_f64((double)a1[e], (double)b1[e], acc1);
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < VV; ++e) {
+        cur[q][e] = nx[q][e];
+        nx[q][e] = nn[q][e];
+      }
   }
+  // sum the four waves' blocks in LDS (fixed order), write the 32x32 partial
+  __shared__ double red[4][1024];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = acc_row<double>(lg, r);
+    red[wave][row * 32 + li] = a00[r];
+    red[wave][row * 32 + 16 + li] = a01[r];
+    red[wave][(16 + row) * 32 + 16 + li] = a11[r];
+    // on the diagonal block the lower-left tile is the transpose of the upper-right one
+    red[wave][dg ? (16 + li) * 32 + row : (16 + row) * 32 + li] = dg ? a01[r] : a10[r];
+  }
+  __syncthreads();
   double* out = prm.part + ((int64_t)blockIdx.y * prm.gx + p) * 1024;
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-    out[(16 * ti + acc_row<double>(lg, r)) * 32 + 16 * tj + li] = acc0[r] + acc1[r];
+  for (int q = 0; q < 4; ++q) {
+    const int e = tid + 256 * q;
+    out[e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
+  }
 }
 
 struct GramReduceP {
