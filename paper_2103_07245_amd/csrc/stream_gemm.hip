@@ -28,8 +28,6 @@
 // Modes: F64 (v_mfma_f64_16x16x4), F32 (v_mfma_f32_16x16x4), BF16 / FP16
 // (v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulate; A converted in
 // registers), BF16X3 (hi*hi + hi*lo + lo*hi of bfloat16 splits).
-#include <type_traits>
-
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
@@ -243,17 +241,14 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[r][c] = ACC{0, 0, 0, 0};
 
-  // stages prefetched into registers: two for split-BF16x3 (one wave per
-  // SIMD, registers to spare), one otherwise
-  constexpr int DEPTH = XN == 2 ? 2 : 1;
-  u32x4 an[DEPTH][TRANS ? 1 : NAR];   // K1: 16-byte A loads
-  u32x2 at[DEPTH][TRANS ? NAR : 1];   // K2: 8-byte A loads (RT consecutive columns of one row)
-  u32x4 xn[DEPTH][XN][XCH];
+  // the next stage, prefetched into registers
+  u32x4 an[TRANS ? 1 : NAR];   // K1: 16-byte A loads
+  u32x2 at[TRANS ? NAR : 1];   // K2: 8-byte A loads (RT consecutive columns of one row)
+  u32x4 xn[XN][XCH];
   double nrm = 0.0;
 
   // ---- loads of one stage starting at contraction index k0
-  auto load_x = [&](int64_t k0, bool full, auto SL) __attribute__((always_inline)) {
-    constexpr int sl = decltype(SL)::value;
+  auto load_x = [&](int64_t k0, bool full) __attribute__((always_inline)) {
 #pragma unroll
     for (int j = 0; j < XCH; ++j) {
       const int q = tid + NTH * j;
@@ -266,18 +261,17 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
       for (int x = 0; x < XN; ++x) {
         const TC* src = x == 0 ? Xc : Xl;
         if (full) {
-          xn[sl][x][j] = ld16(src + off);
+          xn[x][j] = ld16(src + off);
         } else {
           union { u32x4 v; TC e[EX]; } u;
 #pragma unroll
           for (int e = 0; e < EX; ++e) u.e[e] = (k + e < ke) ? src[off + e] : TC(0);
-          xn[sl][x][j] = u.v;
+          xn[x][j] = u.v;
         }
       }
     }
   };
-  auto load_a = [&](int64_t k0, bool full, auto SL) __attribute__((always_inline)) {
-    constexpr int sl = decltype(SL)::value;
+  auto load_a = [&](int64_t k0, bool full) __attribute__((always_inline)) {
     if constexpr (!TRANS) {
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
@@ -287,7 +281,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
           for (int h = 0; h < NLA; ++h) {
             const int64_t k = k0 + st * KS + lg * V + h * EA;
             const TA* src = A + arow[rt] * p.lda + k;
-            u32x4& d = an[sl][(rt * 2 + st) * NLA + h];
+            u32x4& d = an[(rt * 2 + st) * NLA + h];
             if (full) {
               d = *(const u32x4_e*)src;
             } else {
@@ -303,7 +297,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
 #pragma unroll
         for (int e = 0; e < V; ++e) {
           const int64_t i = k0 + st * KS + lg * V + e;
-          u32x2& d = at[sl][st * V + e];
+          u32x2& d = at[st * V + e];
           if (full) {
             d = *(const u32x2_e*)(A + i * p.lda + acol_ld);
             if (sh) d.x = d.y;
@@ -319,20 +313,13 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
     }
   };
 
-  using S0 = std::integral_constant<int, 0>;
-  using S1 = std::integral_constant<int, DEPTH - 1>;
   if (nst > 0) {
-    load_x(kb, nfull > 0, S0{});
-    load_a(kb, nfull > 0, S0{});
+    load_x(kb, nfull > 0);
+    load_a(kb, nfull > 0);
   }
-  if (DEPTH == 2 && nst > 1) {
-    load_x(kb + KC, nfull > 1, S1{});
-    load_a(kb + KC, nfull > 1, S1{});
-  }
-  // one stage: its X and A come from register slot SL, which then takes the
-  // stage DEPTH ahead; the X ring in LDS alternates between two buffers
-  auto stage = [&](int s, auto SL) __attribute__((always_inline)) {
-    constexpr int sl = decltype(SL)::value;
+  // one stage: its X and A come from the registers, which then take the next
+  // stage; the X ring in LDS alternates between two buffers
+  auto stage = [&](int s) __attribute__((always_inline)) {
     const int64_t k0 = kb + (int64_t)s * KC;
     const int buf = s & 1;
     // X(s) -> LDS
@@ -342,7 +329,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
       if (!xch_ok(j, q)) continue;
       const int c = q >> 3, part = q & 7;
 #pragma unroll
-      for (int x = 0; x < XN; ++x) st16(&xs[buf][x][c * kPitch + part * 16], xn[sl][x][j]);
+      for (int x = 0; x < XN; ++x) st16(&xs[buf][x][c * kPitch + part * 16], xn[x][j]);
     }
     // A(s) -> compute-type fragments afr[rt][st] (hi and, for BF16X3, lo)
     u32x4 ahi[RT][2], alo[RT][2];
@@ -352,8 +339,8 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
       for (int st = 0; st < 2; ++st) {
         u32x4 g0, g1;  // the V A values of this lane for (rt, st), as raw TA bits
         if constexpr (!TRANS) {
-          g0 = an[sl][(rt * 2 + st) * NLA];
-          g1 = NLA > 1 ? an[sl][(rt * 2 + st) * NLA + NLA - 1] : g0;
+          g0 = an[(rt * 2 + st) * NLA];
+          g1 = NLA > 1 ? an[(rt * 2 + st) * NLA + NLA - 1] : g0;
           if (!TRANS && p.normA && rowok[rt]) {
             if constexpr (sizeof(TA) == 8) {
               union { u32x4 v; double d[2]; } u;
@@ -362,7 +349,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
             } else {
 #pragma unroll
               for (int h = 0; h < NLA; ++h) {
-                const u32x4 v = an[sl][(rt * 2 + st) * NLA + h];
+                const u32x4 v = an[(rt * 2 + st) * NLA + h];
                 const double x0 = u2f(v.x), x1 = u2f(v.y), x2 = u2f(v.z), x3 = u2f(v.w);
                 nrm += x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
               }
@@ -371,12 +358,12 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
         } else {
           // element e of the fragment is row (lg V + e), column acol + rt
           if constexpr (sizeof(TA) == 8) {
-            g0 = u32x4{at[sl][st * V + 0].x, at[sl][st * V + 0].y, at[sl][st * V + 1].x, at[sl][st * V + 1].y};
+            g0 = u32x4{at[st * V + 0].x, at[st * V + 0].y, at[st * V + 1].x, at[st * V + 1].y};
             g1 = g0;
           } else {
             uint32_t w[8];
 #pragma unroll
-            for (int e = 0; e < V; ++e) w[e] = rt == 0 ? at[sl][st * V + e].x : at[sl][st * V + e].y;
+            for (int e = 0; e < V; ++e) w[e] = rt == 0 ? at[st * V + e].x : at[st * V + e].y;
             g0 = u32x4{w[0], w[1], w[2], w[3]};
             g1 = V > 4 ? u32x4{w[4 % V], w[5 % V], w[6 % V], w[7 % V]} : g0;
           }
@@ -388,41 +375,62 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
           to16<MODE>(g0, g1, p.a_scale, ahi[rt][st], alo[rt][st]);
         }
       }
-    // prefetch stage s + DEPTH (its loads stay in flight across the barrier)
-    if (s + DEPTH < nst) {
-      const bool full = s + DEPTH < nfull;
-      load_x(k0 + DEPTH * KC, full, SL);
-      load_a(k0 + DEPTH * KC, full, SL);
+    // prefetch stage s + 1 (its loads stay in flight across the barrier)
+    if (s + 1 < nst) {
+      const bool full = s + 1 < nfull;
+      load_x(k0 + KC, full);
+      load_a(k0 + KC, full);
     }
     lds_barrier();
+    if constexpr (XN == 2) {
+      // split-BF16x3: six products per X fragment pair; the pair of the next
+      // column tile is read before the products of this one are issued
+      auto frag = [&](int t, u32x4& h, u32x4& l) __attribute__((always_inline)) {
+        const int boff = (16 * (t % NT) + li) * kPitch + (t / NT) * 64 + lg * 16;
+        h = *(const u32x4*)&xs[buf][0][boff];
+        l = *(const u32x4*)&xs[buf][1][boff];
+      };
+      u32x4 fh, fl;
+      frag(0, fh, fl);
 #pragma unroll
-    for (int st = 0; st < 2; ++st) {
-#pragma unroll
-      for (int ct = 0; ct < NT; ++ct) {
-        // keep at most kGroup X fragments in flight: the scheduler would
-        // otherwise hoist every LDS read of the step and spill accumulators
-        if (ct % kGroup == 0 && (ct > 0 || st > 0)) __builtin_amdgcn_sched_barrier(0);
-        const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
-        const u32x4 xhi = *(const u32x4*)&xs[buf][0][boff];
-        const u32x4 xlo = XN == 2 ? *(const u32x4*)&xs[buf][XN - 1][boff] : xhi;
+      for (int t = 0; t < 2 * NT; ++t) {
+        const int st = t / NT, ct = t % NT;
+        u32x4 nh = fh, nl = fl;
+        if (t + 1 < 2 * NT) frag(t + 1, nh, nl);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
           if constexpr (!TRANS)
-            step_mma<MODE>(ahi[rt][st], alo[rt][st], xhi, xlo, acc[rt][ct]);
+            step_mma<MODE>(ahi[rt][st], alo[rt][st], fh, fl, acc[rt][ct]);
           else
-            step_mma<MODE>(xhi, xlo, ahi[rt][st], alo[rt][st], acc[rt][ct]);
+            step_mma<MODE>(fh, fl, ahi[rt][st], alo[rt][st], acc[rt][ct]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        fh = nh;
+        fl = nl;
+      }
+    } else {
+#pragma unroll
+      for (int st = 0; st < 2; ++st) {
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
+          // keep at most kGroup X fragments in flight: the scheduler would
+          // otherwise hoist every LDS read of the step and spill accumulators
+          if (ct % kGroup == 0 && (ct > 0 || st > 0)) __builtin_amdgcn_sched_barrier(0);
+          const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
+          const u32x4 xhi = *(const u32x4*)&xs[buf][0][boff];
+#pragma unroll
+          for (int rt = 0; rt < RT; ++rt) {
+            if constexpr (!TRANS)
+              step_mma<MODE>(ahi[rt][st], alo[rt][st], xhi, xhi, acc[rt][ct]);
+            else
+              step_mma<MODE>(xhi, xhi, ahi[rt][st], alo[rt][st], acc[rt][ct]);
+          }
         }
       }
     }
   };
-  int s = 0;
-  if constexpr (DEPTH == 2) {
-    for (; s + 1 < nst; s += 2) {
-      stage(s, S0{});
-      stage(s + 1, S1{});
-    }
-  }
-  for (; s < nst; ++s) stage(s, S0{});
+  for (int s = 0; s < nst; ++s) stage(s);
 
   TACC* out = (TACC*)p.out + (int64_t)blockIdx.y * p.split_stride;
   const int Tst = p.lp >> 4;
