@@ -46,7 +46,7 @@ typedef enum {
   PBPQLP_EINVAL = 1,       /* an argument breaks the rules stated below            */
   PBPQLP_ENOMEM = 2,       /* caller workspace too small, or device allocation failed */
   PBPQLP_EHIP = 3,         /* a HIP runtime call or kernel launch failed           */
-  PBPQLP_EUNSUPPORTED = 4  /* valid input outside this build's limits (l > 256, ...) */
+  PBPQLP_EUNSUPPORTED = 4  /* valid input outside the library's limits (l > 256, ...) */
 } pbpqlp_status;
 
 /* Storage type of A and of the tall outputs Q and P. */

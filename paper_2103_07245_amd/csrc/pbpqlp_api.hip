@@ -523,7 +523,7 @@ const char* pbpqlp_status_string(pbpqlp_status s) {
     case PBPQLP_EINVAL: return "PBPQLP_EINVAL: invalid argument";
     case PBPQLP_ENOMEM: return "PBPQLP_ENOMEM: workspace too small or allocation failed";
     case PBPQLP_EHIP: return "PBPQLP_EHIP: HIP runtime error";
-    case PBPQLP_EUNSUPPORTED: return "PBPQLP_EUNSUPPORTED: outside this build's limits";
+    case PBPQLP_EUNSUPPORTED: return "PBPQLP_EUNSUPPORTED: outside the library's limits";
   }
   return "PBPQLP: unknown status";
 }

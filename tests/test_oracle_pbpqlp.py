@@ -139,7 +139,7 @@ def test_zero_matrix():
     np.testing.assert_allclose(r.P.T @ r.P, np.eye(6), atol=1e-15)
 
 
-def test_north_star_orientation_is_algorithm1_on_transpose():
+def test_orientation_is_algorithm1_on_transpose():
     rng = synth.rng_for(900)
     A = rng.standard_normal((50, 35))
     k, p, q = 6, 4, 2
