@@ -33,6 +33,14 @@ def test_version_and_status_strings():
         assert lib.pbpqlp_status_string(s).startswith(b"PBPQLP")
 
 
+def test_status_flags_match_header():
+    text = open(HEADER).read()
+    flags = dict((k, int(v)) for k, v in re.findall(r"#define PBPQLP_FLAG_([A-Z]+)\s+(\d+)", text))
+    assert flags == {"DEPENDENT": B.FLAG_DEPENDENT, "NONFINITE": B.FLAG_NONFINITE, "INTERNAL": B.FLAG_INTERNAL}
+    # distinct single bits
+    assert sorted(flags.values()) == [1, 2, 4]
+
+
 def test_info_struct_layout():
     assert ctypes.sizeof(B.InfoStruct) == 56
     assert ctypes.sizeof(B.Opts) == 48
