@@ -162,6 +162,107 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps)
     }
 }
 
+// Short tall matrices (the l x l stages, len <= 256 rows): one block per
+// 16-row panel, its four waves splitting the column tiles (wave w owns
+// K = w, w + 4, ...).  At step J the owner of column J forms Q_J = Y_J W_J
+// and hands it to the others through LDS; every wave then removes Q_J Ra_JK
+// from its own tiles K > J.  Each tile sees the same products in the same
+// order as in apply_kernel, so the results agree bit for bit; the chain per
+// step is one product, the hand-over and a barrier instead of a whole row
+// of products in one wave.
+template <typename T, int NT, int MAXT, int P>
+__device__ __forceinline__ void apply_cols_phase(typename Vec4<T>::type (&y)[(NT + 3) / 4], T* ops, T (*qb)[16 * 17],
+                                                 const T* __restrict__ Ra, const T* __restrict__ Dinv, int lp,
+                                                 int tid, int wave, int li, int lg) {
+  typedef typename Vec4<T>::type ACC;
+  constexpr auto& PH = kApplyPhases<NT, MAXT>;
+  if constexpr (P < PH.n) {
+    constexpr int J0 = PH.j0[P], J1 = PH.j1[P];
+    if constexpr (P > 0) lds_barrier();  // every wave is done with the previous phase
+    const int si = tid >> 4, sc = tid & 15;
+    {
+      int t = 0;
+#pragma unroll
+      for (int J = J0; J < J1; ++J)
+#pragma unroll
+        for (int K = J; K < NT; ++K, ++t)
+          ops[t * kTile + si * 17 + sc] =
+              (K == J) ? Dinv[J * 256 + si * 16 + sc] : -Ra[(int64_t)(16 * J + si) * lp + 16 * K + sc];
+    }
+    lds_barrier();
+    int t = 0;  // tile index of W_J in this phase; (J, K) follows at t + K - J
+#pragma unroll
+    for (int J = J0; J < J1; ++J) {
+      if (wave == J % 4) {
+        ACC q = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) q = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], y[J / 4][s4], q);
+        y[J / 4] = q;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) qb[J & 1][acc_row<T>(lg, r) * 17 + li] = q[r];
+      }
+      lds_barrier();
+      ACC q;
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) q[s4] = qb[J & 1][acc_row<T>(lg, s4) * 17 + li];
+#pragma unroll
+      for (int sl = 0; sl < (NT + 3) / 4; ++sl) {
+        const int K = wave + 4 * sl;
+        if (K > J && K < NT) {
+          const int tk = t + K - J;
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) y[sl] = mma_native(ops[tk * kTile + acc_row<T>(lg, s4) * 17 + li], q[s4], y[sl]);
+        }
+      }
+      t += NT - J;
+    }
+    apply_cols_phase<T, NT, MAXT, P + 1>(y, ops, qb, Ra, Dinv, lp, tid, wave, li, lg);
+  }
+}
+
+template <typename T, int NT, bool B>
+__global__ __launch_bounds__(256) void apply_cols_kernel(const ApplyP* pb, ApplyP ps) {
+  bool past;
+  const ApplyP prm = kparams<B>(pb, ps, past);
+  if (past) return;
+  const T* __restrict__ Y = (const T*)prm.Y;
+  const int64_t ldy = prm.ldy, len = prm.len, ldq = prm.ldq, ldqr = prm.ldqr;
+  const int l = prm.l, lp = prm.lp;
+  T* __restrict__ Qcm = (T*)prm.Qcm;
+  T* __restrict__ Qrm = (T*)prm.Qrm;
+  typedef typename Vec4<T>::type ACC;
+  constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
+  constexpr int NS = (NT + 3) / 4;
+  static_assert(MAXT >= NT, "a phase must hold one full row block");
+  __shared__ T ops[MAXT * kTile];
+  __shared__ T qb[2][16 * 17];
+  const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t arow = (int64_t)blockIdx.x * 16 + li;
+  const bool in = arow < len;
+  ACC y[NS];
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int K = wave + 4 * sl;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      y[sl][r] = (in && K < NT) ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
+  }
+  apply_cols_phase<T, NT, MAXT, 0>(y, ops, qb, (const T*)prm.Ra, (const T*)prm.Dinv, lp, tid, wave, li, lg);
+#pragma unroll
+  for (int sl = 0; sl < NS; ++sl) {
+    const int K = wave + 4 * sl;
+    if (K < NT) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * K + acc_row<T>(lg, r);
+        if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = y[sl][r];
+        if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[sl][r];
+      }
+    }
+  }
+}
+
 // Out = In M for a dense lp x lp M given row-major (Mr[k*ldm + j] = M[k][j]):
 // all output tiles accumulate at once while row blocks I of M stream
 // through LDS, MAXT / NT of them per phase.
@@ -251,6 +352,11 @@ static hipError_t apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, 
   if (e != hipSuccess) return e;
   const int64_t rows = Qcm ? (ldq > len ? ldq : len) : len;
   ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr};
+  if constexpr (sizeof(T) == 8) {
+    if (rows <= 256)  // the FP64 l x l stages: four waves per row panel
+      return launch_k(apply_cols_kernel<T, NT, false>, apply_cols_kernel<T, NT, true>,
+                      dim3((unsigned)((rows + 15) / 16)), dim3(256), s, p);
+  }
   return launch_k(apply_kernel<T, NT, false>, apply_kernel<T, NT, true>, dim3((unsigned)((rows + 63) / 64)),
                   dim3(256), s, p);
 }
