@@ -19,9 +19,9 @@ efficiently computing low-rank approximation of matrices", IEEE TSP 2021):
 Orientation.  ``pbpqlp`` works on an m x n matrix A with an n x l Gaussian
 Omega and returns (Q, L, P) with  A ~= Q @ L.T @ P.T : this is Algorithm 1
 applied to A^T (the paper's Phi -> Omega, Pbar -> Q basis, paper-Q -> P,
-paper Pt -> Qtilde, paper L -> L).  ``pbpqlp_alg1`` keeps the paper's own
-notation (A n1 x n2, Phi n1 x d, A ~= Q L P^T) and is used to check that
-mapping.
+paper Pt -> Qtilde, paper L -> L).  The paper's own orientation for an
+n1 x n2 matrix A with an n1 x d sketch Phi is therefore pbpqlp(A.T,
+Omega=Phi): its (P, L, Q) are the paper's (Q, L, P), with A ~= Q L P^T.
 
 Readings where the paper is silent or ambiguous:
 * orth() is a QR-type (upper-triangular) orthonormalization -- the paper says
@@ -49,7 +49,7 @@ import numpy as np
 
 __all__ = [
     "philox4x32_10", "bf16_rne", "omega", "householder_qr", "hh_orth",
-    "pbpqlp", "pbpqlp_alg1", "OracleResult", "rel_residual", "jacobi_svd",
+    "pbpqlp", "OracleResult", "rel_residual", "jacobi_svd",
     "validate_args",
 ]
 
@@ -212,14 +212,16 @@ class OracleResult:
 
 def pbpqlp(A: np.ndarray, k: int, p: int, q: int, seed: Optional[int] = None,
            Omega: Optional[np.ndarray] = None) -> OracleResult:
-    """PbP-QLP of an m x n matrix A in the spec orientation.
+    """PbP-QLP of an m x n matrix A in the spec orientation (the
+    method of Section III for A^T).
 
-    Steps (Algorithm 1 for A^T, in the paper's order):
-      Omega = randn(n, l);           Y = A Omega;      Qb = orth(Y)
-      repeat q times:  Z = A^T Qb;  Ph = orth(Z);  Y = A Ph;  Qb = orth(Y)
-      W = A^T Qb  (the projection B^T);   W = P R          (unpivoted QR)
-      R^T = Qtilde U  (unpivoted QR);     L = U^T;          Q = Qb Qtilde
-    so that A ~= Q L^T P^T (the paper's eq. (Ahat) written for A^T)."""
+    Qb is an orthonormal basis of the sketch (A A^T)^q A Omega (eq. (c) with
+    the power scheme of Section III-B, orthonormalized after every product
+    with A or A^T, as that section requires for rounding reasons); P and R
+    come from the unpivoted QR of the projection A^T Qb (eqs. (D), (DQR));
+    Qtilde and U from the unpivoted QR of R^T (eq. (R^T = Pt Rt)), L = U^T;
+    and the returned basis is Q = Qb Qtilde, so that A ~= Q L^T P^T, the
+    paper's eq. (Ahat) written for A^T."""
     A = np.asarray(A)
     m, n = A.shape
     l = validate_args(m, n, k, p, q)
@@ -243,27 +245,6 @@ def pbpqlp(A: np.ndarray, k: int, p: int, q: int, seed: Optional[int] = None,
     Qt, U = householder_qr(R.T)
     L = U.T
     return OracleResult(Q=Qb @ Qt, L=L, P=P, R=R, Qbasis=Qb, Qtilde=Qt, Omega=Omega)
-
-
-def pbpqlp_alg1(A: np.ndarray, Phi: np.ndarray, q: int):
-    """Algorithm 1 in the paper's own notation: A is n1 x n2, Phi is n1 x d.
-
-      C = A^T Phi; Pbar = orth(C)
-      for i = 1..q:  C = A Pbar; Pbar = orth(C);  C = A^T Pbar; Pbar = orth(C)
-      D = A Pbar;  [Q, R] = qr(D);  [Pt, Rt] = qr(R^T);  P = Pbar Pt;  L = Rt^T
-    Returns (Q, L, P, R) with A ~= Q L P^T."""
-    A = np.asarray(A, dtype=np.float64)
-    C = A.T @ Phi
-    Pbar = hh_orth(C)
-    for _ in range(q):
-        C = A @ Pbar
-        Pbar = hh_orth(C)
-        C = A.T @ Pbar
-        Pbar = hh_orth(C)
-    D = A @ Pbar
-    Q, R = householder_qr(D)
-    Pt, Rt = householder_qr(R.T)
-    return Q, Rt.T, Pbar @ Pt, R
 
 
 def rel_residual(A: np.ndarray, Q: np.ndarray, L: np.ndarray, P: np.ndarray,

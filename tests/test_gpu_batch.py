@@ -135,3 +135,30 @@ def test_fp64_batch_and_padded_rows():
         ref = oracle_pbpqlp(A64, ks[i], ps[i], qs[i], seeds[i])
         assert np.abs(bt.L[i].cpu().numpy() - ref.L).max() <= 1e-9
     bt.close()
+
+
+def test_batch_full_range_against_oracle():
+    """Batched problems at the corners of the C4 ranges (m in [256, 4096],
+    n in [256, 2048], rank r in [8, 64], l = r + 8 up to 72), odd sizes
+    included, each against the FP64 oracle at the FP32 tolerance."""
+    shapes = [(4096, 2048, 64), (4096, 256, 8), (256, 2048, 64), (256, 256, 8), (3001, 1999, 41),
+              (4095, 2047, 64), (2222, 1023, 17)]
+    members = []
+    for b, (m, n, r) in enumerate(shapes):
+        w = synth.config4_matrix(500 + b, m, n, r)
+        members.append((w.A, w.k, w.p, w.q, w.seed))
+    print(f"batch of {len(members)} problems at the C4 range corners", flush=True)
+    bt, _ = _batch(members)
+    bt.run()
+    torch.cuda.synchronize()
+    for i, (A, k, p, q, seed) in enumerate(members):
+        A64 = A.astype(np.float64)
+        ref = oracle_pbpqlp(A64, k, p, q, seed)
+        r_ref = rel_residual(A64, ref.Q, ref.L, ref.P)
+        Q, L, P = (t.cpu().numpy().astype(np.float64) for t in (bt.Q[i], bt.L[i], bt.P[i]))
+        assert abs(rel_residual(A64, Q, L, P) - r_ref) <= 1e-5, (i, shapes[i])
+        l = k + p
+        assert np.abs(Q.T @ Q - np.eye(l)).max() <= 1e-5, i
+        assert np.abs(P.T @ P - np.eye(l)).max() <= 1e-5, i
+        assert np.max(np.abs(np.diag(L)[:k] - np.diag(ref.L)[:k])) <= 1e-5 * ref.L[0, 0], i
+    bt.close()

@@ -6,7 +6,7 @@
   projection Q Q^T A that the randomized SVD with the same Omega also returns;
 * closed forms: L = chol(R R^T), ||A - Ahat||_F^2 = ||A||_F^2 - ||L||_F^2;
 * exact recovery when rank(A) <= l, orthonormality, argument rules, and the
-  orientation (the spec form is the paper's Algorithm 1 applied to A^T).
+  paper's own orientation (pbpqlp of A^T) against the defining equations.
 """
 import math
 
@@ -15,8 +15,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import (householder_qr, omega, pbpqlp, pbpqlp_alg1, rel_residual,
-                    validate_args)
+from oracle import (householder_qr, omega, pbpqlp, rel_residual, validate_args)
 
 
 def _planted_tiny(m, n, sig, seed):
@@ -139,22 +138,54 @@ def test_zero_matrix():
     np.testing.assert_allclose(r.P.T @ r.P, np.eye(6), atol=1e-15)
 
 
-def test_orientation_is_algorithm1_on_transpose():
+def test_paper_orientation_from_definitions():
+    """The paper's orientation (A is n1 x n2, Phi is n1 x d, A ~= Q L P^T) is
+    pbpqlp(A.T, Omega=Phi) with the roles (P, L, Q) -> (Q, L, P).  Checked
+    against the defining equations of Section III rather than against a
+    second implementation:
+      Pbar: orthonormal, QR-type basis of (A^T A)^q A^T Phi (eq. (c) and the
+            power scheme of Section III-B);
+      D = A Pbar = Q R with Q orthonormal, R upper with diag >= 0 (eqs. (D),
+            (DQR));
+      R^T = Pt Rt, L = Rt^T, P = Pbar Pt: then Q^T A P = L is lower
+            triangular and L L^T = R R^T (eq. (R^T = Pt Rt));
+      A_hat = Q L P^T = Q Q^T A Pbar Pbar^T (eq. (Ahat))."""
     rng = synth.rng_for(900)
-    A = rng.standard_normal((50, 35))
-    k, p, q = 6, 4, 2
-    r = pbpqlp(A, k, p, q, seed=11)
-    Qp, Lp, Pp, Rp = pbpqlp_alg1(A.T, r.Omega, q)     # paper notation on A^T
-    np.testing.assert_allclose(Qp, r.P, atol=1e-13)    # paper Q  <-> spec P
-    np.testing.assert_allclose(Pp, r.Q, atol=1e-13)    # paper P  <-> spec Q Qtilde
-    np.testing.assert_allclose(Lp, r.L, atol=1e-13)
-    # A^T ~= Qp Lp Pp^T  <=>  A ~= Q L^T P^T
-    np.testing.assert_allclose((Qp @ Lp @ Pp.T).T, r.reconstruct(), atol=1e-13)
-    # the literal "Q L P^T" is a different, clearly worse matrix on a decaying spectrum
-    B = _planted_tiny(50, 35, 0.7 ** np.arange(20), 902)
-    rb = pbpqlp(B, k, p, q, seed=11)
+    A = rng.standard_normal((50, 35))          # n1 x n2
+    d, q = 10, 2
+    Phi = omega(50, d, 11)
+    r = pbpqlp(A.T, 6, 4, q, Omega=Phi)
+    Pbar, Qp, Lp, Pp, Rp = r.Qbasis, r.P, r.L, r.Q, r.R
+    I = np.eye(d)
+    # Pbar spans the power sketch, nested like a QR factor of it
+    K = A.T @ Phi
+    for _ in range(q):
+        K = A.T @ (A @ K)
+    T = Pbar.T @ K
+    np.testing.assert_allclose(Pbar @ T, K, atol=1e-11 * np.abs(K).max())
+    np.testing.assert_allclose(np.tril(T, -1), 0.0, atol=1e-11 * np.abs(K).max())
+    assert np.all(np.diag(T) > 0)
+    np.testing.assert_allclose(Pbar.T @ Pbar, I, atol=1e-13)
+    # D = A Pbar = Q R
+    np.testing.assert_allclose(Qp @ Rp, A @ Pbar, atol=1e-12)
+    np.testing.assert_allclose(Qp.T @ Qp, I, atol=1e-13)
+    assert np.all(np.diag(Rp) >= 0) and np.array_equal(np.tril(Rp, -1), np.zeros((d, d)))
+    # Q^T A P = L, lower triangular; L L^T = R R^T; P orthonormal in span(Pbar)
+    np.testing.assert_allclose(Qp.T @ A @ Pp, Lp, atol=1e-12)
+    assert np.array_equal(np.triu(Lp, 1), np.zeros((d, d))) and np.all(np.diag(Lp) >= 0)
+    np.testing.assert_allclose(Lp @ Lp.T, Rp @ Rp.T, atol=1e-12)
+    np.testing.assert_allclose(Pp.T @ Pp, I, atol=1e-13)
+    np.testing.assert_allclose(Pbar @ (Pbar.T @ Pp), Pp, atol=1e-13)
+    # A_hat = Q L P^T = Q Q^T A Pbar Pbar^T
+    np.testing.assert_allclose(Qp @ Lp @ Pp.T, Qp @ (Qp.T @ A @ Pbar) @ Pbar.T, atol=1e-12)
+    # the north-star form of A^T: A^T ~= Q' L^T P'^T with (Q', P') = (Pp, Qp)
+    np.testing.assert_allclose(r.reconstruct(), (Qp @ Lp @ Pp.T).T, atol=1e-13)
+    # the literal "Q L P^T" of the north-star outputs is a different, clearly
+    # worse matrix on a decaying spectrum
+    Bm = _planted_tiny(50, 35, 0.7 ** np.arange(20), 902)
+    rb = pbpqlp(Bm, 6, 4, q, seed=11)
     lit = rb.Q @ rb.L @ rb.P.T
-    assert np.linalg.norm(B - lit) > 3 * np.linalg.norm(B - rb.reconstruct())
+    assert np.linalg.norm(Bm - lit) > 3 * np.linalg.norm(Bm - rb.reconstruct())
 
 
 @pytest.mark.parametrize("args", [(0, 5, 1, 0, 0), (5, 5, 0, 0, 0), (5, 5, 3, -1, 0),
