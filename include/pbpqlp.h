@@ -152,6 +152,29 @@ pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t 
                                    int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
                                    void* stream);
 
+/* ---- allocation-free variant ----
+ *
+ * For callers that cannot allocate device memory: code recorded under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * pbpqlp_factor_noalloc is pbpqlp_factor (same arguments, rules, kernels,
+ * results bit for bit for the same options) with its workspace taken from a
+ * static device array of PBPQLP_NOALLOC_SCRATCH_BYTES that the library holds
+ * on every GPU it runs on until the process ends; opts.workspace is ignored.
+ * It calls no hipMalloc, hipFree or other allocating routine and creates no
+ * trace events.  All calls on one GPU share that GPU's array, which keeps the
+ * last call's contents: calls that overlap on one GPU (different streams or
+ * threads without ordering between them) race and give undefined results.
+ * The device is the calling thread's current HIP device.
+ * Errors: as pbpqlp_factor; EUNSUPPORTED when the problem's workspace
+ * (pbpqlp_workspace_size) exceeds PBPQLP_NOALLOC_SCRATCH_BYTES (checked before
+ * anything touches the device); EHIP if the array's address cannot be
+ * obtained. */
+#define PBPQLP_NOALLOC_SCRATCH_BYTES (64ull << 20)
+pbpqlp_status pbpqlp_factor_noalloc(const void* A, int64_t m, int64_t n, int64_t lda,
+                                    pbpqlp_dtype dt, int k, int p, int q, uint64_t seed, void* Q,
+                                    int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
+                                    const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream);
+
 /* The approximation A_hat = Q L^T P^T (eq. (Ahat), for A^T) of a factorization:
  *   Q (m x l), P (n x l) in dtype dt, L (l x l FP64, lower triangular), all
  *   device, row-major; Ahat (m x n, dt, ldh >= n) is written.

@@ -112,11 +112,15 @@ std::vector<TraceRec> g_trace;
 size_t g_trace_n = 0;
 int g_trace_level = 0;  // 0 off, 1 streaming products, 2 all hot-path kernels
 
+// Set while an allocation-free call runs on this thread: no trace events are
+// created then (creating them is the one allocation tracing would make).
+thread_local bool t_no_trace = false;
+
 struct TraceScope {
   TraceRec* rec = nullptr;
   hipStream_t st;
   TraceScope(const char* name, double bytes, double flops, hipStream_t s, int level = 2) : st(s) {
-    if (g_trace_level < level || pbq::current_recorder()) return;
+    if (g_trace_level < level || pbq::current_recorder() || t_no_trace) return;
     std::lock_guard<std::mutex> lk(g_trace_mu);
     if (g_trace_n == g_trace.size()) {
       TraceRec r;
@@ -612,6 +616,70 @@ pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pb
                             pbpqlp_info* d_info, void* stream) {
   return factor_impl(A, m, n, lda, dt, nullptr, 0, k, p, q, seed, Q, ldq, L, ldl, P, ldp, opts,
                      d_info, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free factorization.  The workspace is one file-scope device
+// array; every GPU the library runs on holds its own copy for the life of the
+// process.  Host code never passes the array's name to a kernel: the device
+// address of the current device's copy is looked up once per device with
+// hipGetSymbolAddress and used from then on.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[PBPQLP_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+pbpqlp_status scratch_of_current_device(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PBPQLP_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PBPQLP_EHIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PBPQLP_OK;
+}
+
+struct NoTrace {
+  NoTrace() { t_no_trace = true; }
+  ~NoTrace() { t_no_trace = false; }
+};
+
+}  // namespace
+
+extern "C" {
+
+pbpqlp_status pbpqlp_factor_noalloc(const void* A, int64_t m, int64_t n, int64_t lda,
+                                    pbpqlp_dtype dt, int k, int p, int q, uint64_t seed, void* Q,
+                                    int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
+                                    const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream) {
+  pbpqlp_opts o;
+  pbpqlp_default_opts(&o);
+  if (opts) o = *opts;
+  o.workspace = nullptr;
+  o.workspace_bytes = 0;
+  // the bound of pbpqlp_workspace_size holds for every q and lda; sizes are
+  // checked before anything touches the device
+  size_t need = 0;
+  pbpqlp_status s = pbpqlp_workspace_size(m, n, k, p, dt, &o, &need);
+  if (s) return s;
+  if (need > (size_t)PBPQLP_NOALLOC_SCRATCH_BYTES) return PBPQLP_EUNSUPPORTED;
+  void* ptr = nullptr;
+  s = scratch_of_current_device(&ptr);
+  if (s) return s;
+  o.workspace = ptr;
+  o.workspace_bytes = (size_t)PBPQLP_NOALLOC_SCRATCH_BYTES;
+  NoTrace nt;
+  return factor_impl(A, m, n, lda, dt, nullptr, 0, k, p, q, seed, Q, ldq, L, ldl, P, ldp, &o, d_info,
+                     stream);
 }
 
 pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t lda,

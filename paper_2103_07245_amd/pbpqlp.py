@@ -77,6 +77,8 @@ class TunePlanStruct(ctypes.Structure):
     _fields_ = [("split_k", ctypes.c_int), ("gram_workgroups", ctypes.c_int), ("ms", ctypes.c_double)]
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PBPQLP_NOALLOC_SCRATCH_BYTES
+
 MLP_IN, MLP_HIDDEN, MLP_OUT, MLP_PARAMS = 64, 128, 6, 25606
 PROBE_K, PROBE_P = 56, 8
 
@@ -102,6 +104,8 @@ def _lib():
         lib.pbpqlp_factor.restype = i32
         lib.pbpqlp_factor.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, u64, vp, i64, dp, i64,
                                       vp, i64, ctypes.POINTER(Opts), vp, vp]
+        lib.pbpqlp_factor_noalloc.restype = i32
+        lib.pbpqlp_factor_noalloc.argtypes = lib.pbpqlp_factor.argtypes
         lib.pbpqlp_omega.restype = i32
         lib.pbpqlp_omega.argtypes = [i64, i32, u64, i32, vp, i64, vp]
         lib.pbpqlp_matmul.restype = i32
@@ -306,6 +310,30 @@ def factor(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", sp
                    gram_wg)
     Q, L, P = f(A, seed)
     return Q, L, P, f.info()
+
+
+def factor_noalloc(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", split_k: int = 0,
+                   out=None):
+    """pbpqlp_factor_noalloc: the factorization with the library's static
+    device scratch as workspace.  ``out`` = (Q, L, P, info_buf) preallocated
+    by the caller (then this call allocates nothing); returns (Q, L, P, info)."""
+    A = _rowmajor(A, "A")
+    m, n = A.shape
+    l = k + p
+    if out is None:
+        out = (torch.empty((m, l), dtype=A.dtype, device=A.device),
+               torch.empty((l, l), dtype=torch.float64, device=A.device),
+               torch.empty((n, l), dtype=A.dtype, device=A.device),
+               torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device))
+    Q, L, P, info = out
+    o = make_opts(plan, split_k)
+    _check(_lib().pbpqlp_factor_noalloc(ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0), _dt(A), k, p, q,
+                                        ctypes.c_uint64(seed), ctypes.c_void_p(Q.data_ptr()), Q.stride(0),
+                                        ctypes.c_void_p(L.data_ptr()), L.stride(0),
+                                        ctypes.c_void_p(P.data_ptr()), P.stride(0), ctypes.byref(o),
+                                        ctypes.c_void_p(info.data_ptr()), _stream(A.device)),
+           "pbpqlp_factor_noalloc")
+    return Q, L, P, info
 
 
 def factor_sketch(A: torch.Tensor, Omega: torch.Tensor, k: int, p: int, q: int, plan="native"):

@@ -189,3 +189,25 @@ def test_tune_load_rejects_malformed_files(tmp_path):
     with pytest.raises(B.PbpqlpError):
         B.tune_load(tmp_path / "missing.txt")
     B.tune_clear()
+
+
+def test_noalloc_rejects_oversized_problem_before_the_device():
+    """pbpqlp_factor_noalloc checks the problem's workspace against its static
+    array (PBPQLP_NOALLOC_SCRATCH_BYTES) before any device call: a 16384^2
+    problem with l = 256 is refused here, on a host without a GPU."""
+    text = open(HEADER).read()
+    assert re.search(r"#define PBPQLP_NOALLOC_SCRATCH_BYTES \(64ull << 20\)", text)
+    assert B.NOALLOC_SCRATCH_BYTES == 64 << 20
+    lib = B.library()
+    need = ctypes.c_size_t(0)
+    assert lib.pbpqlp_workspace_size(16384, 16384, 200, 56, B.F32, None, ctypes.byref(need)) == B.OK
+    assert need.value > B.NOALLOC_SCRATCH_BYTES
+    st = lib.pbpqlp_factor_noalloc(FAKE, 16384, 16384, 16384, B.F32, 200, 56, 1, ctypes.c_uint64(1),
+                                   ctypes.c_void_p(0x2000), 256, ctypes.c_void_p(0x3000), 256,
+                                   ctypes.c_void_p(0x4000), 256, None, None, None)
+    assert st == B.EUNSUPPORTED
+    # argument errors come first, as for pbpqlp_factor
+    st = lib.pbpqlp_factor_noalloc(FAKE, 100, 80, 80, B.F32, 0, 3, 1, ctypes.c_uint64(1),
+                                   ctypes.c_void_p(0x2000), 8, ctypes.c_void_p(0x3000), 8,
+                                   ctypes.c_void_p(0x4000), 8, None, None, None)
+    assert st == B.EINVAL
