@@ -114,7 +114,8 @@ int pbpqlp_version(void);
 /* Default options: every pass NATIVE, automatic split, library-owned workspace. */
 void pbpqlp_default_opts(pbpqlp_opts* opts);
 
-/* Bytes of device workspace pbpqlp_factor needs for this problem.
+/* Bytes of device workspace pbpqlp_factor (and pbpqlp_factor_rr in either
+ * orientation) needs for this problem.
  * Errors: EINVAL for arguments pbpqlp_factor would reject; EUNSUPPORTED for l > 256. */
 pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_dtype dt,
                                     const pbpqlp_opts* opts, size_t* bytes);
@@ -151,6 +152,62 @@ pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t 
                                    int q, void* Q, int64_t ldq, double* L, int64_t ldl, void* P,
                                    int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
                                    void* stream);
+
+/* ---- orientation and rank-revealing outputs ----
+ *
+ * The paper states the method for an n1 x n2 matrix with n1 >= n2 and a
+ * sketch A^T Phi, Phi n1 x d (Algorithm 1), and returns A ~= Q L P^T.
+ * pbpqlp_factor runs that algorithm on A^T (sketch A Omega, Omega n x l), so
+ * its outputs satisfy A ~= Q L^T P^T.  pbpqlp_factor_rr offers both, and the
+ * parts of the factorization that reveal the numerical rank (Section IV-A:
+ * the partition of R, eqs. (Rparti), (sigmak_R11), (2normR22); Section IV-C:
+ * the partition of L, eq. (Lparti), and the Mathias-Stewart inequalities
+ * sigma_min(L11) >= sigma_min(R11), sigma_1(L22) <= sigma_1(R22)).
+ *
+ *   PBPQLP_ORIENT_AT   : A ~= Q L^T P^T, Algorithm 1 applied to A^T (the form
+ *                        of pbpqlp_factor, bit for bit).
+ *   PBPQLP_ORIENT_A    : A ~= Q L P^T, Algorithm 1 as stated: Phi is m x l
+ *                        (element (i, j) from flat index i l + j, the same
+ *                        generator), the power passes alternate A^T and A,
+ *                        the last QR is that of D = A Pbar (eq. (DQR)).  It is
+ *                        the ORIENT_AT factorization of A^T with the roles of
+ *                        Q and P exchanged.
+ *   PBPQLP_ORIENT_AUTO : ORIENT_A when m >= n, else ORIENT_AT, i.e. the
+ *                        algorithm runs on whichever of A, A^T has at least as
+ *                        many rows as columns, as the paper assumes.
+ * The rank-k pieces need no copy: with row-major storage Q[:, :k], P[:, :k]
+ * and L11 = L[:k, :k] are the same pointers with the same leading dimensions,
+ * and Q1 L11 P1^T (ORIENT_A) or Q1 L11^T P1^T (ORIENT_AT) is the rank-k
+ * approximation Q1 Q1^T A of the paper's Section IV-B. */
+#define PBPQLP_ORIENT_AT 0
+#define PBPQLP_ORIENT_A 1
+#define PBPQLP_ORIENT_AUTO 2
+
+typedef struct {
+  int orientation;          /* in: PBPQLP_ORIENT_*                                 */
+  int orientation_used;     /* out (host, written on success): AT or A             */
+  double* R;                /* out, optional (NULL): l x l FP64 device matrix,
+                               row-major, ldr >= l: the upper-triangular R of the
+                               last QR (eq. (DQR)), lower part written 0; its
+                               diagonal holds the R-values                         */
+  int64_t ldr;
+  double rank_tol;          /* in, >= 0: threshold of the rank estimate            */
+  int* d_rank;              /* out, optional device int: the numerical rank
+                               estimated from the L-values, the number of leading
+                               L_ii > rank_tol * L_11 before the first that is not
+                               (0 for A = 0, l if none drops)                      */
+} pbpqlp_rr;
+
+/* pbpqlp_factor in the orientation rr->orientation, with the optional R and
+ * rank outputs of rr (same stream semantics: R and *d_rank are valid once the
+ * stream reaches the end of the call).  Arguments as pbpqlp_factor; in both
+ * orientations Q is m x l and P is n x l.  Errors: as pbpqlp_factor; EINVAL
+ * for rr == NULL, an unknown orientation, ldr < l, a misaligned or aliased R,
+ * rank_tol < 0 or NaN. */
+pbpqlp_status pbpqlp_factor_rr(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                               int k, int p, int q, uint64_t seed, void* Q, int64_t ldq, double* L,
+                               int64_t ldl, void* P, int64_t ldp, const pbpqlp_opts* opts,
+                               pbpqlp_rr* rr, pbpqlp_info* d_info, void* stream);
 
 /* ---- allocation-free variant ----
  *

@@ -73,6 +73,8 @@ hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, 
 // write L = U^T (lower) from upper U, zero elsewhere; rowsq[i] = sum_j L[i][j]^2 (or null)
 hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, int64_t ldl,
                                 double* rowsq, hipStream_t s);
+// number of leading L_ii > tol * L_11 (L row-major FP64) into *out (device)
+hipError_t launch_rank_estimate(const double* L, int64_t ldl, int l, double tol, int* out, hipStream_t s);
 hipError_t launch_info_init(void* info, int l, int q, hipStream_t s);
 hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts,
                                 const double* rowsq, int l, hipStream_t s);

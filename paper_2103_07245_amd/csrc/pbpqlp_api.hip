@@ -151,8 +151,11 @@ const char* mode_name(int mode) {
 
 // Everything one factorization needs, carved from one workspace block.
 struct Ctx {
-  // problem
+  // problem: A is m x n (lda) as stored.  The method runs on M = A, or on
+  // M = A^T when tv (the paper's own orientation): M's rows and columns are
+  // mM x nM, and a product with M or M^T is a pass with A or A^T.
   int64_t m = 0, n = 0, lda = 0;
+  bool tv = false;
   int l = 0, lp = 0, lp32 = 0, q = 0;
   bool f64 = false;
   size_t el = 4;           // bytes of one data element
@@ -177,7 +180,17 @@ struct Ctx {
   int* dep = nullptr;
   double* rowsq = nullptr;
   uint64_t ncall = 0;
+  // optional outputs: R of the projection's QR (row-major, ldr_out) and the
+  // numerical rank estimated from the L-values
+  double* r_out = nullptr;
+  int64_t ldr_out = 0;
+  double rank_tol = 0.0;
+  int* rank_out = nullptr;
 
+  int64_t mM() const { return tv ? n : m; }
+  int64_t nM() const { return tv ? m : n; }
+  int64_t ldmM() const { return tv ? ldn : ldm; }
+  int64_t ldnM() const { return tv ? ldm : ldn; }
   // Split plan of a pass in compute mode `mode` (grid blocks depend on it).
   Split split_for(int mode, bool trans) const {
     const int64_t rb = stream_rows_per_block(mode);
@@ -185,32 +198,38 @@ struct Ctx {
     return plan_split((len + rb - 1) / rb, klen, forced_split);
   }
   // Sizes of the split partials and the ||A||^2 partials for the passes this
-  // context will run (sketch: K1; power: K1 and K2; projection: K2).
-  void plan_buffers(bool k1_sketch, bool k1_power, bool k2_power, bool k2_proj) {
+  // context will run: the sketch M X, the power passes (both directions) and
+  // the projection M^T X.  ||A||_F^2 is accumulated on the one of the sketch
+  // and the projection that is a product A X: the sketch for M = A, the
+  // projection for M = A^T.
+  void plan_buffers(bool sketch, bool power, bool proj) {
     part_bytes = 0;
     auto need = [&](int mode, bool trans) {
       const Split sp = split_for(mode, trans);
       const size_t b = sp.S > 1 ? (size_t)sp.S * lp * (trans ? ldn : ldm) * el : 0;
       if (b > part_bytes) part_bytes = b;
     };
-    if (k1_sketch) need(mode_sketch, false);
-    if (k1_power) need(mode_power, false);
-    if (k2_power) need(mode_power, true);
-    if (k2_proj) need(mode_proj, true);
-    const int64_t rb = stream_rows_per_block(mode_sketch);
+    if (sketch) need(mode_sketch, tv);
+    if (power) {
+      need(mode_power, false);
+      need(mode_power, true);
+    }
+    if (proj) need(mode_proj, !tv);
+    const int nmode = tv ? mode_proj : mode_sketch;
+    const int64_t rb = stream_rows_per_block(nmode);
     k1_blocks = (int)((m + rb - 1) / rb);
-    k1_splits = split_for(mode_sketch, false).S;
+    k1_splits = split_for(nmode, false).S;
   }
 
   void carve(Bump& b, bool need16) {
     const int64_t ldmax = ldm > ldn ? ldm : ldn;
-    Om = b.take((size_t)lp32 * ldn * el);
-    Y = b.take((size_t)lp32 * ldm * el);
-    Qm = b.take((size_t)lp32 * ldm * el);
-    W1m = b.take((size_t)lp32 * ldm * el);
-    Zn = b.take((size_t)lp32 * ldn * el);
-    Pn = b.take((size_t)lp32 * ldn * el);
-    W1n = b.take((size_t)lp32 * ldn * el);
+    Om = b.take((size_t)lp32 * ldnM() * el);
+    Y = b.take((size_t)lp32 * ldmM() * el);
+    Qm = b.take((size_t)lp32 * ldmM() * el);
+    W1m = b.take((size_t)lp32 * ldmM() * el);
+    Zn = b.take((size_t)lp32 * ldnM() * el);
+    Pn = b.take((size_t)lp32 * ldnM() * el);
+    W1n = b.take((size_t)lp32 * ldnM() * el);
     if (need16) {
       Xhi = b.take((size_t)lp32 * ldmax * 2);
       Xlo = b.take((size_t)lp32 * ldmax * 2);
@@ -250,7 +269,7 @@ bool valid_args(int64_t m, int64_t n, int k, int p, int q) {
 }
 
 pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, int k, int p,
-                    int q, const pbpqlp_opts* opts, bool batched = false) {
+                    int q, const pbpqlp_opts* opts, bool batched = false, bool tv = false) {
   if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
   if (!valid_args(m, n, k, p, q) || lda < n) return PBPQLP_EINVAL;
   const int l = k + p;
@@ -258,7 +277,7 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
   pbpqlp_opts o;
   pbpqlp_default_opts(&o);
   if (opts) o = *opts;
-  c.m = m; c.n = n; c.lda = lda; c.q = q;
+  c.m = m; c.n = n; c.lda = lda; c.q = q; c.tv = tv;
   c.l = l; c.lp = (int)rup(l, 16); c.lp32 = (int)rup(l, 32);
   c.f64 = dt == PBPQLP_F64;
   c.el = c.f64 ? 8 : 4;
@@ -280,7 +299,7 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
   }
   c.forced_split = split > 0 ? split : 0;
   if (gram > 0) c.gram_target = gram;
-  c.plan_buffers(true, q > 0, q > 0, true);
+  c.plan_buffers(true, q > 0, true);
   return PBPQLP_OK;
 }
 
@@ -306,6 +325,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
       if (unit_columns) xs = std::ldexp(1.0f, (int)std::floor(0.5 * std::log2((double)xlen)));
       a.out_scale = 1.0f / (a.a_scale * xs);
     }
+    TraceScope ts("convert", (double)xlen * c.l * (4.0 + (mode == M_BF16X3 ? 4.0 : 2.0)), 0.0, st);
     PBQ_CHECK(launch_convert(mode, (const float*)X, ldx, xlen, c.l, c.lp32, xs, c.Xhi, c.Xlo, st));
     a.X = c.Xhi;
     a.Xlo = c.Xlo;
@@ -336,8 +356,10 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
     TraceScope ts(nm.c_str(), bytes, 2.0 * c.m * c.n * c.l, st, 1);
     PBQ_CHECK(launch_stream(trans, mode, a, st));
   }
-  if (sp.S > 1)
+  if (sp.S > 1) {
+    TraceScope ts("splitk_reduce", (double)(sp.S + 1) * olen * c.l * c.el, 0.0, st);
     PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, a.split_stride, sp.S, ldo, c.lp, olen, out, ldo, st));
+  }
   return PBPQLP_OK;
 }
 
@@ -374,6 +396,7 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     src = dst;
   }
   if (Rkeep) {
+    TraceScope ts("r2r1", 3.0 * c.lp * c.lp * 8, 2.0 * c.lp * c.lp * c.lp, st);
     if (passes == 1)
       PBQ_CHECK(launch_copy_mat(c.R1, c.lp, c.lp, c.lp, Rkeep, ldrk, 1, st));
     else
@@ -388,48 +411,75 @@ pbpqlp_status small_qr(Ctx& c, const double* Rrow, int64_t ldr, void* info, hipS
   return orth(c, true, Rrow, ldr, c.l, 2, c.Qt64, c.M1, c.U, c.lp, nullptr, 0, info, st);
 }
 
+// The whole method on M (M = A, or M = A^T for the paper's orientation).
+// Q (mM x l) receives Q Qt and P (nM x l) the orthonormal factor of the
+// projection, so that M ~= Q L^T P^T.  A product M X is a pass with A when
+// M = A and with A^T when M = A^T; M^T X the other way round.
 pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L, int64_t ldl,
                          void* P, int64_t ldp, pbpqlp_info* info, hipStream_t st) {
-  PBQ_CHECK(launch_info_init(info, c.l, c.q, st));
-  // S0: sketch matrix, column-major (lp32 x ldn): generated, or the caller's
-  if (c.omega_in)
-    PBQ_CHECK(launch_rm_to_cm(c.f64, c.omega_in, c.ldo_in, c.n, c.l, c.lp32, c.Om, c.ldn, st));
-  else
-    PBQ_CHECK(launch_omega_cm(c.f64, c.n, c.l, c.lp32, c.seed, c.Om, c.ldn, st));
-  // S1: Y = A Omega (+ ||A||_F^2)
+  const bool tM = c.tv, tMt = !c.tv;   // direction of the passes with A for M X and M^T X
+  const int64_t mM = c.mM(), nM = c.nM(), ldmM = c.ldmM(), ldnM = c.ldnM();
+  {
+    TraceScope ts("info", 0.0, 0.0, st);
+    PBQ_CHECK(launch_info_init(info, c.l, c.q, st));
+  }
+  // S0: sketch matrix, column-major (lp32 x ldnM): generated, or the caller's
+  {
+    TraceScope ts("omega", (double)nM * c.l * c.el, 0.0, st);
+    if (c.omega_in)
+      PBQ_CHECK(launch_rm_to_cm(c.f64, c.omega_in, c.ldo_in, nM, c.l, c.lp32, c.Om, ldnM, st));
+    else
+      PBQ_CHECK(launch_omega_cm(c.f64, nM, c.l, c.lp32, c.seed, c.Om, ldnM, st));
+  }
+  // S1: Y = M Omega (+ ||A||_F^2 when this pass is A X)
   pbpqlp_status s;
-  s = stream_pass(c, false, c.mode_sketch, A, c.Om, c.ldn, c.n, c.omega_in != nullptr, c.Y, c.ldm,
-                  c.normA, st);
+  s = stream_pass(c, tM, c.mode_sketch, A, c.Om, ldnM, nM, c.omega_in != nullptr, c.Y, ldmM,
+                  tM ? nullptr : c.normA, st);
   if (s) return s;
-  s = orth(c, c.f64, c.Y, c.ldm, c.m, c.q == 0 ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
+  s = orth(c, c.f64, c.Y, ldmM, mM, c.q == 0 ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
   if (s) return s;
   // S3: power iterations with re-orthonormalization after each product
   for (int i = 1; i <= c.q; ++i) {
-    s = stream_pass(c, true, c.mode_power, A, c.Qm, c.ldm, c.m, true, c.Zn, c.ldn, nullptr, st);
+    s = stream_pass(c, tMt, c.mode_power, A, c.Qm, ldmM, mM, true, c.Zn, ldnM, nullptr, st);
     if (s) return s;
-    s = orth(c, c.f64, c.Zn, c.ldn, c.n, 1, c.Pn, c.W1n, nullptr, 0, nullptr, 0, info, st);
+    s = orth(c, c.f64, c.Zn, ldnM, nM, 1, c.Pn, c.W1n, nullptr, 0, nullptr, 0, info, st);
     if (s) return s;
-    s = stream_pass(c, false, c.mode_power, A, c.Pn, c.ldn, c.n, true, c.Y, c.ldm, nullptr, st);
+    s = stream_pass(c, tM, c.mode_power, A, c.Pn, ldnM, nM, true, c.Y, ldmM, nullptr, st);
     if (s) return s;
-    s = orth(c, c.f64, c.Y, c.ldm, c.m, i == c.q ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
+    s = orth(c, c.f64, c.Y, ldmM, mM, i == c.q ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
     if (s) return s;
   }
-  // S4: projection B^T = A^T Q;  S5: B^T = P R (P written row-major to the caller)
-  s = stream_pass(c, true, c.mode_proj, A, c.Qm, c.ldm, c.m, true, c.Zn, c.ldn, nullptr, st);
+  // S4: projection M^T Q (+ ||A||_F^2 when this pass is A X);  S5: = P R
+  // (P written row-major to the caller)
+  s = stream_pass(c, tMt, c.mode_proj, A, c.Qm, ldmM, mM, true, c.Zn, ldnM, tMt ? nullptr : c.normA, st);
   if (s) return s;
-  s = orth(c, c.f64, c.Zn, c.ldn, c.n, 2, c.Pn, c.W1n, c.Rfin, c.ldS, P, ldp, info, st);
+  s = orth(c, c.f64, c.Zn, ldnM, nM, 2, c.Pn, c.W1n, c.Rfin, c.ldS, P, ldp, info, st);
   if (s) return s;
+  if (c.r_out) PBQ_CHECK(launch_copy_mat(c.Rfin, c.ldS, c.l, c.l, c.r_out, c.ldr_out, 1, st));
   // S6: R^T = Qt L^T
   s = small_qr(c, c.Rfin, c.ldS, info, st);
   if (s) return s;
-  PBQ_CHECK(launch_write_lower_t(c.U, c.lp, c.l, L, ldl, c.rowsq, st));
+  {
+    TraceScope ts("write_l", 2.0 * c.l * c.l * 8, 0.0, st);
+    PBQ_CHECK(launch_write_lower_t(c.U, c.lp, c.l, L, ldl, c.rowsq, st));
+  }
   // S7: Q Qt, written row-major to the caller; Qt (column-major FP64) is first
   // transposed to row-major in the data type (M1 is free once small_qr is done)
   void* Mr = c.f64 ? (void*)c.M1 : c.Qt32;
-  PBQ_CHECK(launch_transpose_cast(c.f64, c.Qt64, c.ldS, c.lp, c.lp, Mr, c.ldS, st));
-  PBQ_CHECK(launch_right_mul(c.f64, c.Qm, c.ldm, c.m, c.lp, c.l, Mr, c.ldS, nullptr, 0, Q, ldq, st));
-  // S8: result record
-  PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1_splits, c.rowsq, c.l, st));
+  {
+    TraceScope ts("transpose", (double)c.lp * c.lp * (8.0 + c.el), 0.0, st);
+    PBQ_CHECK(launch_transpose_cast(c.f64, c.Qt64, c.ldS, c.lp, c.lp, Mr, c.ldS, st));
+  }
+  {
+    TraceScope ts("right_mul", 2.0 * mM * c.l * c.el, 2.0 * mM * c.l * c.l, st);
+    PBQ_CHECK(launch_right_mul(c.f64, c.Qm, ldmM, mM, c.lp, c.l, Mr, c.ldS, nullptr, 0, Q, ldq, st));
+  }
+  // S8: result record; numerical rank from the L-values
+  {
+    TraceScope ts("info", 0.0, 0.0, st);
+    PBQ_CHECK(launch_info_finalize(info, c.normA, c.k1_blocks * c.k1_splits, c.rowsq, c.l, st));
+  }
+  if (c.rank_out) PBQ_CHECK(launch_rank_estimate(L, ldl, c.l, c.rank_tol, c.rank_out, st));
   return PBPQLP_OK;
 }
 
@@ -544,14 +594,19 @@ void pbpqlp_default_opts(pbpqlp_opts* o) {
 pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_dtype dt,
                                     const pbpqlp_opts* opts, size_t* bytes) {
   if (!bytes) return PBPQLP_EINVAL;
-  Ctx c;
-  // sized for q >= 1: the power passes may split differently from the others
-  pbpqlp_status s = setup(c, m, n, n, dt, k, p, 1, opts);
-  if (s) return s;
-  Bump b;
-  c.carve(b, needs16(c));
-  b.take(sizeof(pbpqlp_info));
-  *bytes = b.off + 256;
+  // sized for q >= 1 (the power passes may split differently from the
+  // others) and for both orientations
+  size_t most = 0;
+  for (int tv = 0; tv < 2; ++tv) {
+    Ctx c;
+    pbpqlp_status s = setup(c, m, n, n, dt, k, p, 1, opts, false, tv != 0);
+    if (s) return s;
+    Bump b;
+    c.carve(b, needs16(c));
+    b.take(sizeof(pbpqlp_info));
+    if (b.off + 256 > most) most = b.off + 256;
+  }
+  *bytes = most;
   return PBPQLP_OK;
 }
 
@@ -559,14 +614,36 @@ pbpqlp_status pbpqlp_workspace_size(int64_t m, int64_t n, int k, int p, pbpqlp_d
 
 namespace {
 
+// Optional parts of a factorization call: orientation, R, numerical rank.
+struct Extras {
+  bool tv = false;            // run on A^T (the paper's orientation)
+  double* R = nullptr;
+  int64_t ldr = 0;
+  double rank_tol = 0.0;
+  int* rank = nullptr;
+};
+
 pbpqlp_status factor_impl(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
                           const void* Omega, int64_t ldo, int k, int p, int q, uint64_t seed,
                           void* Q, int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
-                          const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream) {
+                          const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream,
+                          const Extras& ex = Extras()) {
   if (!A || !Q || !L || !P) return PBPQLP_EINVAL;
   Ctx c;
-  pbpqlp_status s = setup(c, m, n, lda, dt, k, p, q, opts);
+  pbpqlp_status s = setup(c, m, n, lda, dt, k, p, q, opts, false, ex.tv);
   if (s) return s;
+  if (ex.R) {
+    if (ex.ldr < c.l || !aligned(ex.R, 8) || (const void*)ex.R == A || (void*)ex.R == Q ||
+        (void*)ex.R == P || ex.R == L)
+      return PBPQLP_EINVAL;
+    c.r_out = ex.R;
+    c.ldr_out = ex.ldr;
+  }
+  if (ex.rank) {
+    if (!(ex.rank_tol >= 0.0) || !aligned(ex.rank, 4)) return PBPQLP_EINVAL;
+    c.rank_tol = ex.rank_tol;
+    c.rank_out = ex.rank;
+  }
   if (ldq < c.l || ldl < c.l || ldp < c.l) return PBPQLP_EINVAL;
   if (Q == A || P == A || (const void*)L == A || Q == P) return PBPQLP_EINVAL;
   if (!aligned(A, c.el) || !aligned(Q, c.el) || !aligned(P, c.el) || !aligned(L, 8))
@@ -603,6 +680,9 @@ pbpqlp_status factor_impl(const void* A, int64_t m, int64_t n, int64_t lda, pbpq
   pbpqlp_info* own = (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
   if ((size_t)(b.base + b.off - base) > avail) return PBPQLP_ENOMEM;
   pbpqlp_info* info = d_info ? d_info : own;
+  // on M = A^T the method's Q (n x l) is the caller's P and its P (m x l) the
+  // caller's Q: A = M^T ~= P_M L Q_M^T
+  if (c.tv) return run_factor(c, A, P, ldp, L, ldl, Q, ldq, info, st);
   return run_factor(c, A, Q, ldq, L, ldl, P, ldp, info, st);
 }
 
@@ -682,6 +762,28 @@ pbpqlp_status pbpqlp_factor_noalloc(const void* A, int64_t m, int64_t n, int64_t
                      stream);
 }
 
+pbpqlp_status pbpqlp_factor_rr(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
+                               int k, int p, int q, uint64_t seed, void* Q, int64_t ldq, double* L,
+                               int64_t ldl, void* P, int64_t ldp, const pbpqlp_opts* opts,
+                               pbpqlp_rr* rr, pbpqlp_info* d_info, void* stream) {
+  if (!rr) return PBPQLP_EINVAL;
+  Extras ex;
+  switch (rr->orientation) {
+    case PBPQLP_ORIENT_AT: ex.tv = false; break;
+    case PBPQLP_ORIENT_A: ex.tv = true; break;
+    case PBPQLP_ORIENT_AUTO: ex.tv = m >= n; break;
+    default: return PBPQLP_EINVAL;
+  }
+  ex.R = rr->R;
+  ex.ldr = rr->ldr;
+  ex.rank = rr->d_rank;
+  ex.rank_tol = rr->rank_tol;
+  const pbpqlp_status s = factor_impl(A, m, n, lda, dt, nullptr, 0, k, p, q, seed, Q, ldq, L, ldl, P,
+                                      ldp, opts, d_info, stream, ex);
+  if (s == PBPQLP_OK) rr->orientation_used = ex.tv ? PBPQLP_ORIENT_A : PBPQLP_ORIENT_AT;
+  return s;
+}
+
 pbpqlp_status pbpqlp_factor_sketch(const void* A, int64_t m, int64_t n, int64_t lda,
                                    pbpqlp_dtype dt, const void* Omega, int64_t ldo, int k, int p,
                                    int q, void* Q, int64_t ldq, double* L, int64_t ldl, void* P,
@@ -738,7 +840,7 @@ pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int6
   if (!ok) return c.f64 ? PBPQLP_EUNSUPPORTED : PBPQLP_EINVAL;
   c.mode_sketch = c.mode_power = c.mode_proj = mode;
   c.fp16_scale = (float)(fp16_scale_a > 0 ? fp16_scale_a : 1.0);
-  c.plan_buffers(!trans, false, false, trans != 0);
+  c.plan_buffers(!trans, false, trans != 0);
   hipStream_t st = (hipStream_t)stream;
   const int64_t xlen = trans ? m : n, ylen = trans ? n : m;
   const int64_t ldxi = trans ? c.ldm : c.ldn, ldyo = trans ? c.ldn : c.ldm;

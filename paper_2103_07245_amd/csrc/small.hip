@@ -943,6 +943,46 @@ hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts
   return launch_k(info_finalize_kernel<false>, info_finalize_kernel<true>, dim3(1), dim3(256), s, p);
 }
 
+// ---------------------------------------------------------------------------
+// Numerical rank from the L-values (Section III-A: the leading k x k block of
+// L reveals the numerical rank): the number of leading diagonal entries with
+// L_ii > tol * L_11 before the first one that is not (NaN counts as not).
+// One wave scans the diagonal 64 entries at a time.
+// ---------------------------------------------------------------------------
+struct RankP {
+  const double* L;
+  int64_t ldl;
+  int l;
+  double tol;
+  int* out;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void rank_estimate_kernel(const RankP* pb, RankP ps) {
+  bool past;
+  const RankP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  const int lane = threadIdx.x;
+  const double thr = p.tol * p.L[0];
+  int rank = p.l;
+  for (int i0 = 0; i0 < p.l; i0 += 64) {
+    const int i = i0 + lane;
+    const bool fail = i < p.l && !(p.L[(int64_t)i * p.ldl + i] > thr);
+    const uint64_t m = __builtin_amdgcn_ballot_w64(fail);
+    if (m) {
+      rank = i0 + (int)__builtin_ctzll(m);
+      break;
+    }
+  }
+  if (lane == 0) *p.out = rank;
+}
+
+hipError_t launch_rank_estimate(const double* L, int64_t ldl, int l, double tol, int* out, hipStream_t s) {
+  RankP p{L, ldl, l, tol, out};
+  return launch_k(rank_estimate_kernel<false>, rank_estimate_kernel<true>, dim3(1), dim3(64), s, p);
+}
+
 struct FillP {
   uint32_t* p;
   size_t nwords;

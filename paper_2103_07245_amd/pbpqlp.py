@@ -67,6 +67,14 @@ class ProblemStruct(ctypes.Structure):
                 ("P", ctypes.c_void_p), ("ldp", ctypes.c_int64), ("info", ctypes.c_void_p)]
 
 
+class RRStruct(ctypes.Structure):
+    _fields_ = [("orientation", ctypes.c_int), ("orientation_used", ctypes.c_int), ("R", ctypes.c_void_p),
+                ("ldr", ctypes.c_int64), ("rank_tol", ctypes.c_double), ("d_rank", ctypes.c_void_p)]
+
+
+ORIENT = {"AT": 0, "A": 1, "auto": 2}
+
+
 class AutoResult(ctypes.Structure):
     _fields_ = [("q_pred", ctypes.c_int), ("k_pred", ctypes.c_int), ("q_used", ctypes.c_int),
                 ("k_used", ctypes.c_int), ("fell_back", ctypes.c_int), ("passes", ctypes.c_int),
@@ -104,6 +112,9 @@ def _lib():
         lib.pbpqlp_factor.restype = i32
         lib.pbpqlp_factor.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, u64, vp, i64, dp, i64,
                                       vp, i64, ctypes.POINTER(Opts), vp, vp]
+        lib.pbpqlp_factor_rr.restype = i32
+        lib.pbpqlp_factor_rr.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, u64, vp, i64, dp, i64,
+                                         vp, i64, ctypes.POINTER(Opts), ctypes.POINTER(RRStruct), vp, vp]
         lib.pbpqlp_factor_noalloc.restype = i32
         lib.pbpqlp_factor_noalloc.argtypes = lib.pbpqlp_factor.argtypes
         lib.pbpqlp_omega.restype = i32
@@ -310,6 +321,44 @@ def factor(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", sp
                    gram_wg)
     Q, L, P = f(A, seed)
     return Q, L, P, f.info()
+
+
+def factor_rr(A: torch.Tensor, k: int, p: int, q: int, seed: int, orientation: str = "A", plan="native",
+              rank_tol: float = None, want_r: bool = True, split_k: int = 0):
+    """pbpqlp_factor_rr.  orientation "A": A ~= Q @ L @ P.T (Algorithm 1 as the
+    paper states it); "AT": A ~= Q @ L.T @ P.T (pbpqlp_factor); "auto": "A"
+    when m >= n.  Returns (Q, L, P, R or None, rank or None, orientation used,
+    info); R is the upper-triangular factor of the last QR (R-values on its
+    diagonal), rank the number of leading L_ii > rank_tol * L_11."""
+    A = _rowmajor(A, "A")
+    m, n = A.shape
+    l = k + p
+    dev = A.device
+    Q = torch.empty((m, l), dtype=A.dtype, device=dev)
+    P = torch.empty((n, l), dtype=A.dtype, device=dev)
+    L = torch.empty((l, l), dtype=torch.float64, device=dev)
+    R = torch.empty((l, l), dtype=torch.float64, device=dev) if want_r else None
+    rank = torch.full((1,), -1, dtype=torch.int32, device=dev) if rank_tol is not None else None
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    rr = RRStruct()
+    rr.orientation = ORIENT[orientation]
+    rr.R = R.data_ptr() if R is not None else None
+    rr.ldr = l
+    rr.rank_tol = float(rank_tol) if rank_tol is not None else 0.0
+    rr.d_rank = rank.data_ptr() if rank is not None else None
+    o = make_opts(plan, split_k)
+    _check(_lib().pbpqlp_factor_rr(ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0), _dt(A), k, p, q,
+                                   ctypes.c_uint64(seed), ctypes.c_void_p(Q.data_ptr()), l,
+                                   ctypes.c_void_p(L.data_ptr()), l, ctypes.c_void_p(P.data_ptr()), l,
+                                   ctypes.byref(o), ctypes.byref(rr), ctypes.c_void_p(info.data_ptr()),
+                                   _stream(dev)), "pbpqlp_factor_rr")
+    used = "A" if rr.orientation_used == 1 else "AT"
+    return Q, L, P, R, (int(rank.item()) if rank is not None else None), used, Info.from_device(info)
+
+
+def truncate(Q: torch.Tensor, L: torch.Tensor, P: torch.Tensor, k: int):
+    """The rank-k pieces Q[:, :k], L[:k, :k], P[:, :k] as views (no copy)."""
+    return Q[:, :k], L[:k, :k], P[:, :k]
 
 
 def factor_noalloc(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", split_k: int = 0,

@@ -211,3 +211,28 @@ def test_noalloc_rejects_oversized_problem_before_the_device():
                                    ctypes.c_void_p(0x2000), 8, ctypes.c_void_p(0x3000), 8,
                                    ctypes.c_void_p(0x4000), 8, None, None, None)
     assert st == B.EINVAL
+
+
+def test_factor_rr_argument_errors():
+    """pbpqlp_factor_rr rejects a missing options record, an unknown
+    orientation, a short or aliased R and a negative or NaN rank threshold
+    before touching the device; the orientation constants match the header."""
+    text = open(HEADER).read()
+    consts = dict((k, int(v)) for k, v in re.findall(r"#define PBPQLP_ORIENT_([A-Z]+) (\d+)", text))
+    assert consts == {"AT": B.ORIENT["AT"], "A": B.ORIENT["A"], "AUTO": B.ORIENT["auto"]}
+    assert ctypes.sizeof(B.RRStruct) == 40
+    lib = B.library()
+
+    def call(rr):
+        return lib.pbpqlp_factor_rr(FAKE, 100, 80, 80, B.F32, 5, 3, 1, ctypes.c_uint64(1), ctypes.c_void_p(0x2000),
+                                    8, ctypes.c_void_p(0x3000), 8, ctypes.c_void_p(0x4000), 8, None,
+                                    rr, None, None)
+
+    assert call(None) == B.EINVAL
+    for kw in (dict(orientation=3), dict(orientation=-1), dict(R=0x5000, ldr=7), dict(R=0x3000, ldr=8),
+               dict(R=0x5004, ldr=8), dict(d_rank=0x6000, rank_tol=-1.0),
+               dict(d_rank=0x6000, rank_tol=float("nan"))):
+        rr = B.RRStruct()
+        for f, v in kw.items():
+            setattr(rr, f, v)
+        assert call(ctypes.byref(rr)) == B.EINVAL, kw
