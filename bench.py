@@ -9,9 +9,22 @@ whole factorization (sketch, 2q power passes with re-orthonormalization,
 projection, QR of B^T, QR of R^T, Q Qt) on the resident matrix.
 
     python bench.py [--steps K] [--warmup W] [--cpu-baseline full|none]
-    python bench.py --workload c4 [--steps K] [--warmup W]
+    python bench.py --workload c3|c4|c5 [--steps K] [--warmup W]
 
 Prints one JSON line on stdout; progress goes to stderr.
+
+Timing: `value` is the wall-clock time of K factorizations with tracing off,
+between device synchronizations.  The same K factorizations are then run again
+with a HIP event pair around every kernel the library launches (on the
+library's stream); these give the per-kernel table, the kernel with the most
+time per factorization and its roofline (algorithmic bytes or flops per launch
+over its mean event-timed duration).  A plain 1 GiB device copy is timed
+beside it as a measured HBM peak.
+
+--workload c3 is the tall low-rank-plus-noise matrix: 200000 x 4096 FP32,
+X Y^T with X, Y entries N(0, 1/64) (rank 64) plus 1e-3 N(0,1), k = 64, p = 16,
+q = 1; the FP16 plan (every pass on FP16 matrix cores, FP32 accumulation)
+against the FP32 plan on the same matrix, each against the FP64 oracle.
 
 --workload c4 measures the batched form instead: 1024 FP32 matrices,
 m ~ U[256, 4096], n ~ U[256, 2048], rank r ~ U[8, 64] with sigma_i = exp(-i/r)
@@ -33,7 +46,6 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2.json")
 STREAM_SRC = os.path.join(ROOT, "paper_2103_07245_amd", "csrc", "stream_gemm.hip")
 
@@ -47,24 +59,56 @@ def _sha(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def time_plan(B, torch, A_dev, w, plan, steps, warmup):
+# MI355X published peaks: HBM3E bandwidth and dense matrix-core rates
+PEAK = {"hbm": 8000.0, "mfma_bf16": 2500.0, "mfma_fp16": 2500.0, "mfma_fp32": 157.3, "mfma_fp64": 78.6}
+
+
+def run_plan(B, torch, A_dev, w, plan, steps, warmup):
+    """Time one precision plan on the resident matrix.
+
+    Region 1 (the `value`): `steps` factorizations with tracing off, bracketed
+    by device synchronizations.  Region 2: the same `steps` factorizations with
+    a HIP event pair around every kernel the library launches (on its stream),
+    which gives the per-kernel durations and the dominant kernel."""
     f = B.Factorizer(w.A.shape[0], w.A.shape[1], w.k, w.p, w.q, torch.float32, plan, A_dev.device)
     for _ in range(warmup):
         f(A_dev, w.seed)
     torch.cuda.synchronize()
-    B.trace_reset()
-    B.trace_enable(1)
     t0 = time.perf_counter()
     for _ in range(steps):
         f(A_dev, w.seed)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    B.trace_reset()
+    B.trace_enable(2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        f(A_dev, w.seed)
+    torch.cuda.synchronize()
+    ms_traced = (time.perf_counter() - t0) * 1e3 / steps
     B.trace_enable(0)
     recs = B.trace_records()
     B.trace_reset()
-    ms = (t1 - t0) * 1e3 / steps
     Q, L, P = (x.cpu().numpy() for x in (f.Q, f.L, f.P))
-    return ms, recs, Q, L, P, f.info()
+    return dict(ms=ms, ms_traced=ms_traced, kernels=kernel_table(recs, steps), Q=Q, L=L, P=P,
+                info=f.info())
+
+
+def kernel_bound(name):
+    """Resource that bounds a kernel of the library: the streaming products
+    in 16-bit modes (and split-BF16x3) stream A from HBM; in FP32/FP64 they are
+    matrix-core bound; the Gram is an FP64 matrix-core product; the Cholesky
+    is the latency of its pivot chain (reported against FP64 rate)."""
+    if name.startswith(("k1_", "k2_")):
+        mode = name[3:]
+        if mode == "f32":
+            return "mfma", "mfma_fp32"
+        if mode == "f64":
+            return "mfma", "mfma_fp64"
+        return "hbm", "hbm"
+    if name.startswith(("gram", "chol", "r2r1")):
+        return "mfma", "mfma_fp64"
+    return "hbm", "hbm"
 
 
 def kernel_table(recs, steps):
@@ -73,10 +117,56 @@ def kernel_table(recs, steps):
         t = tab.setdefault(name, {"launches": 0, "ms": 0.0, "bytes": by, "flops": fl})
         t["launches"] += 1
         t["ms"] += ms
-    for t in tab.values():
+    for name, t in tab.items():
         t["ms_per_step"] = t["ms"] / steps
         t["avg_ms"] = t["ms"] / t["launches"]
+        t["gbs"] = t["bytes"] / (t["avg_ms"] * 1e-3) / 1e9
+        t["tflops"] = t["flops"] / (t["avg_ms"] * 1e-3) / 1e12
+        bound, peak = kernel_bound(name)
+        t["bound"], t["peak_key"] = bound, peak
+        t["frac"] = (t["gbs"] if bound == "hbm" else t["tflops"]) / PEAK[peak]
     return tab
+
+
+def copy_peak(torch, dev, reps=10):
+    """Measured HBM peak of a plain device copy (1 GiB read + 1 GiB written),
+    HIP events around each copy, best of `reps`."""
+    src = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = min(best, a.elapsed_time(b))
+    del src, dst
+    return 2 * 2 ** 30 / (best * 1e-3) / 1e9
+
+
+def roofline_of(tab, steps, traffic_file=TRAFFIC_FILE):
+    """Roofline object for the kernel with the most time per step."""
+    dom_name, dom = max(tab.items(), key=lambda kv: kv[1]["ms_per_step"])
+    bound, peak_key = dom["bound"], dom["peak_key"]
+    hbm = bound == "hbm"
+    achieved = dom["gbs"] if hbm else dom["tflops"]
+    traffic = None
+    if os.path.exists(traffic_file):
+        try:
+            tr = json.load(open(traffic_file))
+            if tr.get("stream_gemm_sha") == _sha(STREAM_SRC) and dom_name in tr.get("kernels", {}):
+                traffic = tr["kernels"][dom_name]["hbm_bytes_per_launch"]
+        except Exception:
+            traffic = None
+    return {"bound": bound, "kernel": dom_name, "achieved": round(achieved, 1 if hbm else 2),
+            "peak": PEAK[peak_key], "unit": "GB/s" if hbm else "TFLOP/s",
+            "frac": round(achieved / PEAK[peak_key], 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": dom["bytes"], "algorithmic_flops_per_launch": dom["flops"],
+            "avg_launch_ms": round(dom["avg_ms"], 5), "launches_per_step": dom["launches"] / steps,
+            "ms_per_step": round(dom["ms_per_step"], 4)}
 
 
 def main():
@@ -86,7 +176,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-baseline", choices=["full", "none"], default="full",
                     help="time the FP64 oracle on one factorization of the same matrix")
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
     ap.add_argument("--model", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                     "paper_2103_07245_amd", "weights", "qk_mlp.bin"),
                     help="c5: trained q/k network")
@@ -120,8 +210,25 @@ def main():
     if args.workload == "c5":
         return bench_c5(args, torch, np, synth, B, dev)
 
+    return bench_single(args, torch, np, synth, B, dev)
+
+
+# single-matrix workloads: (generator, flagship plan, baseline plan, description)
+SINGLE = {
+    "c2": ("config2", "mixed", "native",
+           "16384x16384 fp32, sigma_i=1/i (i<=512) + 1e-6 N(0,1), k=200 p=20 q=2",
+           "sketch bf16, power bf16, projection split-bf16x3; FP64 Grams and l x l factors", "bf16"),
+    "c3": ("config3", "fp16", "native",
+           "200000x4096 fp32, X Y^T (rank 64, N(0,1/64) entries) + 1e-3 N(0,1), k=64 p=16 q=1",
+           "sketch, power and projection fp16 MFMA with FP32 accumulation; FP64 Grams and l x l factors",
+           "fp16"),
+}
+
+
+def bench_single(args, torch, np, synth, B, dev):
+    gen, flag_plan, base_plan, desc, plan_desc, flag_dtype = SINGLE[args.workload]
     t = time.time()
-    w = synth.config2()
+    w = getattr(synth, gen)()
     m, n, l, q = w.A.shape[0], w.A.shape[1], w.l, w.q
     log(f"generated {m}x{n} FP32 workload in {time.time() - t:.1f}s")
     A_dev = torch.from_numpy(w.A).to(dev)
@@ -134,12 +241,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("ran 1 GiB calibration copy")
+    copy_gbs = copy_peak(torch, dev)
+    log(f"plain 1 GiB device copy: {copy_gbs:.1f} GB/s (read + write)")
 
     results = {}
-    for plan in ("native", "mixed"):
-        ms, recs, Q, L, P, info = time_plan(B, torch, A_dev, w, plan, args.steps, args.warmup)
-        results[plan] = dict(ms=ms, kernels=kernel_table(recs, args.steps), Q=Q, L=L, P=P, info=info)
-        log(f"plan {plan}: {ms:.3f} ms/factorization")
+    for plan in (base_plan, flag_plan):
+        r = run_plan(B, torch, A_dev, w, plan, args.steps, args.warmup)
+        results[plan] = r
+        log(f"plan {plan}: {r['ms']:.3f} ms/factorization ({r['ms_traced']:.3f} ms with every kernel traced)")
 
     # errors against the FP64 oracle on the same stored matrix (host, FP64)
     from oracle import rel_residual
@@ -165,36 +274,32 @@ def main():
         r_oracle = rel_residual(w.A, ref.Q, ref.L, ref.P)
         log(f"oracle: {t_or:.1f}s, residual {r_oracle:.6e}")
         cpu = {"value": t_or * 1e3, "unit": "ms/factorization", "cores": int(threads), "kind": "oracle",
-               "sample": "one whole factorization of the same 16384x16384 matrix (k=200, p=20, q=2) "
+               "sample": f"one whole factorization of the same {m}x{n} matrix (k={w.k}, p={w.p}, q={q}) "
                          "by the FP64 oracle: numpy/OpenBLAS products with A, Householder QR"}
 
-    flag = results["mixed"]
-    base = results["native"]
-    # dominant kernel of the flagship plan, from live events over the timed region
-    dom_name, dom = max(flag["kernels"].items(), key=lambda kv: kv[1]["ms"])
-    achieved = dom["bytes"] / (dom["avg_ms"] * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("stream_gemm_sha") == _sha(STREAM_SRC) and dom_name in tr.get("kernels", {}):
-                traffic = tr["kernels"][dom_name]["hbm_bytes_per_launch"]
-        except Exception:
-            traffic = None
-    roofline = {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": dom["bytes"],
-                "avg_launch_ms": round(dom["avg_ms"], 5), "launches_per_step": dom["launches"] / args.steps}
+    flag = results[flag_plan]
+    base = results[base_plan]
+    roofline = roofline_of(flag["kernels"], args.steps)
+    roofline["copy_kernel_gbs"] = round(copy_gbs, 1)
+    if roofline["unit"] == "GB/s":
+        roofline["frac_of_copy"] = round(roofline["achieved"] / copy_gbs, 4)
 
     passes = 2 * q + 2
     flops = passes * 2.0 * m * n * l
+    a_bytes = passes * m * n * 4
 
     def summary(r):
-        d = {"ms": round(r["ms"], 4), "tflops": round(flops / (r["ms"] * 1e-3) / 1e12, 2),
+        ks = r["kernels"]
+        stream_ms = sum(v["ms_per_step"] for k, v in ks.items() if k.startswith(("k1_", "k2_")))
+        d = {"ms": round(r["ms"], 4), "ms_traced": round(r["ms_traced"], 4),
+             "tflops": round(flops / (r["ms"] * 1e-3) / 1e12, 2),
+             "hbm_frac_whole_step": round(a_bytes / (r["ms"] * 1e-3) / (PEAK["hbm"] * 1e9), 4),
+             "streaming_share": round(stream_ms / r["ms_traced"], 4),
              "resid": r["resid"], "orth_err_q": r["orth_q"], "orth_err_p": r["orth_p"],
              "kernels": {k: {"ms_per_step": round(v["ms_per_step"], 4), "launches": v["launches"] // args.steps,
-                             "gbs": round(v["bytes"] / (v["avg_ms"] * 1e-3) / 1e9, 1)}
-                         for k, v in r["kernels"].items()}}
+                             "avg_us": round(v["avg_ms"] * 1e3, 1), "gbs": round(v["gbs"], 1),
+                             "tflops": round(v["tflops"], 2), "bound": v["bound"], "frac": round(v["frac"], 4)}
+                         for k, v in sorted(ks.items(), key=lambda kv: -kv[1]["ms_per_step"])}}
         if r_oracle is not None:
             d["err_vs_fp64_oracle"] = abs(r["resid"] - r_oracle)
         return d
@@ -210,18 +315,17 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": flag_dtype,
         "data": "synthetic",
-        "config": {"workload": "16384x16384 fp32, sigma_i=1/i (i<=512) + 1e-6 N(0,1), k=200 p=20 q=2",
-                   "m": m, "n": n, "k": w.k, "p": w.p, "q": q, "plan": "mixed",
-                   "plan_passes": "sketch bf16, power bf16, projection split-bf16x3; FP64 Grams and l x l factors"},
+        "config": {"workload": desc, "m": m, "n": n, "k": w.k, "p": w.p, "q": q, "plan": flag_plan,
+                   "plan_passes": plan_desc},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_resid": r_oracle,
-        "mixed": summary(flag),
+        flag_plan: summary(flag),
         "fp32": summary(base),
-        "speedup_mixed_vs_fp32": round(base["ms"] / flag["ms"], 3),
-        "hbm_floor_ms": round(passes * m * n * 4 / (HBM_PEAK_GBS * 1e9) * 1e3, 4),
+        f"speedup_{flag_plan}_vs_fp32": round(base["ms"] / flag["ms"], 3),
+        "hbm_floor_ms": round(a_bytes / (PEAK["hbm"] * 1e9) * 1e3, 4),
         "algorithmic_tflop_per_factorization": flops / 1e12,
     }
     print(json.dumps(line), flush=True)

@@ -1,6 +1,7 @@
 """Build libpbpqlp.so for gfx950 in-tree with hipcc.
 
     python -m paper_2103_07245_amd.build        # or __graft_entry__.build()
+    python -m paper_2103_07245_amd.build --incremental   # only sources newer than their objects
 
 Every HIP source under csrc/ is compiled to an object in _build/ (in
 parallel) and linked into paper_2103_07245_amd/libpbpqlp.so.
@@ -44,13 +45,25 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def _stale(src: str) -> bool:
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    headers = [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    headers.append(os.path.join(ROOT, "include", "pbpqlp.h"))
+    return any(os.path.getmtime(f) > t for f in [os.path.join(CSRC, src), *headers])
+
+
+def build(verbose: bool = True, incremental: bool = False) -> str:
     if shutil.which(HIPCC) is None and not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
-    jobs = min(len(SOURCES), max(1, int(os.environ.get("MAX_JOBS", "8"))))
+    todo = [s for s in SOURCES if not incremental or _stale(s)]
+    jobs = min(max(1, len(todo)), max(1, int(os.environ.get("MAX_JOBS", "8"))))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        list(ex.map(_compile, todo))
+    objs = [os.path.join(BUILD, os.path.splitext(s)[0] + ".o") for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,5 +76,5 @@ def build(verbose: bool = True) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv[1:])
     sys.exit(0)

@@ -369,7 +369,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
 // accumulated triangular factor when non-null.
 pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes,
                    void* out, void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm,
-                   void* info, hipStream_t st) {
+                   void* info, hipStream_t st, bool small = false) {
   const double eps = dep_eps(f64, c.l, len);
   void* Ra = f64 ? c.Ra64 : c.Ra;
   void* Dv = f64 ? c.Dinv64 : c.Dinv;
@@ -381,15 +381,15 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     const uint64_t cseed = c.seed ^ (0x9E3779B97F4A7C15ull * (++c.ncall));
     const double el = f64 ? 8.0 : (double)c.el;
     {
-      TraceScope ts("gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
+      TraceScope ts(small ? "gram_ll" : "gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
       PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, c.gram_target, st));
     }
     {
-      TraceScope ts("chol", (double)c.l * c.l * 8 * 2, (double)c.l * c.l * c.l / 3.0, st);
+      TraceScope ts(small ? "chol_ll" : "chol", (double)c.l * c.l * 8 * 2, (double)c.l * c.l * c.l / 3.0, st);
       PBQ_CHECK(launch_chol(f64, c.G, c.lp, c.l, c.lp, eps, Rt, c.lp, Ra, Dv, c.dep, info, st));
     }
     {
-      TraceScope ts("apply", 2.0 * len * c.l * el, (double)len * c.l * c.l, st);
+      TraceScope ts(small ? "apply_ll" : "apply", 2.0 * len * c.l * el, (double)len * c.l * c.l, st);
       PBQ_CHECK(launch_apply(f64, src, ld, len, c.lp, c.l, Ra, Dv, c.dep, cseed, dst, ld,
                              last ? rm : nullptr, ldrm, st));
     }
@@ -408,7 +408,7 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
 // The l x l stage: R^T = Qt U (U = L^T) by two FP64 CholeskyQR sweeps of the
 // l x l matrix R^T, whose column-major storage is R itself (row-major).
 pbpqlp_status small_qr(Ctx& c, const double* Rrow, int64_t ldr, void* info, hipStream_t st) {
-  return orth(c, true, Rrow, ldr, c.l, 2, c.Qt64, c.M1, c.U, c.lp, nullptr, 0, info, st);
+  return orth(c, true, Rrow, ldr, c.l, 2, c.Qt64, c.M1, c.U, c.lp, nullptr, 0, info, st, true);
 }
 
 // The whole method on M (M = A, or M = A^T for the paper's orientation).
