@@ -184,6 +184,8 @@ def main():
     ap.add_argument("--count", type=int, default=1024, help="c4 batch size")
     ap.add_argument("--skip-per-matrix", action="store_true", help="c4: skip the per-matrix timing")
     ap.add_argument("--no-tune", action="store_true", help="c4: use the built-in batch plan, not the autotuner's")
+    ap.add_argument("--host-resident", action="store_true",
+                    help="c2/c3: also time the factorization with A in pinned host memory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
     args = ap.parse_args()
@@ -277,6 +279,27 @@ def bench_single(args, torch, np, synth, B, dev):
                "sample": f"one whole factorization of the same {m}x{n} matrix (k={w.k}, p={w.p}, q={q}) "
                          "by the FP64 oracle: numpy/OpenBLAS products with A, Householder QR"}
 
+    host = None
+    if args.host_resident:
+        # the same factorization with A left in pinned host memory: every pass
+        # streams A over PCIe in row panels (not the timed `value`)
+        Ah = torch.from_numpy(w.A).pin_memory()
+        for _ in range(1):
+            B.factor_host(Ah, w.k, w.p, w.q, w.seed, plan=flag_plan)
+        torch.cuda.synchronize()
+        hs = max(1, min(args.steps, 5))
+        t0 = time.perf_counter()
+        for _ in range(hs):
+            Qh, Lh, Ph, _ = B.factor_host(Ah, w.k, w.p, w.q, w.seed, plan=flag_plan)
+        torch.cuda.synchronize()
+        ms_h = (time.perf_counter() - t0) * 1e3 / hs
+        r_h = rel_residual(w.A, *(x.cpu().numpy() for x in (Qh, Lh, Ph)))
+        host = {"ms": round(ms_h, 3), "steps": hs, "plan": flag_plan,
+                "pcie_gbs": round((2 * q + 2) * m * n * 4 / (ms_h * 1e-3) / 1e9, 2), "resid": r_h,
+                "note": "A in pinned host memory, 2q+2 passes streamed in ~256 MiB row panels"}
+        log(f"host-resident A: {ms_h:.2f} ms/factorization ({host['pcie_gbs']} GB/s of A), residual {r_h:.6e}")
+        del Ah
+
     flag = results[flag_plan]
     base = results[base_plan]
     roofline = roofline_of(flag["kernels"], args.steps)
@@ -322,6 +345,7 @@ def bench_single(args, torch, np, synth, B, dev):
         "roofline": roofline,
         "cpu_baseline": cpu,
         "oracle_resid": r_oracle,
+        "host_resident": host,
         flag_plan: summary(flag),
         "fp32": summary(base),
         f"speedup_{flag_plan}_vs_fp32": round(base["ms"] / flag["ms"], 3),

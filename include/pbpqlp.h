@@ -209,6 +209,38 @@ pbpqlp_status pbpqlp_factor_rr(const void* A, int64_t m, int64_t n, int64_t lda,
                                int64_t ldl, void* P, int64_t ldp, const pbpqlp_opts* opts,
                                pbpqlp_rr* rr, pbpqlp_info* d_info, void* stream);
 
+/* ---- A in host memory (Section IV-E: when A is stored externally the method
+ * needs 2q + 2 passes over it) ----
+ *
+ * pbpqlp_factor for an A that stays in host memory: every product with A or
+ * A^T streams A once from the host in row panels of panel_rows rows (0: about
+ * 256 MiB of rows; rounded up to a multiple of 256), copied on a copy stream
+ * of the library's own into two device staging buffers in turn, so copies
+ * overlap the kernels of the previous panel.  The same kernels as
+ * pbpqlp_factor run on each panel: A X panel by panel; A^T X as a sum over
+ * panels, every panel's partials kept and summed in a fixed order at the end
+ * (deterministic).  With one panel (panel_rows >= m) the results equal
+ * pbpqlp_factor's bit for bit for the same options; with several, the A^T X
+ * sums run in another order (FP32/FP64 rounding differences only).
+ *   A_host     : m x n row-major in host memory (lda >= n), dtype dt; memory
+ *                from hipHostMalloc lets the copies run at full PCIe rate,
+ *                pageable memory also works (the runtime stages it).  Read only.
+ *   Q, L, P    : device outputs as in pbpqlp_factor (A ~= Q L^T P^T).
+ * The call returns once the last panel has been copied (the caller may then
+ * reuse A_host); the remaining kernels complete in order on `stream`.  Not
+ * capturable in a HIP graph.  The workspace (pbpqlp_workspace_size_host)
+ * includes the two staging buffers.  Errors: as pbpqlp_factor (ldq, ldl,
+ * ldp, alignment, shapes); EINVAL for panel_rows < 0; EHIP when the copy
+ * stream or its events cannot be created. */
+pbpqlp_status pbpqlp_workspace_size_host(int64_t m, int64_t n, int64_t lda, int k, int p,
+                                         pbpqlp_dtype dt, int64_t panel_rows,
+                                         const pbpqlp_opts* opts, size_t* bytes);
+pbpqlp_status pbpqlp_factor_host(const void* A_host, int64_t m, int64_t n, int64_t lda,
+                                 pbpqlp_dtype dt, int k, int p, int q, uint64_t seed,
+                                 int64_t panel_rows, void* Q, int64_t ldq, double* L, int64_t ldl,
+                                 void* P, int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
+                                 void* stream);
+
 /* ---- allocation-free variant ----
  *
  * For callers that cannot allocate device memory: code recorded under HIP

@@ -38,8 +38,10 @@ hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, 
 hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int l, int lp32,
                           float scale, void* hi, void* lo, hipStream_t s);
 // out[c*ldo + i] = sum_s part[s*stride + c*ld + i]   (i < ldo; zero for i >= len)
+// out[c][i] = sum of the S partials for i < len, 0 for len <= i < wlen (wlen < 0: ldo)
 hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
-                                int lp, int64_t len, void* out, int64_t ldo, hipStream_t s);
+                                int lp, int64_t len, void* out, int64_t ldo, hipStream_t s,
+                                int64_t wlen = -1);
 // Gram partials and reduction: G (lp x lp, FP64, row-major, ldg) = X X^T over len
 // `target`: workgroups to aim at (contraction splits x block pairs)
 int gram_splits(int64_t len, int lp, int target);

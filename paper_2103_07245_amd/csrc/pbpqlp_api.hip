@@ -6,6 +6,7 @@
 // Algorithm 1 of the paper applied to A^T.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -186,6 +187,20 @@ struct Ctx {
   int64_t ldr_out = 0;
   double rank_tol = 0.0;
   int* rank_out = nullptr;
+  // host-resident A (Section IV-E, A stored externally): every pass streams
+  // row panels of panel_rows rows through two device staging buffers
+  const char* A_host = nullptr;
+  int64_t panel_rows = 0;
+  int npanels = 0;
+  void* stage[2] = {nullptr, nullptr};
+  hipStream_t cs = nullptr;            // copy stream
+  hipEvent_t ev_copied[2] = {nullptr, nullptr}, ev_used[2] = {nullptr, nullptr};
+  int panel_seq = 0;                   // panels streamed so far (buffer = panel_seq & 1)
+  // pageable A: rows go through two pinned bounce buffers first (a host copy,
+  // then an asynchronous copy that keeps the copy stream's order)
+  bool bounce = false;
+  void* bounce_buf[2] = {nullptr, nullptr};
+  hipEvent_t ev_bounce[2] = {nullptr, nullptr};
 
   int64_t mM() const { return tv ? n : m; }
   int64_t nM() const { return tv ? m : n; }
@@ -194,8 +209,23 @@ struct Ctx {
   // Split plan of a pass in compute mode `mode` (grid blocks depend on it).
   Split split_for(int mode, bool trans) const {
     const int64_t rb = stream_rows_per_block(mode);
-    const int64_t len = trans ? n : m, klen = trans ? m : n;
-    return plan_split((len + rb - 1) / rb, klen, forced_split);
+    const int64_t mr = panel_rows > 0 ? panel_rows : m;   // rows one launch sees
+    const int64_t len = trans ? n : mr, klen = trans ? mr : n;
+    Split sp = plan_split((len + rb - 1) / rb, klen, forced_split);
+    // the A^T X panels of a host-resident A keep every split partial until the
+    // last panel: at most 64 partials in all
+    if (panel_rows > 0 && trans && (int64_t)sp.S * npanels > 64) {
+      const int S = (int)(64 / npanels) > 0 ? (int)(64 / npanels) : 1;
+      sp = plan_split((len + rb - 1) / rb, klen, S);
+    }
+    return sp;
+  }
+  // Partials one pass keeps: split partials of one launch, or, for A^T X over
+  // host panels, those of every panel.
+  int64_t partial_slots(int mode, bool trans) const {
+    const Split sp = split_for(mode, trans);
+    if (panel_rows > 0 && trans) return (int64_t)sp.S * npanels;
+    return sp.S > 1 ? sp.S : 0;
   }
   // Sizes of the split partials and the ||A||^2 partials for the passes this
   // context will run: the sketch M X, the power passes (both directions) and
@@ -205,8 +235,7 @@ struct Ctx {
   void plan_buffers(bool sketch, bool power, bool proj) {
     part_bytes = 0;
     auto need = [&](int mode, bool trans) {
-      const Split sp = split_for(mode, trans);
-      const size_t b = sp.S > 1 ? (size_t)sp.S * lp * (trans ? ldn : ldm) * el : 0;
+      const size_t b = (size_t)partial_slots(mode, trans) * lp * (trans ? ldn : ldm) * el;
       if (b > part_bytes) part_bytes = b;
     };
     if (sketch) need(mode_sketch, tv);
@@ -217,7 +246,13 @@ struct Ctx {
     if (proj) need(mode_proj, !tv);
     const int nmode = tv ? mode_proj : mode_sketch;
     const int64_t rb = stream_rows_per_block(nmode);
-    k1_blocks = (int)((m + rb - 1) / rb);
+    if (panel_rows > 0) {
+      // every panel holds a whole number of row blocks but the last
+      k1_blocks = (int)(((panel_rows + rb - 1) / rb) * (npanels - 1) +
+                        ((m - panel_rows * (npanels - 1)) + rb - 1) / rb);
+    } else {
+      k1_blocks = (int)((m + rb - 1) / rb);
+    }
     k1_splits = split_for(nmode, false).S;
   }
 
@@ -256,6 +291,10 @@ struct Ctx {
     Dinv64 = b.take((size_t)(lp / 16) * 256 * 8);
     dep = (int*)b.take((size_t)(lp + 1) * sizeof(int));
     rowsq = (double*)b.take((size_t)lp * sizeof(double));
+    if (panel_rows > 0) {
+      stage[0] = b.take((size_t)panel_rows * lda * el);
+      stage[1] = b.take((size_t)panel_rows * lda * el);
+    }
   }
 };
 
@@ -307,6 +346,98 @@ bool needs16(const Ctx& c) {
   return c.mode_sketch >= M_BF16 || c.mode_power >= M_BF16 || c.mode_proj >= M_BF16;
 }
 
+// One pass over a host-resident A (Section IV-E: with A stored externally each
+// product with A or A^T is one more pass over it).  Row panels of panel_rows
+// rows are copied on the copy stream into two device staging buffers in turn;
+// the compute stream waits for each copy, and a copy into a buffer waits until
+// the kernel that read the buffer's previous panel is done.  A X: each panel
+// gives its rows of the result (through its own split partials when the
+// contraction is split).  A^T X: each panel's split partials stay in their
+// own slots and one reduction in a fixed order sums all of them at the end.
+pbpqlp_status host_pass(Ctx& c, bool trans, int mode, StreamArgs a, int64_t xlen, void* out,
+                        int64_t ldo, double* normA, hipStream_t st) {
+  const Split sp = c.split_for(mode, trans);
+  const int64_t rb = stream_rows_per_block(mode);
+  const int64_t olen = trans ? c.n : c.m;
+  const double xb = (mode >= M_BF16) ? 2.0 : (double)c.el;
+  int64_t slot = 0;
+  int64_t nblk = 0;   // row blocks of the panels done so far (||A||^2 partial offset)
+  for (int pi = 0; pi < c.npanels; ++pi) {
+    const int64_t r0 = (int64_t)pi * c.panel_rows;
+    const int64_t rows = std::min(c.panel_rows, c.m - r0);
+    const int b = c.panel_seq++ & 1;
+    // the copy waits for the last kernel that read this buffer
+    PBQ_CHECK(hipStreamWaitEvent(c.cs, c.ev_used[b], 0));
+    if (c.bounce) {
+      // the bounce buffer is free once its previous copy to the device is done
+      PBQ_CHECK(hipEventSynchronize(c.ev_bounce[b]));
+      const size_t rb_bytes = (size_t)c.n * c.el;
+      for (int64_t i = 0; i < rows; ++i)
+        std::memcpy((char*)c.bounce_buf[b] + (size_t)i * rb_bytes,
+                    c.A_host + (size_t)(r0 + i) * c.lda * c.el, rb_bytes);
+      PBQ_CHECK(hipMemcpy2DAsync(c.stage[b], (size_t)c.lda * c.el, c.bounce_buf[b], rb_bytes, rb_bytes,
+                                 (size_t)rows, hipMemcpyHostToDevice, c.cs));
+      PBQ_CHECK(hipEventRecord(c.ev_bounce[b], c.cs));
+    } else {
+      PBQ_CHECK(hipMemcpy2DAsync(c.stage[b], (size_t)c.lda * c.el, c.A_host + (size_t)r0 * c.lda * c.el,
+                                 (size_t)c.lda * c.el, (size_t)c.n * c.el, (size_t)rows,
+                                 hipMemcpyHostToDevice, c.cs));
+    }
+    PBQ_CHECK(hipEventRecord(c.ev_copied[b], c.cs));
+    PBQ_CHECK(hipStreamWaitEvent(st, c.ev_copied[b], 0));
+    StreamArgs pa = a;
+    pa.A = c.stage[b];
+    pa.m = rows;
+    if (trans) {
+      // A^T X contracts over the panel's rows: the matching rows of X
+      const size_t xel = mode >= M_BF16 ? 2 : c.el;
+      pa.X = (const char*)a.X + (size_t)r0 * xel;
+      if (a.Xlo) pa.Xlo = (const char*)a.Xlo + (size_t)r0 * xel;
+    }
+    // the same split count for every panel (the last may be shorter)
+    const Split ps = plan_split(trans ? (c.n + rb - 1) / rb : (rows + rb - 1) / rb, trans ? rows : c.n, sp.S);
+    pa.splits = ps.S;
+    pa.chunk = ps.chunk;
+    pa.normA = normA ? normA + nblk * ps.S : nullptr;
+    if (trans) {
+      pa.out = (char*)c.part + (size_t)slot * c.lp * ldo * c.el;
+      pa.ldo = ldo;
+      pa.split_stride = (int64_t)c.lp * ldo;
+      slot += ps.S;
+    } else if (ps.S == 1) {
+      pa.out = (char*)out + (size_t)r0 * c.el;
+      pa.ldo = ldo;
+      pa.split_stride = 0;
+    } else {
+      pa.out = c.part;
+      pa.ldo = ldo;
+      pa.split_stride = (int64_t)c.lp * ldo;
+    }
+    {
+      const double bytes = (double)rows * c.n * c.el + (double)(trans ? rows : xlen) * c.l * xb *
+                           (mode == M_BF16X3 ? 2 : 1) + (double)(trans ? c.n : rows) * c.l * c.el;
+      std::string nm = std::string(trans ? "k2_" : "k1_") + mode_name(mode) + "_panel";
+      TraceScope ts(nm.c_str(), bytes, 2.0 * rows * c.n * c.l, st, 1);
+      PBQ_CHECK(launch_stream(trans, mode, pa, st));
+    }
+    if (!trans && ps.S > 1) {
+      TraceScope ts("splitk_reduce", (double)(ps.S + 1) * rows * c.l * c.el, 0.0, st);
+      // only this panel's rows (the last panel also zeroes the padding rows)
+      const int64_t wl = pi == c.npanels - 1 ? ldo - r0 : rows;
+      PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, pa.split_stride, ps.S, ldo, c.lp, rows,
+                                     (char*)out + (size_t)r0 * c.el, ldo, st, wl));
+    }
+    PBQ_CHECK(hipEventRecord(c.ev_used[b], st));
+    nblk += (rows + rb - 1) / rb;
+  }
+  if (trans) {
+    TraceScope ts("splitk_reduce", (double)(slot + 1) * olen * c.l * c.el, 0.0, st);
+    PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, (int64_t)c.lp * ldo, (int)slot, ldo, c.lp, olen, out,
+                                   ldo, st));
+  }
+  return PBPQLP_OK;
+}
+
 // One A-streaming pass: out (column-major, ld) = A X (trans=0) or A^T X.
 pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const void* X,
                           int64_t ldx, int64_t xlen, bool unit_columns, void* out, int64_t ldo,
@@ -334,6 +465,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
     a.Xlo = nullptr;
   }
   a.ldx = ldx;
+  if (c.A_host) return host_pass(c, trans, mode, a, xlen, out, ldo, normA, st);
   const Split sp = c.split_for(mode, trans);
   a.splits = sp.S;
   a.chunk = sp.chunk;
@@ -686,9 +818,140 @@ pbpqlp_status factor_impl(const void* A, int64_t m, int64_t n, int64_t lda, pbpq
   return run_factor(c, A, Q, ldq, L, ldl, P, ldp, info, st);
 }
 
+// Rows per staged panel of a host-resident A: the caller's count rounded up to
+// a multiple of 256, or about 256 MiB of rows; never more than m rounded up.
+int64_t host_panel_rows(int64_t m, int64_t lda, size_t el, int64_t want) {
+  int64_t r = want > 0 ? want : (int64_t)((256ull << 20) / ((size_t)lda * el));
+  r = rup(r < 1 ? 1 : r, 256);
+  const int64_t mr = rup(m, 256);
+  return r < mr ? r : mr;
+}
+
+// Streams and events of one host-resident call; destroyed at the end of the
+// call, after the copy stream has finished (the compute stream's waits were
+// enqueued before).
+struct HostRes {
+  hipStream_t cs = nullptr;
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  void* bounce[2] = {nullptr, nullptr};
+  ~HostRes() {
+    if (cs) (void)hipStreamSynchronize(cs);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (void* p : bounce)
+      if (p) (void)hipHostFree(p);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+// True for host memory the runtime can copy from asynchronously (allocated
+// with hipHostMalloc or registered); pageable memory reports otherwise.  The
+// query's error on pageable memory is cleared so no later call reports it.
+bool host_pinned(const void* p) {
+  hipPointerAttribute_t at;
+  const hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeHost;
+}
+
+pbpqlp_status host_setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, int k, int p,
+                         int q, int64_t panel_rows, const pbpqlp_opts* opts) {
+  pbpqlp_status s = setup(c, m, n, lda, dt, k, p, q, opts, false, false);
+  if (s) return s;
+  if (panel_rows < 0) return PBPQLP_EINVAL;
+  c.panel_rows = host_panel_rows(m, lda, c.el, panel_rows);
+  c.npanels = (int)((m + c.panel_rows - 1) / c.panel_rows);
+  c.plan_buffers(true, q > 0, true);
+  return PBPQLP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+pbpqlp_status pbpqlp_workspace_size_host(int64_t m, int64_t n, int64_t lda, int k, int p,
+                                         pbpqlp_dtype dt, int64_t panel_rows,
+                                         const pbpqlp_opts* opts, size_t* bytes) {
+  if (!bytes) return PBPQLP_EINVAL;
+  Ctx c;
+  pbpqlp_status s = host_setup(c, m, n, lda, dt, k, p, 1, panel_rows, opts);
+  if (s) return s;
+  Bump b;
+  c.carve(b, needs16(c));
+  b.take(sizeof(pbpqlp_info));
+  *bytes = b.off + 256;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_factor_host(const void* A_host, int64_t m, int64_t n, int64_t lda,
+                                 pbpqlp_dtype dt, int k, int p, int q, uint64_t seed,
+                                 int64_t panel_rows, void* Q, int64_t ldq, double* L, int64_t ldl,
+                                 void* P, int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
+                                 void* stream) {
+  if (!A_host || !Q || !L || !P) return PBPQLP_EINVAL;
+  Ctx c;
+  pbpqlp_status s = host_setup(c, m, n, lda, dt, k, p, q, panel_rows, opts);
+  if (s) return s;
+  if (ldq < c.l || ldl < c.l || ldp < c.l || Q == P) return PBPQLP_EINVAL;
+  if (!aligned(A_host, c.el) || !aligned(Q, c.el) || !aligned(P, c.el) || !aligned(L, 8))
+    return PBPQLP_EINVAL;
+  c.seed = seed;
+  c.A_host = (const char*)A_host;
+  hipStream_t st = (hipStream_t)stream;
+  const bool n16 = needs16(c);
+  Bump sizer;
+  c.carve(sizer, n16);
+  sizer.take(sizeof(pbpqlp_info));
+  const size_t need = sizer.off + 256;
+  ScratchGuard g;
+  char* base;
+  size_t avail;
+  if (opts && opts->workspace) {
+    base = (char*)opts->workspace;
+    avail = opts->workspace_bytes;
+    if (avail < need) return PBPQLP_ENOMEM;
+  } else {
+    s = alloc_scratch(g, need, st);
+    if (s) return s;
+    base = (char*)g.p;
+    avail = need;
+  }
+  Bump b;
+  b.base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
+  c.carve(b, n16);
+  pbpqlp_info* own = (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  if ((size_t)(b.base + b.off - base) > avail) return PBPQLP_ENOMEM;
+  pbpqlp_info* info = d_info ? d_info : own;
+  HostRes hr;
+  if (hipStreamCreateWithFlags(&hr.cs, hipStreamNonBlocking) != hipSuccess) return PBPQLP_EHIP;
+  for (hipEvent_t& e : hr.ev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return PBPQLP_EHIP;
+  c.cs = hr.cs;
+  c.ev_copied[0] = hr.ev[0];
+  c.ev_copied[1] = hr.ev[1];
+  c.ev_used[0] = hr.ev[2];
+  c.ev_used[1] = hr.ev[3];
+  c.ev_bounce[0] = hr.ev[4];
+  c.ev_bounce[1] = hr.ev[5];
+  if (!host_pinned(A_host)) {
+    c.bounce = true;
+    for (int i = 0; i < 2; ++i) {
+      if (hipHostMalloc(&hr.bounce[i], (size_t)c.panel_rows * c.n * c.el, hipHostMallocDefault) != hipSuccess) {
+        hr.bounce[i] = nullptr;
+        return PBPQLP_ENOMEM;
+      }
+      c.bounce_buf[i] = hr.bounce[i];
+      if (hipEventRecord(c.ev_bounce[i], c.cs) != hipSuccess) return PBPQLP_EHIP;
+    }
+  }
+  // the staging buffers are free once the work already on the stream is done
+  if (hipEventRecord(c.ev_used[0], st) != hipSuccess || hipEventRecord(c.ev_used[1], st) != hipSuccess)
+    return PBPQLP_EHIP;
+  return run_factor(c, nullptr, Q, ldq, L, ldl, P, ldp, info, st);
+}
 
 pbpqlp_status pbpqlp_factor(const void* A, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt,
                             int k, int p, int q, uint64_t seed, void* Q, int64_t ldq, double* L,

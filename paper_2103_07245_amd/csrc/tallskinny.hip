@@ -142,9 +142,10 @@ struct ReduceP {
   const void* part;
   int64_t stride;
   int S;
-  int64_t ld, len;
+  int64_t ld, len;   // partials: leading dimension, rows summed (later rows are 0)
   void* out;
   int64_t ldo;
+  int64_t wlen;      // rows written: len rounded to the buffer's padding, or one panel's rows
   PBQ_GRID;
 };
 
@@ -157,7 +158,7 @@ __global__ void splitk_reduce_kernel(const ReduceP* pb, ReduceP ps) {
   T* out = (T*)p.out;
   const int c = blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (i0 >= p.ldo) return;
+  if (i0 >= p.wlen) return;
   T acc[4] = {0, 0, 0, 0};
   if (i0 + 3 < p.len) {
     for (int sp = 0; sp < p.S; ++sp) {
@@ -175,13 +176,15 @@ __global__ void splitk_reduce_kernel(const ReduceP* pb, ReduceP ps) {
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e)
-    if (i0 + e < p.ldo) out[(int64_t)c * p.ldo + i0 + e] = acc[e];
+    if (i0 + e < p.wlen) out[(int64_t)c * p.ldo + i0 + e] = acc[e];
 }
 
 hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
-                                int lp, int64_t len, void* out, int64_t ldo, hipStream_t s) {
-  dim3 grid((unsigned)((ldo / 4 + 255) / 256), (unsigned)lp);
-  ReduceP p{part, stride, S, ld, len, out, ldo};
+                                int lp, int64_t len, void* out, int64_t ldo, hipStream_t s,
+                                int64_t wlen) {
+  if (wlen < 0) wlen = ldo;
+  dim3 grid((unsigned)((wlen + 1023) / 1024), (unsigned)lp);
+  ReduceP p{part, stride, S, ld, len, out, ldo, wlen};
   if (f64) return launch_k(splitk_reduce_kernel<double, false>, splitk_reduce_kernel<double, true>, grid, dim3(256), s, p);
   return launch_k(splitk_reduce_kernel<float, false>, splitk_reduce_kernel<float, true>, grid, dim3(256), s, p);
 }

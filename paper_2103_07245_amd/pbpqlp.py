@@ -117,6 +117,12 @@ def _lib():
                                          vp, i64, ctypes.POINTER(Opts), ctypes.POINTER(RRStruct), vp, vp]
         lib.pbpqlp_factor_noalloc.restype = i32
         lib.pbpqlp_factor_noalloc.argtypes = lib.pbpqlp_factor.argtypes
+        lib.pbpqlp_workspace_size_host.restype = i32
+        lib.pbpqlp_workspace_size_host.argtypes = [i64, i64, i64, i32, i32, i32, i64, ctypes.POINTER(Opts),
+                                                   ctypes.POINTER(ctypes.c_size_t)]
+        lib.pbpqlp_factor_host.restype = i32
+        lib.pbpqlp_factor_host.argtypes = [vp, i64, i64, i64, i32, i32, i32, i32, u64, i64, vp, i64, dp,
+                                           i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
         lib.pbpqlp_omega.restype = i32
         lib.pbpqlp_omega.argtypes = [i64, i32, u64, i32, vp, i64, vp]
         lib.pbpqlp_matmul.restype = i32
@@ -383,6 +389,43 @@ def factor_noalloc(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="nat
                                         ctypes.c_void_p(info.data_ptr()), _stream(A.device)),
            "pbpqlp_factor_noalloc")
     return Q, L, P, info
+
+
+def factor_host(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native", panel_rows: int = 0,
+                split_k: int = 0, device="cuda"):
+    """pbpqlp_factor_host: A (m x n, float32/float64) stays in host memory
+    (a CPU tensor; pinned memory, ``A.pin_memory()``, lets the copies overlap
+    the kernels) and is streamed to ``device`` in row panels on every pass.
+    Returns (Q, L, P, info) on the device with A ~= Q @ L.T @ P.T."""
+    if A.is_cuda:
+        raise ValueError("A must be a host (CPU) tensor")
+    if A.dim() != 2 or A.stride(1) != 1 or A.stride(0) < A.shape[1]:
+        A = A.contiguous()
+    m, n = A.shape
+    l = k + p
+    dev = torch.device(device)
+    Q = torch.empty((m, l), dtype=A.dtype, device=dev)
+    P = torch.empty((n, l), dtype=A.dtype, device=dev)
+    L = torch.empty((l, l), dtype=torch.float64, device=dev)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    o = make_opts(plan, split_k)
+    with torch.cuda.device(dev):
+        _check(_lib().pbpqlp_factor_host(ctypes.c_void_p(A.data_ptr()), m, n, A.stride(0), _dt(A), k, p, q,
+                                         ctypes.c_uint64(seed), int(panel_rows), ctypes.c_void_p(Q.data_ptr()),
+                                         l, ctypes.c_void_p(L.data_ptr()), l, ctypes.c_void_p(P.data_ptr()),
+                                         l, ctypes.byref(o), ctypes.c_void_p(info.data_ptr()), _stream(dev)),
+               "pbpqlp_factor_host")
+    return Q, L, P, Info.from_device(info)
+
+
+def workspace_size_host(m: int, n: int, k: int, p: int, dtype=torch.float32, plan="native",
+                        panel_rows: int = 0, lda: int = None) -> int:
+    sz = ctypes.c_size_t(0)
+    o = make_opts(plan)
+    _check(_lib().pbpqlp_workspace_size_host(m, n, n if lda is None else lda, k, p,
+                                             F64 if dtype == torch.float64 else F32, int(panel_rows),
+                                             ctypes.byref(o), ctypes.byref(sz)), "pbpqlp_workspace_size_host")
+    return int(sz.value)
 
 
 def factor_sketch(A: torch.Tensor, Omega: torch.Tensor, k: int, p: int, q: int, plan="native"):

@@ -236,3 +236,29 @@ def test_factor_rr_argument_errors():
         for f, v in kw.items():
             setattr(rr, f, v)
         assert call(ctypes.byref(rr)) == B.EINVAL, kw
+
+
+def test_factor_host_argument_errors():
+    """pbpqlp_factor_host rejects null pointers, a negative panel size, short
+    leading dimensions, widths beyond the library's limit and misaligned
+    outputs before it creates a stream or touches the device; its workspace
+    includes the two staging panels."""
+    lib = B.library()
+
+    def call(A=FAKE, m=100, n=80, lda=80, k=5, p=3, panel=0, ldq=8, Q=0x2000, P=0x4000):
+        return lib.pbpqlp_factor_host(A, m, n, lda, B.F32, k, p, 1, ctypes.c_uint64(1), panel,
+                                      ctypes.c_void_p(Q), ldq, ctypes.c_void_p(0x3000), 8,
+                                      ctypes.c_void_p(P), 8, None, None, None)
+
+    assert call(A=None) == B.EINVAL
+    assert call(panel=-1) == B.EINVAL
+    assert call(lda=79) == B.EINVAL
+    assert call(ldq=7) == B.EINVAL
+    assert call(Q=0x2002) == B.EINVAL
+    assert call(Q=0x2000, P=0x2000) == B.EINVAL
+    assert call(m=400, n=400, lda=400, k=250, p=10, ldq=260) == B.EUNSUPPORTED
+    one = B.workspace_size_host(4096, 1024, 40, 8, panel_rows=4096)
+    four = B.workspace_size_host(4096, 1024, 40, 8, panel_rows=1024)
+    # two staging panels of 4096 (one panel) or 1024 rows of 1024 FP32 values
+    assert one - four >= 2 * (4096 - 1024) * 1024 * 4 - (1 << 20)
+    assert B.workspace_size_host(4096, 1024, 40, 8, panel_rows=1000) == four   # rounded up to 1024
