@@ -9,7 +9,7 @@ whole factorization (sketch, 2q power passes with re-orthonormalization,
 projection, QR of B^T, QR of R^T, Q Qt) on the resident matrix.
 
     python bench.py [--steps K] [--warmup W] [--cpu-baseline full|none]
-    python bench.py --workload c3|c4|c5 [--steps K] [--warmup W]
+    python bench.py --workload c3|c4|c5|tables [--steps K] [--warmup W]
 
 Prints one JSON line on stdout; progress goes to stderr.
 
@@ -176,7 +176,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-baseline", choices=["full", "none"], default="full",
                     help="time the FP64 oracle on one factorization of the same matrix")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "tables"], default="c2")
+    ap.add_argument("--tables-n", default="", help="tables: comma-separated orders n (default: the paper's)")
     ap.add_argument("--model", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                     "paper_2103_07245_amd", "weights", "qk_mlp.bin"),
                     help="c5: trained q/k network")
@@ -211,6 +212,8 @@ def main():
         return bench_c4(args, torch, np, synth, B, dev)
     if args.workload == "c5":
         return bench_c5(args, torch, np, synth, B, dev)
+    if args.workload == "tables":
+        return bench_tables(args, torch, np, synth, B, dev)
 
     return bench_single(args, torch, np, synth, B, dev)
 
@@ -351,6 +354,69 @@ def bench_single(args, torch, np, synth, B, dev):
         f"speedup_{flag_plan}_vs_fp32": round(base["ms"] / flag["ms"], 3),
         "hbm_floor_ms": round(a_bytes / (PEAK["hbm"] * 1e9) * 1e3, 4),
         "algorithmic_tflop_per_factorization": flops / 1e12,
+    }
+    print(json.dumps(line), flush=True)
+
+
+# The paper's PbP-QLP runtimes (seconds; MATLAB, FP64, on a 4-core 1.8 GHz
+# Intel Core i7 with 8 GB of memory), Section V-A Tables I-III:
+# PAPER_SECONDS[d/n][q] = times for n = 5000, 10000, 15000, 20000, 25000.
+PAPER_SECONDS = {
+    0.04: {0: [0.29, 2.2, 7.1, 16.0, 31.6], 1: [0.53, 4.1, 12.7, 28.7, 56.6], 2: [0.81, 5.9, 18.6, 41.4, 81.7]},
+    0.2: {0: [2.1, 15.4, 48.7, 160, 319], 1: [3.3, 24.1, 77.5, 248, 496], 2: [4.3, 33.4, 107, 332, 654]},
+    0.3: {0: [3.5, 25.9, 95.0, 285, 601], 1: [5.2, 38.7, 146, 402, 896], 2: [7.0, 51.5, 197, 530, 1201]},
+}
+TABLE_N = [5000, 10000, 15000, 20000, 25000]
+
+
+def bench_tables(args, torch, np, synth, B, dev):
+    """The paper's runtime experiment (square dense matrices of order n,
+    d = 0.04 n, 0.2 n, 0.3 n, q = 0, 1, 2) on the GPU, FP64 as in the paper and
+    FP32: seconds per factorization with l = d (k = d, p = 0).  The
+    distribution of the singular values does not affect the run time, so A
+    is a seeded Gaussian matrix generated on the GPU."""
+    ns = [int(x) for x in args.tables_n.split(",")] if args.tables_n else TABLE_N
+    rows = []
+    t_all = time.time()
+    for n in ns:
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(synth.seed_a(6, n))
+        A64 = torch.randn(n, n, generator=gen, device=dev, dtype=torch.float64)
+        A32 = A64.float()
+        for frac in (0.04, 0.2, 0.3):
+            d = int(round(frac * n))
+            for q in (0, 1, 2):
+                rec = {"n": n, "d": d, "q": q}
+                for name, A in (("fp64", A64), ("fp32", A32)):
+                    f = B.Factorizer(n, n, d, 0, q, A.dtype, "native", dev)
+                    f(A, 1)
+                    torch.cuda.synchronize()
+                    reps = 2
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        f(A, 1)
+                    torch.cuda.synchronize()
+                    rec[name + "_s"] = (time.perf_counter() - t0) / reps
+                    rec[name + "_resid_est"] = f.info().resid_rel_est
+                    del f
+                if n in TABLE_N:
+                    rec["paper_s"] = PAPER_SECONDS[frac][q][TABLE_N.index(n)]
+                    rec["fp64_speedup_vs_paper"] = round(rec["paper_s"] / rec["fp64_s"], 1)
+                rows.append(rec)
+                log(f"n={n} d={d} q={q}: fp64 {rec['fp64_s'] * 1e3:.1f} ms, fp32 {rec['fp32_s'] * 1e3:.1f} ms"
+                    + (f" (paper {rec['paper_s']} s)" if "paper_s" in rec else ""))
+        del A64, A32
+        torch.cuda.empty_cache()
+    big = rows[-1]
+    line = {
+        "metric": "PbP-QLP seconds per factorization on the paper's runtime shapes (Tables I-III), FP64",
+        "value": round(big["fp64_s"], 4), "unit": "s/factorization", "n_gpus": 1, "steps": 2, "warmup": 1,
+        "ms_per_step": round(big["fp64_s"] * 1e3, 2), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"square Gaussian n x n, d = 0.04n/0.2n/0.3n, q = 0..2; value: n = {big['n']}, "
+                               f"d = {big['d']}, q = {big['q']}", "k": "d", "p": 0},
+        "rows": rows, "wall_s": round(time.time() - t_all, 1),
+        "paper_hardware": "MATLAB, 4-core Intel Core i7 at 1.8 GHz, 8 GB (Section V)",
     }
     print(json.dumps(line), flush=True)
 

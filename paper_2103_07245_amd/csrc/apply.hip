@@ -123,6 +123,7 @@ struct ApplyP {
   int64_t ldq;
   void* Qrm;
   int64_t ldqr;
+  int64_t wq;     // rows of Qcm written (padding rows up to ldq, or only len for a sub-matrix)
   PBQ_GRID;
 };
 
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = 16 * J + acc_row<T>(lg, r);
-      if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = y[J][r];
+      if (Qcm && arow < prm.wq) Qcm[(int64_t)c * ldq + arow] = y[J][r];
       if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[J][r];
     }
 }
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(256) void apply_cols_kernel(const ApplyP* pb, Apply
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int c = 16 * K + acc_row<T>(lg, r);
-        if (Qcm && arow < ldq) Qcm[(int64_t)c * ldq + arow] = y[sl][r];
+        if (Qcm && arow < prm.wq) Qcm[(int64_t)c * ldq + arow] = y[sl][r];
         if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[sl][r];
       }
     }
@@ -345,13 +346,14 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const RightMulP* pb, Rig
 template <typename T, int NT>
 static hipError_t apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
                                const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
-                               void* Qrm, int64_t ldqr, hipStream_t s) {
+                               void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq) {
   CompleteP c{(void*)Y, ldy, len, l, lp, dep, seed};
   hipError_t e = launch_k(complete_kernel<T, false>, complete_kernel<T, true>, dim3((unsigned)((len + 255) / 256)),
                           dim3(256), s, c);
   if (e != hipSuccess) return e;
-  const int64_t rows = Qcm ? (ldq > len ? ldq : len) : len;
-  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr};
+  if (wq < 0) wq = ldq;
+  const int64_t rows = Qcm ? (wq > len ? wq : len) : len;
+  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr, wq};
   if constexpr (sizeof(T) == 8) {
     if (rows <= 256)  // the FP64 l x l stages: four waves per row panel
       return launch_k(apply_cols_kernel<T, NT, false>, apply_cols_kernel<T, NT, true>,
@@ -375,13 +377,13 @@ static hipError_t right_mul_launch(const void* In, int64_t ldi, int64_t len, int
 
 hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
                         const void* Ra, const void* Dinv, const int* dep, uint64_t seed, void* Qcm,
-                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s) {
+                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq) {
   if (lp % 16 || lp < 16 || lp > kMaxL) return hipErrorInvalidValue;
   switch (lp / 16) {
-#define PBQ_CASE(N)                                                                                         \
-  case N:                                                                                                   \
-    return f64 ? apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s)   \
-               : apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s);
+#define PBQ_CASE(N)                                                                                             \
+  case N:                                                                                                       \
+    return f64 ? apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s, wq)   \
+               : apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s, wq);
     PBQ_TILES(PBQ_CASE)
 #undef PBQ_CASE
   }

@@ -37,7 +37,6 @@ hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, 
 // FP32 column-major operand -> compute type (mode BF16/FP16/BF16X3), zero padded
 hipError_t launch_convert(int mode, const float* X, int64_t ld, int64_t len, int l, int lp32,
                           float scale, void* hi, void* lo, hipStream_t s);
-// out[c*ldo + i] = sum_s part[s*stride + c*ld + i]   (i < ldo; zero for i >= len)
 // out[c][i] = sum of the S partials for i < len, 0 for len <= i < wlen (wlen < 0: ldo)
 hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int S, int64_t ld,
                                 int lp, int64_t len, void* out, int64_t ldo, hipStream_t s,
@@ -48,14 +47,18 @@ int gram_splits(int64_t len, int lp, int target);
 size_t gram_partial_elems(int64_t len, int lp, int target);
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
                        double* G, int64_t ldg, int target, hipStream_t s);
-// Cholesky of the Gram with dependent-column detection (single workgroup)
+// Cholesky of the Gram with dependent-column detection (single workgroup,
+// lp <= 256); gdiag (optional): the diagonal the dependence test measures
+// against, when G is a trailing block already updated by earlier panels
 hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
-                       hipStream_t s);
-// Q = Y Ra^-1 by blocked substitution (column-major in/out), optional row-major copy
+                       hipStream_t s, const double* gdiag = nullptr);
+// Q = Y Ra^-1 by blocked substitution (column-major in/out), optional row-major copy;
+// Qcm rows [0, wq) are written (wq < 0: ldq, the padding rows zeroed)
 hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
                         const void* Ra, const void* Dinv, const int* dep, uint64_t seed,
-                        void* Qcm, int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s);
+                        void* Qcm, int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s,
+                        int64_t wq = -1);
 // Out = In M with M dense l x l given row-major (Mr[k*ldm + j] = M[k][j])
 hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
                             const void* Mr, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
@@ -83,5 +86,20 @@ hipError_t launch_info_finalize(void* info, const double* normA_part, int nparts
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_copy_mat(const double* in, int64_t ldi, int rows, int cols, double* out,
                            int64_t ldo, int upper_only, hipStream_t s);
+
+// ---- wide sketches (l > 256) ----
+// Omega for any width (column-major lp32 x ld, same values as launch_omega_cm)
+hipError_t launch_omega_big(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot, int64_t ld,
+                            hipStream_t s);
+// Cout = beta Cin + alpha A B with element strides; dt 0: FP32, 1: FP64,
+// 2: FP32 operands accumulated in FP64 into an FP64 C, 3: FP32 A and C with
+// an FP64 B (FP32 accumulation); upper: skip output tiles wholly below the
+// diagonal
+hipError_t launch_gemm(int dt, int64_t M, int64_t N, int64_t K, const void* A, int64_t sai, int64_t sak,
+                       const void* B, int64_t sbk, int64_t sbj, const void* Cin, void* Cout, int64_t sci,
+                       int64_t scj, double alpha, double beta, bool upper, hipStream_t s);
+hipError_t launch_save_diag(const double* G, int64_t ldg, int l, int lp, double* d, hipStream_t s);
+hipError_t launch_zero_dep_rows(double* R, int64_t ldr, int rows, int64_t cols, const int* dep, hipStream_t s);
+hipError_t launch_cast_f32(const double* in, float* out, int64_t count, hipStream_t s);
 
 }  // namespace pbq

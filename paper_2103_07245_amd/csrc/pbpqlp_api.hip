@@ -81,6 +81,10 @@ double dep_eps(bool f64, int l, int64_t len) {
   return a > b ? a : b;
 }
 
+// Widest sketch of the single-problem path (the blocked l x l stages); the
+// batched path stays at 256.
+constexpr int kMaxWideL = 16384;
+
 struct Split {
   int S;
   int64_t chunk;
@@ -201,6 +205,18 @@ struct Ctx {
   bool bounce = false;
   void* bounce_buf[2] = {nullptr, nullptr};
   hipEvent_t ev_bounce[2] = {nullptr, nullptr};
+  // sketches wider than 256 columns: the l x l stages are blocked by 256
+  bool wide = false;
+  double* gdiag = nullptr;             // the Gram's diagonal before the blocked updates
+  int nbw() const { return (lp + kMaxL - 1) / kMaxL; }
+  // apply forms, diagonal-block inverses and dependence flags of block J
+  void* ra_blk(bool f64, int J) const {
+    return (char*)(f64 ? Ra64 : Ra) + (size_t)J * kMaxL * kMaxL * (f64 ? 8 : el);
+  }
+  void* dinv_blk(bool f64, int J) const {
+    return (char*)(f64 ? Dinv64 : Dinv) + (size_t)J * (kMaxL / 16) * 256 * (f64 ? 8 : el);
+  }
+  int* dep_blk(int J) const { return dep + (size_t)J * (kMaxL + 16); }
 
   int64_t mM() const { return tv ? n : m; }
   int64_t nM() const { return tv ? m : n; }
@@ -285,12 +301,17 @@ struct Ctx {
     M1 = (double*)b.take((size_t)lp32 * ldS * 8);
     Qt64 = (double*)b.take((size_t)lp32 * ldS * 8);
     Qt32 = b.take((size_t)lp32 * ldS * 4);
-    Ra = b.take((size_t)lp * lp * el);
-    Dinv = b.take((size_t)(lp / 16) * 256 * el);
-    Ra64 = b.take((size_t)lp * lp * 8);
-    Dinv64 = b.take((size_t)(lp / 16) * 256 * 8);
-    dep = (int*)b.take((size_t)(lp + 1) * sizeof(int));
+    // wide sketches keep one 256 x 256 apply form per diagonal block
+    const size_t nra = wide ? (size_t)nbw() * kMaxL * kMaxL : (size_t)lp * lp;
+    const size_t ndv = wide ? (size_t)nbw() * (kMaxL / 16) * 256 : (size_t)(lp / 16) * 256;
+    const size_t ndep = wide ? (size_t)nbw() * (kMaxL + 16) : (size_t)lp + 1;
+    Ra = b.take(nra * el);
+    Dinv = b.take(ndv * el);
+    Ra64 = b.take(nra * 8);
+    Dinv64 = b.take(ndv * 8);
+    dep = (int*)b.take(ndep * sizeof(int));
     rowsq = (double*)b.take((size_t)lp * sizeof(double));
+    gdiag = wide ? (double*)b.take((size_t)lp * sizeof(double)) : nullptr;
     if (panel_rows > 0) {
       stage[0] = b.take((size_t)panel_rows * lda * el);
       stage[1] = b.take((size_t)panel_rows * lda * el);
@@ -312,12 +333,13 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
   if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
   if (!valid_args(m, n, k, p, q) || lda < n) return PBPQLP_EINVAL;
   const int l = k + p;
-  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  if (l > (batched ? kMaxL : kMaxWideL)) return PBPQLP_EUNSUPPORTED;
   pbpqlp_opts o;
   pbpqlp_default_opts(&o);
   if (opts) o = *opts;
   c.m = m; c.n = n; c.lda = lda; c.q = q; c.tv = tv;
   c.l = l; c.lp = (int)rup(l, 16); c.lp32 = (int)rup(l, 32);
+  c.wide = c.lp > kMaxL;
   c.f64 = dt == PBPQLP_F64;
   c.el = c.f64 ? 8 : 4;
   c.ldm = rup(m, 64); c.ldn = rup(n, 64); c.ldS = rup(c.lp, 64);
@@ -344,6 +366,19 @@ pbpqlp_status setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype dt, 
 
 bool needs16(const Ctx& c) {
   return c.mode_sketch >= M_BF16 || c.mode_power >= M_BF16 || c.mode_proj >= M_BF16;
+}
+
+// The launch of a product over columns [j0, j0 + 256) of X and of the result
+// (the whole product when l <= 256).
+StreamArgs slice_args(const Ctx& c, const StreamArgs& a, int mode, int j0) {
+  StreamArgs s = a;
+  const int w32 = c.lp32 - j0 < kMaxL ? c.lp32 - j0 : kMaxL;
+  s.lp32 = w32;
+  s.lp = c.lp - j0 < w32 ? c.lp - j0 : w32;
+  const size_t xel = mode >= M_BF16 ? 2 : c.el;
+  s.X = (const char*)a.X + (size_t)j0 * a.ldx * xel;
+  if (a.Xlo) s.Xlo = (const char*)a.Xlo + (size_t)j0 * a.ldx * xel;
+  return s;
 }
 
 // One pass over a host-resident A (Section IV-E: with A stored externally each
@@ -385,55 +420,61 @@ pbpqlp_status host_pass(Ctx& c, bool trans, int mode, StreamArgs a, int64_t xlen
     }
     PBQ_CHECK(hipEventRecord(c.ev_copied[b], c.cs));
     PBQ_CHECK(hipStreamWaitEvent(st, c.ev_copied[b], 0));
-    StreamArgs pa = a;
-    pa.A = c.stage[b];
-    pa.m = rows;
-    if (trans) {
-      // A^T X contracts over the panel's rows: the matching rows of X
-      const size_t xel = mode >= M_BF16 ? 2 : c.el;
-      pa.X = (const char*)a.X + (size_t)r0 * xel;
-      if (a.Xlo) pa.Xlo = (const char*)a.Xlo + (size_t)r0 * xel;
-    }
     // the same split count for every panel (the last may be shorter)
     const Split ps = plan_split(trans ? (c.n + rb - 1) / rb : (rows + rb - 1) / rb, trans ? rows : c.n, sp.S);
-    pa.splits = ps.S;
-    pa.chunk = ps.chunk;
-    pa.normA = normA ? normA + nblk * ps.S : nullptr;
-    if (trans) {
-      pa.out = (char*)c.part + (size_t)slot * c.lp * ldo * c.el;
+    for (int j0 = 0; j0 < c.lp32; j0 += kMaxL) {
+      StreamArgs pa = slice_args(c, a, mode, j0);
+      pa.A = c.stage[b];
+      pa.m = rows;
+      if (trans) {
+        // A^T X contracts over the panel's rows: the matching rows of X
+        const size_t xel = mode >= M_BF16 ? 2 : c.el;
+        pa.X = (const char*)pa.X + (size_t)r0 * xel;
+        if (pa.Xlo) pa.Xlo = (const char*)pa.Xlo + (size_t)r0 * xel;
+      }
+      pa.splits = ps.S;
+      pa.chunk = ps.chunk;
+      pa.normA = (normA && j0 == 0) ? normA + nblk * ps.S : nullptr;
       pa.ldo = ldo;
-      pa.split_stride = (int64_t)c.lp * ldo;
-      slot += ps.S;
-    } else if (ps.S == 1) {
-      pa.out = (char*)out + (size_t)r0 * c.el;
-      pa.ldo = ldo;
-      pa.split_stride = 0;
-    } else {
-      pa.out = c.part;
-      pa.ldo = ldo;
-      pa.split_stride = (int64_t)c.lp * ldo;
+      const size_t jo = (size_t)j0 * ldo * c.el;
+      if (trans) {
+        pa.out = (char*)c.part + (size_t)slot * c.lp * ldo * c.el + jo;
+        pa.split_stride = (int64_t)c.lp * ldo;
+      } else if (ps.S == 1) {
+        pa.out = (char*)out + (size_t)r0 * c.el + jo;
+        pa.split_stride = 0;
+      } else {
+        pa.out = (char*)c.part + jo;
+        pa.split_stride = (int64_t)c.lp * ldo;
+      }
+      const int w = pa.lp < c.l - j0 ? pa.lp : c.l - j0;
+      {
+        const double bytes = (double)rows * c.n * c.el + (double)(trans ? rows : xlen) * w * xb *
+                             (mode == M_BF16X3 ? 2 : 1) + (double)(trans ? c.n : rows) * w * c.el;
+        std::string nm = std::string(trans ? "k2_" : "k1_") + mode_name(mode) + "_panel";
+        TraceScope ts(nm.c_str(), bytes, 2.0 * rows * c.n * w, st, 1);
+        PBQ_CHECK(launch_stream(trans, mode, pa, st));
+      }
+      if (!trans && ps.S > 1) {
+        TraceScope ts("splitk_reduce", (double)(ps.S + 1) * rows * w * c.el, 0.0, st);
+        // only this panel's rows (the last panel also zeroes the padding rows)
+        const int64_t wl = pi == c.npanels - 1 ? ldo - r0 : rows;
+        PBQ_CHECK(launch_splitk_reduce(c.f64, (char*)c.part + jo, pa.split_stride, ps.S, ldo, pa.lp, rows,
+                                       (char*)out + (size_t)r0 * c.el + jo, ldo, st, wl));
+      }
     }
-    {
-      const double bytes = (double)rows * c.n * c.el + (double)(trans ? rows : xlen) * c.l * xb *
-                           (mode == M_BF16X3 ? 2 : 1) + (double)(trans ? c.n : rows) * c.l * c.el;
-      std::string nm = std::string(trans ? "k2_" : "k1_") + mode_name(mode) + "_panel";
-      TraceScope ts(nm.c_str(), bytes, 2.0 * rows * c.n * c.l, st, 1);
-      PBQ_CHECK(launch_stream(trans, mode, pa, st));
-    }
-    if (!trans && ps.S > 1) {
-      TraceScope ts("splitk_reduce", (double)(ps.S + 1) * rows * c.l * c.el, 0.0, st);
-      // only this panel's rows (the last panel also zeroes the padding rows)
-      const int64_t wl = pi == c.npanels - 1 ? ldo - r0 : rows;
-      PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, pa.split_stride, ps.S, ldo, c.lp, rows,
-                                     (char*)out + (size_t)r0 * c.el, ldo, st, wl));
-    }
+    if (trans) slot += ps.S;
     PBQ_CHECK(hipEventRecord(c.ev_used[b], st));
     nblk += (rows + rb - 1) / rb;
   }
   if (trans) {
-    TraceScope ts("splitk_reduce", (double)(slot + 1) * olen * c.l * c.el, 0.0, st);
-    PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, (int64_t)c.lp * ldo, (int)slot, ldo, c.lp, olen, out,
-                                   ldo, st));
+    for (int j0 = 0; j0 < c.lp32; j0 += kMaxL) {
+      const int wl = c.lp - j0 < kMaxL ? c.lp - j0 : kMaxL;
+      const size_t jo = (size_t)j0 * ldo * c.el;
+      TraceScope ts("splitk_reduce", (double)(slot + 1) * olen * wl * c.el, 0.0, st);
+      PBQ_CHECK(launch_splitk_reduce(c.f64, (char*)c.part + jo, (int64_t)c.lp * ldo, (int)slot, ldo, wl, olen,
+                                     (char*)out + jo, ldo, st));
+    }
   }
   return PBPQLP_OK;
 }
@@ -467,30 +508,143 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
   a.ldx = ldx;
   if (c.A_host) return host_pass(c, trans, mode, a, xlen, out, ldo, normA, st);
   const Split sp = c.split_for(mode, trans);
-  a.splits = sp.S;
-  a.chunk = sp.chunk;
-  a.normA = normA;
   const int64_t olen = trans ? c.n : c.m;
-  if (sp.S == 1) {
-    a.out = out;
-    a.ldo = ldo;
-    a.split_stride = 0;
-  } else {
-    a.out = c.part;
-    a.ldo = ldo;
-    a.split_stride = (int64_t)c.lp * ldo;
+  const double xb = (mode >= M_BF16) ? 2.0 : (double)c.el;
+  // at most 256 columns of X per launch: wider sketches take several launches
+  for (int j0 = 0; j0 < c.lp32; j0 += kMaxL) {
+    StreamArgs sa = slice_args(c, a, mode, j0);
+    sa.splits = sp.S;
+    sa.chunk = sp.chunk;
+    sa.normA = j0 == 0 ? normA : nullptr;
+    sa.ldo = ldo;
+    char* outj = (char*)out + (size_t)j0 * ldo * c.el;
+    char* partj = (char*)c.part + (size_t)j0 * ldo * c.el;
+    if (sp.S == 1) {
+      sa.out = outj;
+      sa.split_stride = 0;
+    } else {
+      sa.out = partj;
+      sa.split_stride = (int64_t)c.lp * ldo;
+    }
+    const int w = sa.lp < c.l - j0 ? sa.lp : c.l - j0;
+    {
+      const double bytes = (double)c.m * c.n * c.el + (double)xlen * w * xb * (mode == M_BF16X3 ? 2 : 1) +
+                           (double)olen * w * c.el;
+      std::string nm = std::string(trans ? "k2_" : "k1_") + mode_name(mode);
+      TraceScope ts(nm.c_str(), bytes, 2.0 * c.m * c.n * w, st, 1);
+      PBQ_CHECK(launch_stream(trans, mode, sa, st));
+    }
+    if (sp.S > 1) {
+      TraceScope ts("splitk_reduce", (double)(sp.S + 1) * olen * w * c.el, 0.0, st);
+      PBQ_CHECK(launch_splitk_reduce(c.f64, partj, sa.split_stride, sp.S, ldo, sa.lp, olen, outj, ldo, st));
+    }
   }
-  {
-    const double xb = (mode >= M_BF16) ? 2.0 : (double)c.el;
-    const double bytes = (double)c.m * c.n * c.el + (double)xlen * c.l * xb * (mode == M_BF16X3 ? 2 : 1) +
-                         (double)olen * c.l * c.el;
-    std::string nm = std::string(trans ? "k2_" : "k1_") + mode_name(mode);
-    TraceScope ts(nm.c_str(), bytes, 2.0 * c.m * c.n * c.l, st, 1);
-    PBQ_CHECK(launch_stream(trans, mode, a, st));
+  return PBPQLP_OK;
+}
+
+// Blocked upper Cholesky G = Rt^T Rt (lp x lp, FP64) for lp > 256, blocks of
+// 256: each diagonal block (already updated by the earlier blocks) is
+// factored by the single-workgroup Cholesky with the dependence test measured
+// against the Gram's own diagonal; the block's row of Rt is the triangular
+// solve R_J,K = R_JJ^-T G_J,K (the tall apply on the FP64 matrix cores, the
+// rows of dependent columns set to 0), and the trailing upper triangle takes
+// G_K,K' -= R_J,K^T R_J,K' on the FP64 matrix cores.  Outputs: Rt (lower part
+// 0), and per diagonal block its apply form, inverses and dependence flags in
+// the storage type of the tall matrix.
+pbpqlp_status chol_wide(Ctx& c, bool f64, double eps, double* Rt, void* info, hipStream_t st) {
+  const int lp = c.lp, l = c.l, nb = c.nbw();
+  double* G = c.G;
+  PBQ_CHECK(launch_save_diag(G, lp, l, lp, c.gdiag, st));
+  PBQ_CHECK(launch_fill_zero(Rt, (size_t)lp * lp * sizeof(double), st));
+  for (int J = 0; J < nb; ++J) {
+    const int j0 = J * kMaxL;
+    const int bJ = lp - j0 < kMaxL ? lp - j0 : kMaxL;
+    const int lJ = l - j0 < bJ ? (l - j0 > 0 ? l - j0 : 0) : bJ;
+    const int64_t rest = lp - (j0 + bJ);
+    {
+      TraceScope ts("chol", (double)bJ * bJ * 8 * 2, (double)bJ * bJ * bJ / 3.0, st);
+      PBQ_CHECK(launch_chol(true, G + (size_t)j0 * lp + j0, lp, lJ, bJ, eps, Rt + (size_t)j0 * lp + j0, lp,
+                            c.ra_blk(true, J), c.dinv_blk(true, J), c.dep_blk(J), info, st, c.gdiag + j0));
+    }
+    if (!f64) {
+      PBQ_CHECK(launch_cast_f32((const double*)c.ra_blk(true, J), (float*)c.ra_blk(false, J), (int64_t)bJ * bJ, st));
+      PBQ_CHECK(launch_cast_f32((const double*)c.dinv_blk(true, J), (float*)c.dinv_blk(false, J),
+                                (int64_t)(bJ / 16) * 256, st));
+    }
+    if (rest <= 0) continue;
+    const size_t off = (size_t)j0 * lp + j0 + bJ;
+    {
+      // R_J,K^T = G_K,J R_JJ^-1: column c of the tall operand is row j0 + c
+      TraceScope ts("chol_panel", 2.0 * rest * bJ * 8, (double)rest * bJ * bJ, st);
+      PBQ_CHECK(launch_apply(true, G + off, lp, rest, bJ, lJ, c.ra_blk(true, J), c.dinv_blk(true, J),
+                             c.dep_blk(J), c.seed, Rt + off, lp, nullptr, 0, st, rest));
+      PBQ_CHECK(launch_zero_dep_rows(Rt + off, lp, bJ, rest, c.dep_blk(J), st));
+    }
+    {
+      const size_t t0 = (size_t)(j0 + bJ);
+      TraceScope ts("chol_update", (double)rest * rest * 8 * 2, (double)rest * rest * bJ, st);
+      PBQ_CHECK(launch_gemm(1, rest, rest, bJ, Rt + off, 1, lp, Rt + off, lp, 1, G + t0 * lp + t0,
+                            G + t0 * lp + t0, lp, 1, -1.0, 1.0, true, st));
+    }
   }
-  if (sp.S > 1) {
-    TraceScope ts("splitk_reduce", (double)(sp.S + 1) * olen * c.l * c.el, 0.0, st);
-    PBQ_CHECK(launch_splitk_reduce(c.f64, c.part, a.split_stride, sp.S, ldo, c.lp, olen, out, ldo, st));
+  return PBPQLP_OK;
+}
+
+// Q = Y Rt^-1 for lp > 256 by column blocks of 256: block J first takes
+// Y_J - Q_<J Rt_<J,J (a matrix-core product), then the single-block apply
+// with block J's apply form (dependent columns completed as in the narrow
+// path).  dst may be written in place of the block being solved.
+pbpqlp_status apply_wide(Ctx& c, bool f64, const void* src, int64_t ld, int64_t len, const double* Rt,
+                         uint64_t cseed, void* dst, void* rm, int64_t ldrm, hipStream_t st) {
+  const int lp = c.lp, l = c.l, nb = c.nbw();
+  const size_t el = f64 ? 8 : c.el;
+  for (int J = 0; J < nb; ++J) {
+    const int j0 = J * kMaxL;
+    const int bJ = lp - j0 < kMaxL ? lp - j0 : kMaxL;
+    const int lJ = l - j0 < bJ ? (l - j0 > 0 ? l - j0 : 0) : bJ;
+    const void* srcJ = (const char*)src + (size_t)j0 * ld * el;
+    void* dstJ = (char*)dst + (size_t)j0 * ld * el;
+    if (J > 0) {
+      TraceScope ts("apply_update", 2.0 * len * bJ * el, 2.0 * len * j0 * bJ, st);
+      PBQ_CHECK(launch_gemm(f64 ? 1 : 3, len, bJ, j0, dst, 1, ld, Rt + j0, lp, 1, srcJ, dstJ, 1, ld, -1.0, 1.0,
+                            false, st));
+      srcJ = dstJ;
+    }
+    TraceScope ts("apply", 2.0 * len * bJ * el, (double)len * bJ * bJ, st);
+    PBQ_CHECK(launch_apply(f64, srcJ, ld, len, bJ, lJ, c.ra_blk(f64, J), c.dinv_blk(f64, J), c.dep_blk(J),
+                           cseed + (uint64_t)J, dstJ, ld, rm ? (char*)rm + (size_t)j0 * el : nullptr, ldrm, st));
+  }
+  return PBPQLP_OK;
+}
+
+pbpqlp_status orth_wide(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes, void* out,
+                        void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm, void* info,
+                        hipStream_t st, bool small) {
+  const double eps = dep_eps(f64, c.l, len);
+  const void* src = X;
+  for (int ps = 0; ps < passes; ++ps) {
+    const bool last = ps == passes - 1;
+    void* dst = last ? out : tmp;
+    double* Rt = ps == 0 ? c.R1 : c.R2;
+    const uint64_t cseed = c.seed ^ (0x9E3779B97F4A7C15ull * (++c.ncall));
+    const double el = f64 ? 8.0 : (double)c.el;
+    {
+      TraceScope ts(small ? "gram_ll" : "gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
+      PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, c.gram_target, st));
+    }
+    pbpqlp_status s = chol_wide(c, f64, eps, Rt, info, st);
+    if (s) return s;
+    s = apply_wide(c, f64, src, ld, len, Rt, cseed, dst, last ? rm : nullptr, ldrm, st);
+    if (s) return s;
+    src = dst;
+  }
+  if (Rkeep) {
+    TraceScope ts("r2r1", 3.0 * c.lp * c.lp * 8, 2.0 * c.lp * c.lp * c.lp, st);
+    if (passes == 1)
+      PBQ_CHECK(launch_copy_mat(c.R1, c.lp, c.lp, c.lp, Rkeep, ldrk, 1, st));
+    else
+      PBQ_CHECK(launch_gemm(1, c.lp, c.lp, c.lp, c.R2, c.lp, 1, c.R1, c.lp, 1, nullptr, Rkeep, ldrk, 1, 1.0, 0.0,
+                            false, st));
   }
   return PBPQLP_OK;
 }
@@ -502,6 +656,7 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
 pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes,
                    void* out, void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm,
                    void* info, hipStream_t st, bool small = false) {
+  if (c.wide) return orth_wide(c, f64, X, ld, len, passes, out, tmp, Rkeep, ldrk, rm, ldrm, info, st, small);
   const double eps = dep_eps(f64, c.l, len);
   void* Ra = f64 ? c.Ra64 : c.Ra;
   void* Dv = f64 ? c.Dinv64 : c.Dinv;
@@ -561,7 +716,8 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
     if (c.omega_in)
       PBQ_CHECK(launch_rm_to_cm(c.f64, c.omega_in, c.ldo_in, nM, c.l, c.lp32, c.Om, ldnM, st));
     else
-      PBQ_CHECK(launch_omega_cm(c.f64, nM, c.l, c.lp32, c.seed, c.Om, ldnM, st));
+      PBQ_CHECK(c.wide ? launch_omega_big(c.f64, nM, c.l, c.lp32, c.seed, c.Om, ldnM, st)
+                       : launch_omega_cm(c.f64, nM, c.l, c.lp32, c.seed, c.Om, ldnM, st));
   }
   // S1: Y = M Omega (+ ||A||_F^2 when this pass is A X)
   pbpqlp_status s;
@@ -604,7 +760,11 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   }
   {
     TraceScope ts("right_mul", 2.0 * mM * c.l * c.el, 2.0 * mM * c.l * c.l, st);
-    PBQ_CHECK(launch_right_mul(c.f64, c.Qm, ldmM, mM, c.lp, c.l, Mr, c.ldS, nullptr, 0, Q, ldq, st));
+    if (c.wide)
+      PBQ_CHECK(launch_gemm(c.f64 ? 1 : 0, mM, c.l, c.l, c.Qm, 1, ldmM, Mr, c.ldS, 1, nullptr, Q, ldq, 1, 1.0,
+                            0.0, false, st));
+    else
+      PBQ_CHECK(launch_right_mul(c.f64, c.Qm, ldmM, mM, c.lp, c.l, Mr, c.ldS, nullptr, 0, Q, ldq, st));
   }
   // S8: result record; numerical rank from the L-values
   {
@@ -1062,7 +1222,7 @@ pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt, voi
                            int64_t ldo, void* stream) {
   if (!Omega || n < 1 || l < 1 || ldo < l) return PBPQLP_EINVAL;
   if (dt != PBPQLP_F64 && dt != PBPQLP_F32) return PBPQLP_EINVAL;
-  if (l > kMaxL) return PBPQLP_EUNSUPPORTED;
+  if (l > kMaxWideL) return PBPQLP_EUNSUPPORTED;
   const bool f64 = dt == PBPQLP_F64;
   if (!aligned(Omega, f64 ? 8 : 4)) return PBPQLP_EINVAL;
   // the factorization's own generator (column-major), then the caller's layout
@@ -1072,7 +1232,8 @@ pbpqlp_status pbpqlp_omega(int64_t n, int l, uint64_t seed, pbpqlp_dtype dt, voi
   ScratchGuard g;
   pbpqlp_status s = alloc_scratch(g, (size_t)lp32 * ld * (f64 ? 8 : 4), st);
   if (s) return s;
-  PBQ_CHECK(launch_omega_cm(f64, n, l, lp32, seed, g.p, ld, st));
+  PBQ_CHECK(lp32 > kMaxL ? launch_omega_big(f64, n, l, lp32, seed, g.p, ld, st)
+                         : launch_omega_cm(f64, n, l, lp32, seed, g.p, ld, st));
   PBQ_CHECK(launch_cm_to_rm(f64, g.p, ld, n, l, Omega, ldo, st));
   return PBPQLP_OK;
 }

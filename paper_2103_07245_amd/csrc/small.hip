@@ -205,6 +205,7 @@ struct CholP {
   void* Dinv;
   int* dep;
   pbpqlp_info* info;
+  const double* gdiag;  // dependence reference diagonal, or null (G's own)
   PBQ_GRID;
 };
 
@@ -226,7 +227,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, Cho
   __shared__ CholShared sh;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   if (tid < kMaxL) {
-    sh.gd[tid] = (tid < l) ? G[(int64_t)tid * ldg + tid] : 0.0;
+    sh.gd[tid] = (tid < l) ? (prm.gdiag ? prm.gdiag[tid] : G[(int64_t)tid * ldg + tid]) : 0.0;
     sh.sdep[tid] = 0;
   }
   if (tid == 0) sh.sflag = 0;
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
   __shared__ CholSharedDW sh;
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   if (tid < kMaxL) {
-    sh.gd[tid] = (tid < l) ? G[(int64_t)tid * ldg + tid] : 0.0;
+    sh.gd[tid] = (tid < l) ? (prm.gdiag ? prm.gdiag[tid] : G[(int64_t)tid * ldg + tid]) : 0.0;
     sh.sdep[tid] = 0;
   }
   if (tid == 0) {
@@ -726,9 +727,9 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
 
 hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
-                       hipStream_t s) {
+                       hipStream_t s, const double* gdiag) {
   if (lp > kMaxL || (lp & 15)) return hipErrorInvalidValue;
-  CholP p{G, ldg, l, lp, eps_dep, Rt, ldr, Ra, Dinv, dep, (pbpqlp_info*)info};
+  CholP p{G, ldg, l, lp, eps_dep, Rt, ldr, Ra, Dinv, dep, (pbpqlp_info*)info, gdiag};
   if (lp <= 16 * kDwRows) {
     if (f64) return launch_k(chol_dw_kernel<double, false>, chol_dw_kernel<double, true>, dim3(1), dim3(kCholThreads), s, p);
     return launch_k(chol_dw_kernel<float, false>, chol_dw_kernel<float, true>, dim3(1), dim3(kCholThreads), s, p);
@@ -920,7 +921,9 @@ __global__ void info_finalize_kernel(const InfoFinP* pb, InfoFinP ps) {
   }
   if (i < p.nparts) a0 += p.parts[i];
   ra[t] = a0 + a1;
-  rl[t] = (t < p.l) ? p.rowsq[t] : 0.0;
+  double sl = 0.0;
+  for (int r = t; r < p.l; r += 256) sl += p.rowsq[r];
+  rl[t] = sl;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (t < off) {

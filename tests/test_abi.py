@@ -64,7 +64,8 @@ def test_invalid_arguments_rejected_before_launch(kw):
 
 
 def test_unsupported_width_and_precision():
-    assert _factor(m=400, n=400, lda=400, k=250, p=10, ldq=260, ldl=260, ldp=260) == B.EUNSUPPORTED
+    # sketches up to 16384 columns are supported (wider ones are blocked by 256)
+    assert _factor(m=20000, n=20000, lda=20000, k=16380, p=10, ldq=16390, ldl=16390, ldp=16390) == B.EUNSUPPORTED
     o = B.make_opts("bf16")
     assert _factor(dt=B.F64, opts=ctypes.byref(o)) == B.EUNSUPPORTED
 
@@ -256,7 +257,7 @@ def test_factor_host_argument_errors():
     assert call(ldq=7) == B.EINVAL
     assert call(Q=0x2002) == B.EINVAL
     assert call(Q=0x2000, P=0x2000) == B.EINVAL
-    assert call(m=400, n=400, lda=400, k=250, p=10, ldq=260) == B.EUNSUPPORTED
+    assert call(m=20000, n=20000, lda=20000, k=16380, p=10, ldq=16390) == B.EUNSUPPORTED
     one = B.workspace_size_host(4096, 1024, 40, 8, panel_rows=4096)
     four = B.workspace_size_host(4096, 1024, 40, 8, panel_rows=1024)
     # two staging panels of 4096 (one panel) or 1024 rows of 1024 FP32 values
