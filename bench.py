@@ -9,7 +9,7 @@ whole factorization (sketch, 2q power passes with re-orthonormalization,
 projection, QR of B^T, QR of R^T, Q Qt) on the resident matrix.
 
     python bench.py [--steps K] [--warmup W] [--cpu-baseline full|none]
-    python bench.py --workload c3|c4|c5|tables [--steps K] [--warmup W]
+    python bench.py --workload c3|c4|c5|tables|sparse [--steps K] [--warmup W]
 
 Prints one JSON line on stdout; progress goes to stderr.
 
@@ -176,7 +176,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-baseline", choices=["full", "none"], default="full",
                     help="time the FP64 oracle on one factorization of the same matrix")
-    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "tables"], default="c2")
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5", "tables", "sparse"], default="c2")
+    ap.add_argument("--sparse-m", type=int, default=2_000_000)
+    ap.add_argument("--sparse-n", type=int, default=1_000_000)
+    ap.add_argument("--sparse-nnz-row", type=int, default=20)
     ap.add_argument("--tables-n", default="", help="tables: comma-separated orders n (default: the paper's)")
     ap.add_argument("--model", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                     "paper_2103_07245_amd", "weights", "qk_mlp.bin"),
@@ -214,6 +217,8 @@ def main():
         return bench_c5(args, torch, np, synth, B, dev)
     if args.workload == "tables":
         return bench_tables(args, torch, np, synth, B, dev)
+    if args.workload == "sparse":
+        return bench_sparse(args, torch, np, synth, B, dev)
 
     return bench_single(args, torch, np, synth, B, dev)
 
@@ -417,6 +422,63 @@ def bench_tables(args, torch, np, synth, B, dev):
                                f"d = {big['d']}, q = {big['q']}", "k": "d", "p": 0},
         "rows": rows, "wall_s": round(time.time() - t_all, 1),
         "paper_hardware": "MATLAB, 4-core Intel Core i7 at 1.8 GHz, 8 GB (Section V)",
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sparse(args, torch, np, synth, B, dev):
+    """Sparse A in CSR (Section IV-E, O(z d) per product): m x n FP32 with a
+    fixed number of nonzeros per row whose column indices follow a power law
+    (P(j) proportional to (j + 1)^-0.8: a few nearly dense columns), N(0,1)
+    values, generated on the GPU from a seeded generator; k = 64, p = 16,
+    q = 1.  A step is one whole factorization including the stable transpose
+    of the structure."""
+    m, n, per_row = args.sparse_m, args.sparse_n, args.sparse_nnz_row
+    k, p, q = 64, 16, 1
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(synth.seed_a(7, 0))
+    nnz = m * per_row
+    u = torch.rand(nnz, generator=gen, device=dev, dtype=torch.float64)
+    cols = torch.clamp((n * u ** (1.0 / 0.2)).long(), max=n - 1)      # inverse CDF of ~ (j/n)^0.2
+    rows = torch.arange(m, device=dev).repeat_interleave(per_row)
+    key = rows * n + cols
+    key = torch.unique(key)                                             # sorted, duplicates dropped
+    rows, cols = key // n, key % n
+    nnz = key.numel()
+    rowptr = torch.zeros(m + 1, dtype=torch.int64, device=dev)
+    rowptr[1:] = torch.cumsum(torch.bincount(rows, minlength=m), 0)
+    colind = cols.to(torch.int32).contiguous()
+    vals = torch.randn(nnz, generator=gen, device=dev, dtype=torch.float32)
+    del u, key, rows, cols
+    torch.cuda.synchronize()
+    log(f"sparse {m}x{n}, nnz {nnz} ({nnz / m:.1f} per row)")
+    for _ in range(args.warmup):
+        B.factor_csr(rowptr, colind, vals, (m, n), k, p, q, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Q, L, P, info = B.factor_csr(rowptr, colind, vals, (m, n), k, p, q, 1)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    B.trace_reset()
+    B.trace_enable(2)
+    for _ in range(args.steps):
+        B.factor_csr(rowptr, colind, vals, (m, n), k, p, q, 1)
+    torch.cuda.synchronize()
+    B.trace_enable(0)
+    tab = kernel_table(B.trace_records(), args.steps)
+    B.trace_reset()
+    roofline = roofline_of(tab, args.steps)
+    line = {
+        "metric": "PbP-QLP ms/factorization of a sparse CSR matrix (FP32, power-law columns)",
+        "value": round(ms, 3), "unit": "ms/factorization", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"CSR {m}x{n}, {per_row} nonzeros per row drawn with P(j) ~ (j+1)^-0.8, N(0,1) "
+                               f"values, k={k} p={p} q={q}", "nnz": nnz},
+        "roofline": roofline, "resid_est": info.resid_rel_est,
+        "kernels": {k_: {"ms_per_step": round(v["ms_per_step"], 4), "launches": v["launches"] // args.steps,
+                         "gbs": round(v["gbs"], 1)} for k_, v in sorted(tab.items(), key=lambda kv: -kv[1]["ms_per_step"])},
     }
     print(json.dumps(line), flush=True)
 

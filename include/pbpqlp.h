@@ -104,6 +104,9 @@ typedef struct {
 #define PBPQLP_FLAG_NONFINITE 2  /* a Gram matrix held NaN or Inf (non-finite input)   */
 #define PBPQLP_FLAG_INTERNAL 4   /* a bounded wait inside a kernel gave up (should never
                                     happen): the results of that call are not valid   */
+#define PBPQLP_FLAG_BADINPUT 8   /* sparse input: a row pointer out of order or range, or
+                                    a column index outside [0, n); such entries are
+                                    skipped                                           */
 
 /* Human-readable name of a status code (static storage). */
 const char* pbpqlp_status_string(pbpqlp_status s);
@@ -240,6 +243,33 @@ pbpqlp_status pbpqlp_factor_host(const void* A_host, int64_t m, int64_t n, int64
                                  int64_t panel_rows, void* Q, int64_t ldq, double* L, int64_t ldl,
                                  void* P, int64_t ldp, const pbpqlp_opts* opts, pbpqlp_info* d_info,
                                  void* stream);
+
+/* ---- sparse A (Section IV-E: for a sparse A with z nonzeros each product with
+ * A or A^T costs O(z d)) ----
+ *
+ * pbpqlp_factor for A given in CSR on the device:
+ *   rowptr : m + 1 int64 (rowptr[0] = 0, nondecreasing, rowptr[m] = nnz);
+ *   colind : nnz int32 in [0, n), distinct within a row (any order);
+ *   vals   : nnz values of dtype dt.  All three are read only.
+ * The sketch and power passes and the projection are row-gather products with
+ * A's CSR (A X) and with the CSR of A^T (A^T X), which the call builds first
+ * by a stable counting sort (each row of A^T in increasing row order of A), so
+ * every output entry is summed in one fixed order: results are deterministic.
+ * The orthonormalization stack (Grams, Cholesky, apply, the l x l QR) is the
+ * dense path's; the outputs are those of pbpqlp_factor on the dense A up to
+ * rounding (A ~= Q L^T P^T).  Only the native precision of dt is supported
+ * (every opts precision NATIVE; the gathers are not matrix-core products):
+ * EUNSUPPORTED otherwise.  Invalid structure (row pointers out of order or
+ * range, column indices outside [0, n)) is not read out of bounds: such
+ * entries are skipped and PBPQLP_FLAG_BADINPUT is set in d_info.
+ * Errors: as pbpqlp_factor; EINVAL for nnz < 0, m or n above 2^31 - 1, null
+ * or misaligned arrays. */
+pbpqlp_status pbpqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, pbpqlp_dtype dt,
+                                        const pbpqlp_opts* opts, size_t* bytes);
+pbpqlp_status pbpqlp_factor_csr(const int64_t* rowptr, const int32_t* colind, const void* vals, int64_t m,
+                                int64_t n, int64_t nnz, pbpqlp_dtype dt, int k, int p, int q, uint64_t seed,
+                                void* Q, int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
+                                const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream);
 
 /* ---- allocation-free variant ----
  *

@@ -21,7 +21,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libpbpqlp.so")
 
 SOURCES = ["stream_gemm.hip", "tallskinny.hip", "small.hip", "apply.hip", "pbpqlp_api.hip",
-           "learned.hip", "tune.hip", "reconstruct.hip", "large.hip"]
+           "learned.hip", "tune.hip", "reconstruct.hip", "large.hip", "sparse.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -205,6 +206,23 @@ struct Ctx {
   bool bounce = false;
   void* bounce_buf[2] = {nullptr, nullptr};
   hipEvent_t ev_bounce[2] = {nullptr, nullptr};
+  // sparse A in CSR (Section IV-E): both products are row-gather products
+  bool sparse = false;
+  const int64_t* rowptr = nullptr;
+  const int32_t* colind = nullptr;
+  const void* vals = nullptr;
+  int64_t nnz = 0;
+  int nbT = 1;            // row blocks of the stable transpose
+  int nsq = 1;            // ||A||_F^2 partials
+  int64_t* ptr_t = nullptr;
+  int32_t* idx_t = nullptr;
+  void* vals_t = nullptr;
+  int* tcnt = nullptr;
+  int64_t* colcnt = nullptr;
+  void* Xrm = nullptr;    // row-major copy of the l-column operand (lp32 wide)
+  void* Yrm = nullptr;    // row-major product of one 256-column slice
+  void* spart = nullptr;  // partial rows of the nonzero-balanced product
+  int ldyr() const { return lp32 < kMaxL ? lp32 : kMaxL; }
   // sketches wider than 256 columns: the l x l stages are blocked by 256
   bool wide = false;
   double* gdiag = nullptr;             // the Gram's diagonal before the blocked updates
@@ -250,6 +268,11 @@ struct Ctx {
   // projection for M = A^T.
   void plan_buffers(bool sketch, bool power, bool proj) {
     part_bytes = 0;
+    if (sparse) {
+      k1_blocks = nsq;
+      k1_splits = 1;
+      return;
+    }
     auto need = [&](int mode, bool trans) {
       const size_t b = (size_t)partial_slots(mode, trans) * lp * (trans ? ldn : ldm) * el;
       if (b > part_bytes) part_bytes = b;
@@ -315,6 +338,16 @@ struct Ctx {
     if (panel_rows > 0) {
       stage[0] = b.take((size_t)panel_rows * lda * el);
       stage[1] = b.take((size_t)panel_rows * lda * el);
+    }
+    if (sparse) {
+      ptr_t = (int64_t*)b.take((size_t)(n + 1) * sizeof(int64_t));
+      idx_t = (int32_t*)b.take((size_t)nnz * sizeof(int32_t));
+      vals_t = b.take((size_t)nnz * el);
+      tcnt = (int*)b.take((size_t)nbT * n * sizeof(int));
+      colcnt = (int64_t*)b.take((size_t)n * sizeof(int64_t));
+      Xrm = b.take((size_t)(m > n ? m : n) * lp32 * el);
+      Yrm = b.take((size_t)(m > n ? m : n) * ldyr() * el);
+      spart = b.take((size_t)2 * (spmm_chunks(nnz) > 0 ? spmm_chunks(nnz) : 1) * ldyr() * el);
     }
   }
 };
@@ -479,10 +512,37 @@ pbpqlp_status host_pass(Ctx& c, bool trans, int mode, StreamArgs a, int64_t xlen
   return PBPQLP_OK;
 }
 
+// One pass with a sparse A: the operand is copied row-major (its padding
+// columns are 0 from the set-up), then out = A X with A's CSR or A^T X with
+// the CSR of A^T, 256 columns per launch.
+pbpqlp_status sparse_pass(Ctx& c, bool trans, const void* X, int64_t ldx, int64_t xlen, void* out,
+                          int64_t ldo, hipStream_t st) {
+  {
+    TraceScope ts("sp_rowmajor", 2.0 * xlen * c.l * c.el, 0.0, st);
+    PBQ_CHECK(launch_cm_to_rm(c.f64, X, ldx, xlen, c.l, c.Xrm, c.lp32, st));
+  }
+  const int64_t rows = trans ? c.n : c.m, cols = trans ? c.m : c.n;
+  for (int j0 = 0; j0 < c.lp; j0 += kMaxL) {
+    const int w = c.lp - j0 < kMaxL ? c.lp - j0 : kMaxL;
+    const double bytes = (double)c.nnz * (c.el + 4) + (double)rows * 8 + (double)c.nnz * w * c.el +
+                         (double)rows * w * c.el;
+    TraceScope ts(trans ? "k2_spmm" : "k1_spmm", bytes, 2.0 * c.nnz * w, st, 1);
+    void* oj = (char*)out + (size_t)j0 * ldo * c.el;
+    if (trans)
+      PBQ_CHECK(launch_spmm(c.f64, c.ptr_t, c.idx_t, c.vals_t, rows, cols, c.nnz, c.Xrm, c.lp32, j0, w, c.Yrm,
+                            c.ldyr(), c.spart, oj, ldo, st));
+    else
+      PBQ_CHECK(launch_spmm(c.f64, c.rowptr, c.colind, c.vals, rows, cols, c.nnz, c.Xrm, c.lp32, j0, w, c.Yrm,
+                            c.ldyr(), c.spart, oj, ldo, st));
+  }
+  return PBPQLP_OK;
+}
+
 // One A-streaming pass: out (column-major, ld) = A X (trans=0) or A^T X.
 pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const void* X,
                           int64_t ldx, int64_t xlen, bool unit_columns, void* out, int64_t ldo,
                           double* normA, hipStream_t st) {
+  if (c.sparse) return sparse_pass(c, trans, X, ldx, xlen, out, ldo, st);
   StreamArgs a;
   a.A = A; a.lda = c.lda; a.m = c.m; a.n = c.n;
   a.lp = c.lp;
@@ -709,6 +769,15 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   {
     TraceScope ts("info", 0.0, 0.0, st);
     PBQ_CHECK(launch_info_init(info, c.l, c.q, st));
+  }
+  if (c.sparse) {
+    // CSR of A^T (stable), ||A||_F^2 from the values, zero padding of the
+    // row-major operand copy
+    TraceScope ts("csr_transpose", (double)c.nnz * 2 * (c.el + 4) + (double)c.nbT * c.n * 8, 0.0, st);
+    PBQ_CHECK(launch_fill_zero(c.Xrm, (size_t)(c.m > c.n ? c.m : c.n) * c.lp32 * c.el, st));
+    PBQ_CHECK(launch_csr_transpose(c.f64, c.rowptr, c.colind, c.vals, c.m, c.n, c.nnz, c.nbT, c.tcnt, c.colcnt,
+                                   c.ptr_t, c.idx_t, c.vals_t, &info->status_flags, st));
+    PBQ_CHECK(launch_sumsq(c.f64, c.vals, c.nnz, c.nsq, c.normA, st));
   }
   // S0: sketch matrix, column-major (lp32 x ldnM): generated, or the caller's
   {
@@ -1028,9 +1097,83 @@ pbpqlp_status host_setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype
   return PBPQLP_OK;
 }
 
+pbpqlp_status csr_setup(Ctx& c, int64_t m, int64_t n, int64_t nnz, pbpqlp_dtype dt, int k, int p, int q,
+                        const pbpqlp_opts* opts) {
+  if (nnz < 0 || m > INT32_MAX || n > INT32_MAX) return PBPQLP_EINVAL;
+  pbpqlp_status s = setup(c, m, n, n, dt, k, p, q, opts, false, false);
+  if (s) return s;
+  const int native = c.f64 ? M_F64 : M_F32;
+  if (c.mode_sketch != native || c.mode_power != native || c.mode_proj != native) return PBPQLP_EUNSUPPORTED;
+  c.sparse = true;
+  c.nnz = nnz;
+  // row blocks of the transpose: their column counters take at most 256 MiB
+  int64_t nb = (int64_t)(256ull << 20) / ((int64_t)n * 4);
+  nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
+  c.nbT = (int)(nb < m ? nb : m);
+  const int64_t ns = (nnz + 4095) / 4096;
+  c.nsq = (int)(ns < 1 ? 1 : (ns > 256 ? 256 : ns));
+  c.plan_buffers(true, q > 0, true);
+  return PBPQLP_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+pbpqlp_status pbpqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, pbpqlp_dtype dt,
+                                        const pbpqlp_opts* opts, size_t* bytes) {
+  if (!bytes) return PBPQLP_EINVAL;
+  Ctx c;
+  pbpqlp_status s = csr_setup(c, m, n, nnz, dt, k, p, 1, opts);
+  if (s) return s;
+  Bump b;
+  c.carve(b, false);
+  b.take(sizeof(pbpqlp_info));
+  *bytes = b.off + 256;
+  return PBPQLP_OK;
+}
+
+pbpqlp_status pbpqlp_factor_csr(const int64_t* rowptr, const int32_t* colind, const void* vals, int64_t m,
+                                int64_t n, int64_t nnz, pbpqlp_dtype dt, int k, int p, int q, uint64_t seed,
+                                void* Q, int64_t ldq, double* L, int64_t ldl, void* P, int64_t ldp,
+                                const pbpqlp_opts* opts, pbpqlp_info* d_info, void* stream) {
+  if (!rowptr || (nnz > 0 && (!colind || !vals)) || !Q || !L || !P) return PBPQLP_EINVAL;
+  Ctx c;
+  pbpqlp_status s = csr_setup(c, m, n, nnz, dt, k, p, q, opts);
+  if (s) return s;
+  if (ldq < c.l || ldl < c.l || ldp < c.l || Q == P) return PBPQLP_EINVAL;
+  if (!aligned(rowptr, 8) || !aligned(colind, 4) || !aligned(vals, c.el) || !aligned(Q, c.el) ||
+      !aligned(P, c.el) || !aligned(L, 8))
+    return PBPQLP_EINVAL;
+  c.rowptr = rowptr;
+  c.colind = colind;
+  c.vals = vals;
+  c.seed = seed;
+  hipStream_t st = (hipStream_t)stream;
+  Bump sizer;
+  c.carve(sizer, false);
+  sizer.take(sizeof(pbpqlp_info));
+  const size_t need = sizer.off + 256;
+  ScratchGuard g;
+  char* base;
+  size_t avail;
+  if (opts && opts->workspace) {
+    base = (char*)opts->workspace;
+    avail = opts->workspace_bytes;
+    if (avail < need) return PBPQLP_ENOMEM;
+  } else {
+    s = alloc_scratch(g, need, st);
+    if (s) return s;
+    base = (char*)g.p;
+    avail = need;
+  }
+  Bump b;
+  b.base = (char*)(((uintptr_t)base + 255) & ~(uintptr_t)255);
+  c.carve(b, false);
+  pbpqlp_info* own = (pbpqlp_info*)b.take(sizeof(pbpqlp_info));
+  if ((size_t)(b.base + b.off - base) > avail) return PBPQLP_ENOMEM;
+  return run_factor(c, nullptr, Q, ldq, L, ldl, P, ldp, d_info ? d_info : own, st);
+}
 
 pbpqlp_status pbpqlp_workspace_size_host(int64_t m, int64_t n, int64_t lda, int k, int p,
                                          pbpqlp_dtype dt, int64_t panel_rows,

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libpbpqlp.so")
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, 1, 2, 3, 4
 F64, F32 = 0, 1
 PREC = {"native": 0, "bf16": 1, "fp16": 2, "bf16x3": 3}
-FLAG_DEPENDENT, FLAG_NONFINITE, FLAG_INTERNAL = 1, 2, 4
+FLAG_DEPENDENT, FLAG_NONFINITE, FLAG_INTERNAL, FLAG_BADINPUT = 1, 2, 4, 8
 
 # named precision plans: (sketch pass, power-iteration passes, projection pass)
 PLANS = {
@@ -117,6 +117,12 @@ def _lib():
                                          vp, i64, ctypes.POINTER(Opts), ctypes.POINTER(RRStruct), vp, vp]
         lib.pbpqlp_factor_noalloc.restype = i32
         lib.pbpqlp_factor_noalloc.argtypes = lib.pbpqlp_factor.argtypes
+        lib.pbpqlp_workspace_size_csr.restype = i32
+        lib.pbpqlp_workspace_size_csr.argtypes = [i64, i64, i64, i32, i32, i32, ctypes.POINTER(Opts),
+                                                  ctypes.POINTER(ctypes.c_size_t)]
+        lib.pbpqlp_factor_csr.restype = i32
+        lib.pbpqlp_factor_csr.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, i32, i32, u64, vp, i64, dp,
+                                          i64, vp, i64, ctypes.POINTER(Opts), vp, vp]
         lib.pbpqlp_workspace_size_host.restype = i32
         lib.pbpqlp_workspace_size_host.argtypes = [i64, i64, i64, i32, i32, i32, i64, ctypes.POINTER(Opts),
                                                    ctypes.POINTER(ctypes.c_size_t)]
@@ -415,6 +421,36 @@ def factor_host(A: torch.Tensor, k: int, p: int, q: int, seed: int, plan="native
                                          l, ctypes.c_void_p(L.data_ptr()), l, ctypes.c_void_p(P.data_ptr()),
                                          l, ctypes.byref(o), ctypes.c_void_p(info.data_ptr()), _stream(dev)),
                "pbpqlp_factor_host")
+    return Q, L, P, Info.from_device(info)
+
+
+def factor_csr(rowptr: torch.Tensor, colind: torch.Tensor, vals: torch.Tensor, shape, k: int, p: int, q: int,
+               seed: int):
+    """pbpqlp_factor_csr: A (m x n) in CSR on the device (rowptr int64 m + 1,
+    colind int32, vals float32/float64).  Returns (Q, L, P, info) with
+    A ~= Q @ L.T @ P.T."""
+    m, n = shape
+    for t, name in ((rowptr, "rowptr"), (colind, "colind"), (vals, "vals")):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous device tensor")
+    if rowptr.dtype != torch.int64 or colind.dtype != torch.int32 or rowptr.numel() != m + 1:
+        raise ValueError("rowptr must be int64 of length m + 1 and colind int32")
+    nnz = vals.numel()
+    if colind.numel() != nnz:
+        raise ValueError("colind and vals must have the same length")
+    l = k + p
+    dev = vals.device
+    Q = torch.empty((m, l), dtype=vals.dtype, device=dev)
+    P = torch.empty((n, l), dtype=vals.dtype, device=dev)
+    L = torch.empty((l, l), dtype=torch.float64, device=dev)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=dev)
+    o = make_opts("native")
+    _check(_lib().pbpqlp_factor_csr(ctypes.c_void_p(rowptr.data_ptr()), ctypes.c_void_p(colind.data_ptr()),
+                                    ctypes.c_void_p(vals.data_ptr()), m, n, nnz, _dt(vals), k, p, q,
+                                    ctypes.c_uint64(seed), ctypes.c_void_p(Q.data_ptr()), l,
+                                    ctypes.c_void_p(L.data_ptr()), l, ctypes.c_void_p(P.data_ptr()), l,
+                                    ctypes.byref(o), ctypes.c_void_p(info.data_ptr()), _stream(dev)),
+           "pbpqlp_factor_csr")
     return Q, L, P, Info.from_device(info)
 
 

@@ -23,7 +23,7 @@ __all__ = [
     "rng_for", "seed_a", "seed_omega", "haar_panel", "planted", "Workload",
     "config1", "config2", "config3", "config4_shapes", "config4_matrix",
     "lowrank_plus_noise", "paper_matrix1", "paper_matrix3", "paper_matrix4",
-    "spectrum_family", "gaussian",
+    "spectrum_family", "gaussian", "sparse_lowrank",
 ]
 
 
@@ -225,3 +225,45 @@ def spectrum_family(rng: np.random.Generator, length: int, family: Optional[str]
     else:
         raise ValueError(family)
     return family, sigma
+
+
+def sparse_lowrank(m: int, n: int, r: int, density: float, noise_nnz_per_row: float, seed: int,
+                   decay: float = 0.9, col_alpha: float = 0.0, dtype=np.float64):
+    """Sparse A = sum_k sigma_k u_k v_k^T + sparse noise, in CSR (scipy).
+
+    u_k (m) and v_k (n) are sparse Gaussian vectors with about density * m and
+    density * n nonzeros, scaled to unit norm, sigma_k = decay^k; the noise has
+    about noise_nnz_per_row entries per row with N(0, 1e-3) values.  With
+    col_alpha > 0 the column indices of both parts are drawn with probability
+    proportional to (j + 1)^-col_alpha (a power-law column degree
+    distribution: a few nearly dense columns, many short ones).  Returns
+    (A_csr, sigma)."""
+    import scipy.sparse as sp
+    rng = rng_for(seed)
+    if col_alpha > 0:
+        w = (np.arange(n, dtype=np.float64) + 1.0) ** -col_alpha
+        col_p = w / w.sum()
+    else:
+        col_p = None
+    sigma = decay ** np.arange(r, dtype=np.float64)
+    A = sp.csr_matrix((m, n), dtype=np.float64)
+    for k in range(r):
+        ku = max(1, int(round(density * m)))
+        kv = max(1, int(round(density * n)))
+        iu = rng.choice(m, size=ku, replace=False)
+        iv = rng.choice(n, size=kv, replace=False, p=col_p)
+        u = rng.standard_normal(ku)
+        v = rng.standard_normal(kv)
+        u /= np.linalg.norm(u)
+        v /= np.linalg.norm(v)
+        A = A + sp.csr_matrix((sigma[k] * np.outer(u, v).ravel(),
+                               (np.repeat(iu, kv), np.tile(iv, ku))), shape=(m, n))
+    nz = int(round(noise_nnz_per_row * m))
+    if nz > 0:
+        ri = rng.integers(0, m, size=nz)
+        ci = rng.choice(n, size=nz, p=col_p) if col_p is not None else rng.integers(0, n, size=nz)
+        A = A + sp.csr_matrix((1e-3 * rng.standard_normal(nz), (ri, ci)), shape=(m, n))
+    A = sp.csr_matrix(A, dtype=dtype)
+    A.sum_duplicates()
+    A.sort_indices()
+    return A, sigma

@@ -36,9 +36,10 @@ def test_version_and_status_strings():
 def test_status_flags_match_header():
     text = open(HEADER).read()
     flags = dict((k, int(v)) for k, v in re.findall(r"#define PBPQLP_FLAG_([A-Z]+)\s+(\d+)", text))
-    assert flags == {"DEPENDENT": B.FLAG_DEPENDENT, "NONFINITE": B.FLAG_NONFINITE, "INTERNAL": B.FLAG_INTERNAL}
+    assert flags == {"DEPENDENT": B.FLAG_DEPENDENT, "NONFINITE": B.FLAG_NONFINITE, "INTERNAL": B.FLAG_INTERNAL,
+                     "BADINPUT": B.FLAG_BADINPUT}
     # distinct single bits
-    assert sorted(flags.values()) == [1, 2, 4]
+    assert sorted(flags.values()) == [1, 2, 4, 8]
 
 
 def test_info_struct_layout():
@@ -263,3 +264,27 @@ def test_factor_host_argument_errors():
     # two staging panels of 4096 (one panel) or 1024 rows of 1024 FP32 values
     assert one - four >= 2 * (4096 - 1024) * 1024 * 4 - (1 << 20)
     assert B.workspace_size_host(4096, 1024, 40, 8, panel_rows=1000) == four   # rounded up to 1024
+
+
+def test_factor_csr_argument_errors():
+    """pbpqlp_factor_csr rejects null arrays, nnz < 0, short leading
+    dimensions and reduced-precision plans before touching the device."""
+    lib = B.library()
+
+    def call(rowptr=0x1000, colind=0x2000, vals=0x3000, m=100, n=80, nnz=500, k=5, p=3, ldq=8, opts=None):
+        return lib.pbpqlp_factor_csr(ctypes.c_void_p(rowptr), ctypes.c_void_p(colind), ctypes.c_void_p(vals), m, n,
+                                     nnz, B.F32, k, p, 1, ctypes.c_uint64(1), ctypes.c_void_p(0x4000), ldq,
+                                     ctypes.c_void_p(0x5000), 8, ctypes.c_void_p(0x6000), 8, opts, None, None)
+
+    assert call(rowptr=0) == B.EINVAL
+    assert call(colind=0) == B.EINVAL
+    assert call(nnz=-1) == B.EINVAL
+    assert call(ldq=7) == B.EINVAL
+    assert call(rowptr=0x1004) == B.EINVAL
+    o = B.make_opts("mixed")
+    assert call(opts=ctypes.byref(o)) == B.EUNSUPPORTED
+    sz = ctypes.c_size_t(0)
+    oo = B.make_opts("native")
+    assert lib.pbpqlp_workspace_size_csr(4000, 3000, 10 ** 6, 40, 8, B.F32, ctypes.byref(oo), ctypes.byref(sz)) == 0
+    # the CSR of A^T (indices and values) and its counters are part of the workspace
+    assert sz.value >= 10 ** 6 * 8
