@@ -253,7 +253,7 @@ pbpqlp_status pbpqlp_factor_host(const void* A_host, int64_t m, int64_t n, int64
  *   vals   : nnz values of dtype dt.  All three are read only.
  * The sketch and power passes and the projection are row-gather products with
  * A's CSR (A X) and with the CSR of A^T (A^T X), which the call builds first
- * by a stable counting sort (each row of A^T in increasing row order of A), so
+ * by a stable radix sort (each row of A^T in increasing row order of A), so
  * every output entry is summed in one fixed order: results are deterministic.
  * The orthonormalization stack (Grams, Cholesky, apply, the l x l QR) is the
  * dense path's; the outputs are those of pbpqlp_factor on the dense A up to
@@ -262,8 +262,8 @@ pbpqlp_status pbpqlp_factor_host(const void* A_host, int64_t m, int64_t n, int64
  * EUNSUPPORTED otherwise.  Invalid structure (row pointers out of order or
  * range, column indices outside [0, n)) is not read out of bounds: such
  * entries are skipped and PBPQLP_FLAG_BADINPUT is set in d_info.
- * Errors: as pbpqlp_factor; EINVAL for nnz < 0, m or n above 2^31 - 1, null
- * or misaligned arrays. */
+ * Errors: as pbpqlp_factor; EINVAL for nnz < 0, nnz, m or n of 2^31 - 1 or
+ * more, null or misaligned arrays. */
 pbpqlp_status pbpqlp_workspace_size_csr(int64_t m, int64_t n, int64_t nnz, int k, int p, pbpqlp_dtype dt,
                                         const pbpqlp_opts* opts, size_t* bytes);
 pbpqlp_status pbpqlp_factor_csr(const int64_t* rowptr, const int32_t* colind, const void* vals, int64_t m,

@@ -103,11 +103,13 @@ hipError_t launch_zero_dep_rows(double* R, int64_t ldr, int rows, int64_t cols, 
 hipError_t launch_cast_f32(const double* in, float* out, int64_t count, hipStream_t s);
 
 // ---- sparse A (CSR) ----
-// CSR of A^T (ptr_t n + 1, idx_t / vals_t nnz) by a stable counting sort over nb
-// row blocks (cnt: nb x n ints, colcnt: n); bad[0] |= 1 for invalid input
+// CSR of A^T (ptr_t n + 1, idx_t / vals_t nnz) by a stable radix sort of the
+// column indices; scratch of csr_transpose_scratch_bytes; *bad |= FLAG_BADINPUT
+// for invalid structure
+size_t csr_transpose_scratch_bytes(int64_t nnz, int64_t n);
 hipError_t launch_csr_transpose(bool f64, const int64_t* rowptr, const int32_t* colind, const void* vals,
-                                int64_t m, int64_t n, int64_t nnz, int nb, int* cnt, int64_t* colcnt,
-                                int64_t* ptr_t, int32_t* idx_t, void* vals_t, int* bad, hipStream_t s);
+                                int64_t m, int64_t n, int64_t nnz, void* scratch, int64_t* ptr_t,
+                                int32_t* idx_t, void* vals_t, int* bad, hipStream_t s);
 // part[b] = sum of squares of values slice b (nparts slices)
 hipError_t launch_sumsq(bool f64, const void* vals, int64_t nnz, int nparts, double* part, hipStream_t s);
 // out (column-major, ldo, padding 0) = M X[:, c0:c0+w] for CSR M (rows x cols)

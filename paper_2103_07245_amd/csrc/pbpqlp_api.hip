@@ -212,13 +212,11 @@ struct Ctx {
   const int32_t* colind = nullptr;
   const void* vals = nullptr;
   int64_t nnz = 0;
-  int nbT = 1;            // row blocks of the stable transpose
   int nsq = 1;            // ||A||_F^2 partials
   int64_t* ptr_t = nullptr;
   int32_t* idx_t = nullptr;
   void* vals_t = nullptr;
-  int* tcnt = nullptr;
-  int64_t* colcnt = nullptr;
+  void* tscratch = nullptr;  // the stable sort of the transpose
   void* Xrm = nullptr;    // row-major copy of the l-column operand (lp32 wide)
   void* Yrm = nullptr;    // row-major product of one 256-column slice
   void* spart = nullptr;  // partial rows of the nonzero-balanced product
@@ -343,8 +341,7 @@ struct Ctx {
       ptr_t = (int64_t*)b.take((size_t)(n + 1) * sizeof(int64_t));
       idx_t = (int32_t*)b.take((size_t)nnz * sizeof(int32_t));
       vals_t = b.take((size_t)nnz * el);
-      tcnt = (int*)b.take((size_t)nbT * n * sizeof(int));
-      colcnt = (int64_t*)b.take((size_t)n * sizeof(int64_t));
+      tscratch = b.take(csr_transpose_scratch_bytes(nnz, n));
       Xrm = b.take((size_t)(m > n ? m : n) * lp32 * el);
       Yrm = b.take((size_t)(m > n ? m : n) * ldyr() * el);
       spart = b.take((size_t)2 * (spmm_chunks(nnz) > 0 ? spmm_chunks(nnz) : 1) * ldyr() * el);
@@ -773,10 +770,10 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   if (c.sparse) {
     // CSR of A^T (stable), ||A||_F^2 from the values, zero padding of the
     // row-major operand copy
-    TraceScope ts("csr_transpose", (double)c.nnz * 2 * (c.el + 4) + (double)c.nbT * c.n * 8, 0.0, st);
+    TraceScope ts("csr_transpose", (double)c.nnz * (2 * (c.el + 4) + 40) + (double)c.n * 12, 0.0, st);
     PBQ_CHECK(launch_fill_zero(c.Xrm, (size_t)(c.m > c.n ? c.m : c.n) * c.lp32 * c.el, st));
-    PBQ_CHECK(launch_csr_transpose(c.f64, c.rowptr, c.colind, c.vals, c.m, c.n, c.nnz, c.nbT, c.tcnt, c.colcnt,
-                                   c.ptr_t, c.idx_t, c.vals_t, &info->status_flags, st));
+    PBQ_CHECK(launch_csr_transpose(c.f64, c.rowptr, c.colind, c.vals, c.m, c.n, c.nnz, c.tscratch, c.ptr_t,
+                                   c.idx_t, c.vals_t, &info->status_flags, st));
     PBQ_CHECK(launch_sumsq(c.f64, c.vals, c.nnz, c.nsq, c.normA, st));
   }
   // S0: sketch matrix, column-major (lp32 x ldnM): generated, or the caller's
@@ -1099,17 +1096,13 @@ pbpqlp_status host_setup(Ctx& c, int64_t m, int64_t n, int64_t lda, pbpqlp_dtype
 
 pbpqlp_status csr_setup(Ctx& c, int64_t m, int64_t n, int64_t nnz, pbpqlp_dtype dt, int k, int p, int q,
                         const pbpqlp_opts* opts) {
-  if (nnz < 0 || m > INT32_MAX || n > INT32_MAX) return PBPQLP_EINVAL;
+  if (nnz < 0 || nnz >= INT32_MAX || m >= INT32_MAX || n >= INT32_MAX) return PBPQLP_EINVAL;
   pbpqlp_status s = setup(c, m, n, n, dt, k, p, q, opts, false, false);
   if (s) return s;
   const int native = c.f64 ? M_F64 : M_F32;
   if (c.mode_sketch != native || c.mode_power != native || c.mode_proj != native) return PBPQLP_EUNSUPPORTED;
   c.sparse = true;
   c.nnz = nnz;
-  // row blocks of the transpose: their column counters take at most 256 MiB
-  int64_t nb = (int64_t)(256ull << 20) / ((int64_t)n * 4);
-  nb = nb < 1 ? 1 : (nb > 256 ? 256 : nb);
-  c.nbT = (int)(nb < m ? nb : m);
   const int64_t ns = (nnz + 4095) / 4096;
   c.nsq = (int)(ns < 1 ? 1 : (ns > 256 ? 256 : ns));
   c.plan_buffers(true, q > 0, true);

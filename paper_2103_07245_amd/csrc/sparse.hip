@@ -2,8 +2,8 @@
 // O(z d) for z nonzeros).  A is given in CSR (row pointers int64, column
 // indices int32, values FP32/FP64).  Both products of the method become
 // row-gather products Y = M X for a CSR matrix M: M = A for A X, and M = the
-// CSR of A^T for A^T X, built once per factorization by a stable counting
-// sort of the column indices (entries of each row of A^T in increasing row
+// CSR of A^T for A^T X, built once per factorization by a stable radix sort
+// of the column indices (entries of each row of A^T in increasing row
 // order of A), so every output entry is a sum in one fixed order and results
 // are deterministic.  The orthonormalization stack is the dense path's.
 #include "common.h"
@@ -15,158 +15,379 @@ namespace pbq {
 
 constexpr int64_t kSpmmChunk = 256;   // nonzeros per wave of the balanced product
 
-// Bounds of row i's entries, clamped to [0, nnz] and ordered.
-__device__ __forceinline__ void row_range(const int64_t* rowptr, int64_t i, int64_t nnz, int64_t& e0,
-                                          int64_t& e1) {
-  e0 = rowptr[i];
-  e1 = rowptr[i + 1];
-  e0 = e0 < 0 ? 0 : (e0 > nnz ? nnz : e0);
-  e1 = e1 < e0 ? e0 : (e1 > nnz ? nnz : e1);
+// ---------------------------------------------------------------------------
+// CSR of A^T by a stable LSD radix sort of the column indices (8 bits per
+// pass) carrying each entry's position: entries keep A's order (increasing
+// row) within each column.  An entry whose column index lies outside [0, n)
+// gets key n, sorts after every valid one and is left out of A^T; such
+// indices and row pointers out of order or range raise PBPQLP_FLAG_BADINPUT.
+// One pass over tiles of 4096 entries:
+//   histogram  per tile and digit (digit-major table H[d T + t]);
+//   scan       exclusive prefix of H: where tile t's digit-d entries start;
+//   scatter    16 rounds of 256 entries in order; each entry's rank among the
+//              round's equal digits comes from eight ballots (its wave) and
+//              per-wave counts in LDS (earlier waves), plus the tile's running
+//              count of the digit from earlier rounds.
+// ---------------------------------------------------------------------------
+constexpr int kRsTile = 4096;
+
+struct NarrowP {
+  const int64_t* in;
+  int32_t* out;
+  int64_t n;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void narrow_kernel(const NarrowP* pb, NarrowP ps) {
+  bool past;
+  const NarrowP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p.n) p.out[i] = (int32_t)p.in[i];
 }
 
-// ---------------------------------------------------------------------------
-// Stable transpose of the structure, step 1: row block b (rows [b R, b R + R))
-// counts its entries per column into cnt[b n + j]; column indices outside
-// [0, n) and row pointers out of order are flagged (PBPQLP_FLAG_BADINPUT into *bad) and such
-// entries are skipped everywhere.
-// ---------------------------------------------------------------------------
-struct CsrCountP {
-  const int64_t* rowptr;
+hipError_t launch_narrow(const int64_t* in, int32_t* out, int64_t n, hipStream_t s) {
+  NarrowP p{in, out, n};
+  return launch_k(narrow_kernel<false>, narrow_kernel<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, p);
+}
+
+struct KeyInitP {
   const int32_t* colind;
-  int64_t m, n, nnz, R;
-  int* cnt;
+  int64_t nnz, n;
+  int32_t* key;
+  int32_t* perm;
   int* bad;
   PBQ_GRID;
 };
 
 template <bool B>
-__global__ __launch_bounds__(256) void csr_count_kernel(const CsrCountP* pb, CsrCountP ps) {
+__global__ void key_init_kernel(const KeyInitP* pb, KeyInitP ps) {
   bool past;
-  const CsrCountP p = kparams<B>(pb, ps, past);
+  const KeyInitP p = kparams<B>(pb, ps, past);
   if (past) return;
-  const int64_t b = blockIdx.x;
-  const int64_t r0 = b * p.R, r1 = r0 + p.R < p.m ? r0 + p.R : p.m;
-  int* cnt = p.cnt + b * p.n;
-  for (int64_t i = r0; i < r1; ++i) {
-    const int64_t a0 = p.rowptr[i], a1 = p.rowptr[i + 1];
-    if (threadIdx.x == 0 && (a0 < 0 || a1 < a0 || a1 > p.nnz)) atomicOr(p.bad, PBPQLP_FLAG_BADINPUT);
-    int64_t e0, e1;
-    row_range(p.rowptr, i, p.nnz, e0, e1);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const int j = p.colind[e];
-      if (j < 0 || j >= p.n) {
-        atomicOr(p.bad, PBPQLP_FLAG_BADINPUT);
-        continue;
-      }
-      atomicAdd(&cnt[j], 1);
-    }
-  }
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= p.nnz) return;
+  const int j = p.colind[e];
+  const bool ok = j >= 0 && j < p.n;
+  if (!ok) atomicOr(p.bad, PBPQLP_FLAG_BADINPUT);
+  p.key[e] = ok ? j : (int32_t)p.n;
+  p.perm[e] = (int32_t)e;
 }
 
-// Step 2: per column j, the entries of the row blocks before b
-// (cnt[b n + j] becomes that exclusive prefix) and the column's total.
-struct ColPrefixP {
-  int* cnt;
-  int64_t n;
-  int nb;
-  int64_t* colcnt;
+struct RowCheckP {
+  const int64_t* rowptr;
+  int64_t m, nnz;
+  int* bad;
   PBQ_GRID;
 };
 
 template <bool B>
-__global__ void col_prefix_kernel(const ColPrefixP* pb, ColPrefixP ps) {
+__global__ void rowptr_check_kernel(const RowCheckP* pb, RowCheckP ps) {
   bool past;
-  const ColPrefixP p = kparams<B>(pb, ps, past);
+  const RowCheckP p = kparams<B>(pb, ps, past);
   if (past) return;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= p.n) return;
-  int64_t s = 0;
-  for (int b = 0; b < p.nb; ++b) {
-    const int t = p.cnt[(int64_t)b * p.n + j];
-    p.cnt[(int64_t)b * p.n + j] = (int)s;
-    s += t;
-  }
-  p.colcnt[j] = s;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > p.m) return;
+  const int64_t v = p.rowptr[i];
+  bool badv = v < 0 || v > p.nnz || (i == 0 && v != 0) || (i == p.m && v != p.nnz);
+  if (i < p.m && p.rowptr[i + 1] < v) badv = true;
+  if (badv) atomicOr(p.bad, PBPQLP_FLAG_BADINPUT);
 }
 
-// Step 3: ptr[0] = 0, ptr[j + 1] = ptr[j] + cnt[j] (one workgroup, 1024
-// entries per round with a running carry).
-struct ScanP {
-  const int64_t* cnt;
-  int64_t n;
-  int64_t* ptr;
+struct RsP {
+  const int32_t* kin;
+  const int32_t* pin;
+  int32_t* kout;
+  int32_t* pout;
+  int64_t nnz, T;
+  int shift;
+  int* H;   // 256 x T: counts, then (after the scan) start positions
   PBQ_GRID;
 };
 
 template <bool B>
-__global__ __launch_bounds__(1024) void scan_kernel(const ScanP* pb, ScanP ps) {
+__global__ __launch_bounds__(256) void rs_hist_kernel(const RsP* pb, RsP ps) {
   bool past;
-  const ScanP p = kparams<B>(pb, ps, past);
+  const RsP p = kparams<B>(pb, ps, past);
   if (past) return;
-  __shared__ int64_t s[1024];
-  __shared__ int64_t carry;
-  const int t = threadIdx.x;
-  if (t == 0) {
-    carry = 0;
-    p.ptr[0] = 0;
+  __shared__ int h[256];
+  const int tid = threadIdx.x;
+  h[tid] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsTile / 256; ++r) {
+    const int64_t e = base + r * 256 + tid;
+    if (e < p.nnz) atomicAdd(&h[(p.kin[e] >> p.shift) & 255], 1);
   }
   __syncthreads();
-  for (int64_t base = 0; base < p.n; base += 1024) {
-    const int64_t j = base + t;
-    s[t] = j < p.n ? p.cnt[j] : 0;
+  p.H[(int64_t)tid * p.T + blockIdx.x] = h[tid];
+}
+
+template <bool B>
+__global__ __launch_bounds__(256) void rs_scatter_kernel(const RsP* pb, RsP ps) {
+  bool past;
+  const RsP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  __shared__ int run[256];
+  __shared__ int wc[4][256];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  run[tid] = p.H[(int64_t)tid * p.T + blockIdx.x];   // start of this tile's digit-tid entries
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kRsTile;
+  for (int r = 0; r < kRsTile / 256; ++r) {
+    wc[0][tid] = 0;
+    wc[1][tid] = 0;
+    wc[2][tid] = 0;
+    wc[3][tid] = 0;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {   // inclusive Hillis-Steele scan
-      const int64_t v = t >= off ? s[t - off] : 0;
-      __syncthreads();
-      s[t] += v;
-      __syncthreads();
+    const int64_t e = base + r * 256 + tid;
+    const bool valid = e < p.nnz;
+    int key = 0, d = 0;
+    int32_t pv = 0;
+    if (valid) {
+      key = p.kin[e];
+      pv = p.pin[e];
+      d = (key >> p.shift) & 255;
     }
-    if (j < p.n) p.ptr[j + 1] = carry + s[t];
+    uint64_t mask = __builtin_amdgcn_ballot_w64(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1;
+      const uint64_t bb = __builtin_amdgcn_ballot_w64(on);
+      mask &= on ? bb : ~bb;
+    }
+    const int rank = __popcll(mask & below);
+    if (valid && rank == 0) wc[wave][d] = __popcll(mask);
     __syncthreads();
-    if (t == 1023) carry += s[1023];
+    if (valid) {
+      int off = run[d] + rank;
+      for (int w = 0; w < wave; ++w) off += wc[w][d];
+      p.kout[off] = key;
+      p.pout[off] = pv;
+    }
     __syncthreads();
+    run[tid] += wc[0][tid] + wc[1][tid] + wc[2][tid] + wc[3][tid];
   }
 }
 
-// Step 4: row block b places its entries row by row (rows in order, a
-// barrier between rows), entry (i, j) at ptr[j] + (entries of column j in
-// earlier rows): the CSR of A^T with each row's entries in increasing order of
-// i.  Within one row every column appears once, so the slot counters see at
-// most one increment per column between barriers.
-struct PlaceP {
+// Exclusive scan of n int32 counts into int64 (out[0 .. n], out[n] = total),
+// 4096 per block: local scan, block totals scanned by a recursive call,
+// offsets added.
+struct ScanLP {
+  const int32_t* in;
+  const int64_t* in64;
+  int64_t n;
+  int64_t* out;
+  int64_t* bsum;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ __launch_bounds__(1024) void scan_local_kernel(const ScanLP* pb, ScanLP ps) {
+  bool past;
+  const ScanLP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  __shared__ int64_t s[1024];
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * 4096 + (int64_t)t * 4;
+  int64_t v[4], acc = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + k;
+    v[k] = i < p.n ? (p.in ? (int64_t)p.in[i] : p.in64[i]) : 0;
+    acc += v[k];
+  }
+  s[t] = acc;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t x = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += x;
+    __syncthreads();
+  }
+  int64_t run = s[t] - acc;   // exclusive prefix of this thread's four
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t i = base + k;
+    if (i < p.n) p.out[i] = run;
+    run += v[k];
+  }
+  if (t == 1023) p.bsum[blockIdx.x] = s[1023];
+}
+
+struct ScanAddP {
+  int64_t* out;
+  int64_t n;
+  const int64_t* boff;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void scan_add_kernel(const ScanAddP* pb, ScanAddP ps) {
+  bool past;
+  const ScanAddP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < p.n) p.out[i] += p.boff[i / 4096];
+}
+
+struct TotalP {
+  int64_t* out;
+  int64_t n;
+  const int64_t* boff;
+  const int64_t* bsum;
+  int64_t nb;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void scan_total_kernel(const TotalP* pb, TotalP ps) {
+  bool past;
+  const TotalP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  if (threadIdx.x == 0) p.out[p.n] = p.boff[p.nb - 1] + p.bsum[p.nb - 1];
+}
+
+// scratch for a scan of n elements: its block totals and their own scan, recursively
+size_t scan_scratch_elems(int64_t n) {
+  const int64_t nb = (n + 4095) / 4096;
+  return nb <= 1 ? 2 : (size_t)(2 * nb + 1) + scan_scratch_elems(nb);
+}
+
+hipError_t launch_scan(const int32_t* in, const int64_t* in64, int64_t n, int64_t* out, int64_t* scratch,
+                       hipStream_t s) {
+  const int64_t nb = (n + 4095) / 4096 > 0 ? (n + 4095) / 4096 : 1;
+  int64_t* bsum = scratch;
+  int64_t* boff = scratch + nb;
+  ScanLP lp{in, in64, n, out, bsum};
+  hipError_t e = launch_k(scan_local_kernel<false>, scan_local_kernel<true>, dim3((unsigned)nb), dim3(1024), s, lp);
+  if (e != hipSuccess) return e;
+  if (nb > 1) {
+    e = launch_scan(nullptr, bsum, nb, boff, scratch + 2 * nb + 1, s);
+    if (e != hipSuccess) return e;
+    ScanAddP ap{out, n, boff};
+    e = launch_k(scan_add_kernel<false>, scan_add_kernel<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, ap);
+    if (e != hipSuccess) return e;
+  } else {
+    e = launch_fill_zero(boff, sizeof(int64_t), s);
+    if (e != hipSuccess) return e;
+  }
+  TotalP tp{out, n, boff, bsum, nb};
+  return launch_k(scan_total_kernel<false>, scan_total_kernel<true>, dim3(1), dim3(64), s, tp);
+}
+
+// Column counts of the valid entries (from the sorted keys: the last entry of
+// each run of equal keys knows its count) and the entries of A^T.
+struct FinishP {
+  const int32_t* key;   // sorted
+  const int32_t* perm;
   const int64_t* rowptr;
-  const int32_t* colind;
   const void* vals;
-  int64_t m, n, nnz, R;
-  const int64_t* ptr;
-  int* cnt;
+  int64_t m, n, nnz;
+  int32_t* colcnt;
   int32_t* idx_t;
   void* vals_t;
   PBQ_GRID;
 };
 
 template <typename T, bool B>
-__global__ __launch_bounds__(256) void csr_place_kernel(const PlaceP* pb, PlaceP ps) {
+__global__ void csr_finish_kernel(const FinishP* pb, FinishP ps) {
   bool past;
-  const PlaceP p = kparams<B>(pb, ps, past);
+  const FinishP p = kparams<B>(pb, ps, past);
   if (past) return;
-  const int64_t b = blockIdx.x;
-  const int64_t r0 = b * p.R, r1 = r0 + p.R < p.m ? r0 + p.R : p.m;
-  int* cnt = p.cnt + b * p.n;
-  const T* vals = (const T*)p.vals;
-  T* vt = (T*)p.vals_t;
-  for (int64_t i = r0; i < r1; ++i) {
-    int64_t e0, e1;
-    row_range(p.rowptr, i, p.nnz, e0, e1);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-      const int j = p.colind[e];
-      if (j < 0 || j >= p.n) continue;
-      const int64_t pos = p.ptr[j] + atomicAdd(&cnt[j], 1);
-      p.idx_t[pos] = (int32_t)i;
-      vt[pos] = vals[e];
-    }
-    __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.nnz) return;
+  const int k = p.key[i];
+  if (k >= p.n) return;   // invalid entries sort last and are left out
+  const int64_t e = p.perm[i];
+  // row of entry e: the last r with rowptr[r] <= e
+  int64_t lo = 0, hi = p.m - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (p.rowptr[mid] <= e) lo = mid; else hi = mid - 1;
   }
+  p.idx_t[i] = (int32_t)lo;
+  ((T*)p.vals_t)[i] = ((const T*)p.vals)[e];
+  if (i + 1 == p.nnz || p.key[i + 1] != k) {
+    // the run of key k ends here; it started after the previous key's run
+    int64_t a = 0, b = i;
+    while (a < b) {   // first index with key == k (sorted keys)
+      const int64_t mid = (a + b) >> 1;
+      if (p.key[mid] < k) a = mid + 1; else b = mid;
+    }
+    p.colcnt[k] = (int32_t)(i + 1 - a);
+  }
+}
+
+size_t csr_transpose_scratch_bytes(int64_t nnz, int64_t n) {
+  const int64_t T = (nnz + kRsTile - 1) / kRsTile > 0 ? (nnz + kRsTile - 1) / kRsTile : 1;
+  size_t b = 0;
+  auto take = [&](size_t x) { b += (x + 255) / 256 * 256; };
+  take(4 * (size_t)nnz * sizeof(int32_t));         // keys and positions, two of each
+  take((size_t)256 * T * sizeof(int32_t));          // H
+  take(((size_t)256 * T + 1) * sizeof(int64_t));    // its scan
+  take((size_t)n * sizeof(int32_t));                // column counts
+  const int64_t big = 256 * T > n ? 256 * T : n;
+  take(scan_scratch_elems(big) * sizeof(int64_t));
+  return b + 256;
+}
+
+hipError_t launch_csr_transpose(bool f64, const int64_t* rowptr, const int32_t* colind, const void* vals,
+                                int64_t m, int64_t n, int64_t nnz, void* scratch, int64_t* ptr_t,
+                                int32_t* idx_t, void* vals_t, int* bad, hipStream_t s) {
+  const int64_t T = (nnz + kRsTile - 1) / kRsTile > 0 ? (nnz + kRsTile - 1) / kRsTile : 1;
+  char* sp = (char*)(((uintptr_t)scratch + 255) & ~(uintptr_t)255);
+  auto take = [&](size_t x) { char* r = sp; sp += (x + 255) / 256 * 256; return (void*)r; };
+  int32_t* ka = (int32_t*)take((size_t)nnz * 4);
+  int32_t* kb = (int32_t*)take((size_t)nnz * 4);
+  int32_t* pa = (int32_t*)take((size_t)nnz * 4);
+  int32_t* pbm = (int32_t*)take((size_t)nnz * 4);
+  int32_t* H = (int32_t*)take((size_t)256 * T * 4);
+  int64_t* Hs = (int64_t*)take(((size_t)256 * T + 1) * 8);
+  int32_t* colcnt = (int32_t*)take((size_t)n * 4);
+  int64_t* ss = (int64_t*)sp;
+  hipError_t e;
+  {
+    RowCheckP rc{rowptr, m, nnz, bad};
+    e = launch_k(rowptr_check_kernel<false>, rowptr_check_kernel<true>, dim3((unsigned)((m + 1 + 255) / 256)),
+                 dim3(256), s, rc);
+    if (e != hipSuccess) return e;
+  }
+  if (nnz > 0) {
+    KeyInitP kp{colind, nnz, n, ka, pa, bad};
+    e = launch_k(key_init_kernel<false>, key_init_kernel<true>, dim3((unsigned)((nnz + 255) / 256)), dim3(256), s, kp);
+    if (e != hipSuccess) return e;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) <= n) ++bits;   // keys lie in [0, n]
+    int32_t *kin = ka, *kout = kb, *pin = pa, *pout = pbm;
+    for (int shift = 0; shift < bits; shift += 8) {
+      RsP rp{kin, pin, kout, pout, nnz, T, shift, H};
+      e = launch_k(rs_hist_kernel<false>, rs_hist_kernel<true>, dim3((unsigned)T), dim3(256), s, rp);
+      if (e != hipSuccess) return e;
+      e = launch_scan(H, nullptr, 256 * T, Hs, ss, s);
+      if (e != hipSuccess) return e;
+      // start positions back into H (they fit in int32: nnz < 2^31)
+      e = launch_narrow(Hs, H, 256 * T, s);
+      if (e != hipSuccess) return e;
+      e = launch_k(rs_scatter_kernel<false>, rs_scatter_kernel<true>, dim3((unsigned)T), dim3(256), s, rp);
+      if (e != hipSuccess) return e;
+      int32_t* t1 = kin; kin = kout; kout = t1;
+      int32_t* t2 = pin; pin = pout; pout = t2;
+    }
+    e = launch_fill_zero(colcnt, (size_t)n * 4, s);
+    if (e != hipSuccess) return e;
+    FinishP fp{kin, pin, rowptr, vals, m, n, nnz, colcnt, idx_t, vals_t};
+    e = f64 ? launch_k(csr_finish_kernel<double, false>, csr_finish_kernel<double, true>,
+                       dim3((unsigned)((nnz + 255) / 256)), dim3(256), s, fp)
+            : launch_k(csr_finish_kernel<float, false>, csr_finish_kernel<float, true>,
+                       dim3((unsigned)((nnz + 255) / 256)), dim3(256), s, fp);
+    if (e != hipSuccess) return e;
+  } else {
+    e = launch_fill_zero(colcnt, (size_t)n * 4, s);
+    if (e != hipSuccess) return e;
+  }
+  return launch_scan(colcnt, nullptr, n, ptr_t, ss, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,26 +578,6 @@ __global__ __launch_bounds__(256) void spmm_fix_kernel(const SpmmP* pb, SpmmP ps
     const int c = lane + 64 * q;
     if (c < p.w) Y[c] = s[q];
   }
-}
-
-hipError_t launch_csr_transpose(bool f64, const int64_t* rowptr, const int32_t* colind, const void* vals,
-                                int64_t m, int64_t n, int64_t nnz, int nb, int* cnt, int64_t* colcnt,
-                                int64_t* ptr_t, int32_t* idx_t, void* vals_t, int* bad, hipStream_t s) {
-  const int64_t R = (m + nb - 1) / nb;
-  hipError_t e = launch_fill_zero(cnt, (size_t)nb * n * sizeof(int), s);
-  if (e != hipSuccess) return e;
-  CsrCountP cp{rowptr, colind, m, n, nnz, R, cnt, bad};
-  e = launch_k(csr_count_kernel<false>, csr_count_kernel<true>, dim3((unsigned)nb), dim3(256), s, cp);
-  if (e != hipSuccess) return e;
-  ColPrefixP pp{cnt, n, nb, colcnt};
-  e = launch_k(col_prefix_kernel<false>, col_prefix_kernel<true>, dim3((unsigned)((n + 255) / 256)), dim3(256), s, pp);
-  if (e != hipSuccess) return e;
-  ScanP sp{colcnt, n, ptr_t};
-  e = launch_k(scan_kernel<false>, scan_kernel<true>, dim3(1), dim3(1024), s, sp);
-  if (e != hipSuccess) return e;
-  PlaceP lp{rowptr, colind, vals, m, n, nnz, R, ptr_t, cnt, idx_t, vals_t};
-  if (f64) return launch_k(csr_place_kernel<double, false>, csr_place_kernel<double, true>, dim3((unsigned)nb), dim3(256), s, lp);
-  return launch_k(csr_place_kernel<float, false>, csr_place_kernel<float, true>, dim3((unsigned)nb), dim3(256), s, lp);
 }
 
 hipError_t launch_sumsq(bool f64, const void* vals, int64_t nnz, int nparts, double* part, hipStream_t s) {
