@@ -1,6 +1,6 @@
 // A-streaming products of PbP-QLP on gfx950 matrix cores.
 //
-// These are the passes that dominate the method's cost (Section IV-F: the
+// These are the passes that dominate the method's cost (Section IV-E: the
 // cost is dominated by the multiplications of A and A^T with d-column
 // matrices; 2q+2 of them):
 //   K1  Y = A X      (eq. (c) for A^T, i.e. the sketch, and the A-side power step)
