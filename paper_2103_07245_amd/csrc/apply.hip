@@ -124,8 +124,32 @@ struct ApplyP {
   void* Qrm;
   int64_t ldqr;
   int64_t wq;     // rows of Qcm written (padding rows up to ldq, or only len for a sub-matrix)
+  const int* ident;  // set by the Cholesky of a later sweep whose factor is the identity: copy
+  // optional 16-bit copy of Qcm (x xs) for the next A-streaming pass (same
+  // layout, ld ldq): BF16 or FP16 in hi, and for split-BF16x3 the low BF16
+  // part of x xs - hi in lo; emode 0 = none
+  void* hi;
+  void* lo;
+  int emode;
+  float xs;
   PBQ_GRID;
 };
+
+// The 16-bit copies of one stored value (the conversion of a separate pass,
+// done where the value is produced).
+template <typename T>
+__device__ __forceinline__ void store16(const ApplyP& p, int64_t off, T y) {
+  if constexpr (sizeof(T) == 4) {
+    const float v = (float)y * p.xs;
+    if (p.emode == M_F16) {
+      ((_Float16*)p.hi)[off] = (_Float16)v;
+    } else {
+      const __bf16 h = (__bf16)v;
+      ((__bf16*)p.hi)[off] = h;
+      if (p.emode == M_BF16X3) ((__bf16*)p.lo)[off] = (__bf16)(v - (float)h);
+    }
+  }
+}
 
 template <typename T, int NT, bool B>
 __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps) {
@@ -152,13 +176,17 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
       y[K][r] = in ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
-  apply_phase<T, NT, MAXT, 0>(y, ops, Ra, Dinv, lp, tid, li, lg);
+  // the identity factor of a later sweep leaves Y as it is (block-uniform test)
+  if (!(prm.ident && *prm.ident)) apply_phase<T, NT, MAXT, 0>(y, ops, Ra, Dinv, lp, tid, li, lg);
 #pragma unroll
   for (int J = 0; J < NT; ++J)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int c = 16 * J + acc_row<T>(lg, r);
-      if (Qcm && arow < prm.wq) Qcm[(int64_t)c * ldq + arow] = y[J][r];
+      if (Qcm && arow < prm.wq) {
+        Qcm[(int64_t)c * ldq + arow] = y[J][r];
+        if (prm.emode) store16<T>(prm, (int64_t)c * ldq + arow, y[J][r]);
+      }
       if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[J][r];
     }
 }
@@ -249,7 +277,8 @@ __global__ __launch_bounds__(256) void apply_cols_kernel(const ApplyP* pb, Apply
     for (int r = 0; r < 4; ++r)
       y[sl][r] = (in && K < NT) ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
   }
-  apply_cols_phase<T, NT, MAXT, 0>(y, ops, qb, (const T*)prm.Ra, (const T*)prm.Dinv, lp, tid, wave, li, lg);
+  if (!(prm.ident && *prm.ident))
+    apply_cols_phase<T, NT, MAXT, 0>(y, ops, qb, (const T*)prm.Ra, (const T*)prm.Dinv, lp, tid, wave, li, lg);
 #pragma unroll
   for (int sl = 0; sl < NS; ++sl) {
     const int K = wave + 4 * sl;
@@ -257,7 +286,10 @@ __global__ __launch_bounds__(256) void apply_cols_kernel(const ApplyP* pb, Apply
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int c = 16 * K + acc_row<T>(lg, r);
-        if (Qcm && arow < prm.wq) Qcm[(int64_t)c * ldq + arow] = y[sl][r];
+        if (Qcm && arow < prm.wq) {
+          Qcm[(int64_t)c * ldq + arow] = y[sl][r];
+          if (prm.emode) store16<T>(prm, (int64_t)c * ldq + arow, y[sl][r]);
+        }
         if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[sl][r];
       }
     }
@@ -346,14 +378,15 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const RightMulP* pb, Rig
 template <typename T, int NT>
 static hipError_t apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, int l, const void* Ra,
                                const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
-                               void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq) {
+                               void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq, const int* ident,
+                               const Emit16& em) {
   CompleteP c{(void*)Y, ldy, len, l, lp, dep, seed};
   hipError_t e = launch_k(complete_kernel<T, false>, complete_kernel<T, true>, dim3((unsigned)((len + 255) / 256)),
                           dim3(256), s, c);
   if (e != hipSuccess) return e;
   if (wq < 0) wq = ldq;
   const int64_t rows = Qcm ? (wq > len ? wq : len) : len;
-  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr, wq};
+  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr, wq, ident, em.hi, em.lo, em.mode, em.xs};
   if constexpr (sizeof(T) == 8) {
     if (rows <= 256)  // the FP64 l x l stages: four waves per row panel
       return launch_k(apply_cols_kernel<T, NT, false>, apply_cols_kernel<T, NT, true>,
@@ -377,13 +410,16 @@ static hipError_t right_mul_launch(const void* In, int64_t ldi, int64_t len, int
 
 hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
                         const void* Ra, const void* Dinv, const int* dep, uint64_t seed, void* Qcm,
-                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq) {
+                        int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq, const int* ident,
+                        const Emit16& em) {
   if (lp % 16 || lp < 16 || lp > kMaxL) return hipErrorInvalidValue;
   switch (lp / 16) {
 #define PBQ_CASE(N)                                                                                             \
   case N:                                                                                                       \
-    return f64 ? apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s, wq)   \
-               : apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s, wq);
+    return f64 ? apply_launch<double, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s, wq,   \
+                                         ident, em)                                                           \
+               : apply_launch<float, N>(Y, ldy, len, lp, l, Ra, Dinv, dep, seed, Qcm, ldq, Qrm, ldqr, s, wq, ident, \
+                                        em);
     PBQ_TILES(PBQ_CASE)
 #undef PBQ_CASE
   }

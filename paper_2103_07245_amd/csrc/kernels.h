@@ -45,20 +45,34 @@ hipError_t launch_splitk_reduce(bool f64, const void* part, int64_t stride, int 
 // `target`: workgroups to aim at (contraction splits x block pairs)
 int gram_splits(int64_t len, int lp, int target);
 size_t gram_partial_elems(int64_t len, int lp, int target);
+// far (optional): per (row, 64-column block) flags of |G_ij - delta_ij| > tol
+// for i, j < l, the identity test of a later sweep (gram_far_cols(lp) per row)
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
-                       double* G, int64_t ldg, int target, hipStream_t s);
+                       double* G, int64_t ldg, int target, hipStream_t s, int* far = nullptr, int l = 0,
+                       double tol = 0.0);
+inline int gram_far_cols(int lp) { return (lp + 63) / 64; }
 // Cholesky of the Gram with dependent-column detection (single workgroup,
 // lp <= 256); gdiag (optional): the diagonal the dependence test measures
 // against, when G is a trailing block already updated by earlier panels
+// ident (optional, later sweeps): when G is the identity to ident_tol the
+// factor is the identity and *ident = 1 (the sweep's apply then copies)
 hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
-                       hipStream_t s, const double* gdiag = nullptr);
+                       hipStream_t s, const double* gdiag = nullptr, int* ident = nullptr,
+                       const int* far = nullptr);
 // Q = Y Ra^-1 by blocked substitution (column-major in/out), optional row-major copy;
 // Qcm rows [0, wq) are written (wq < 0: ldq, the padding rows zeroed)
+// 16-bit copies of an apply's output for the next pass (mode 0: none)
+struct Emit16 {
+  void* hi = nullptr;
+  void* lo = nullptr;
+  int mode = 0;
+  float xs = 1.0f;
+};
 hipError_t launch_apply(bool f64, const void* Y, int64_t ldy, int64_t len, int lp, int l,
                         const void* Ra, const void* Dinv, const int* dep, uint64_t seed,
                         void* Qcm, int64_t ldq, void* Qrm, int64_t ldqr, hipStream_t s,
-                        int64_t wq = -1);
+                        int64_t wq = -1, const int* ident = nullptr, const Emit16& em = Emit16());
 // Out = In M with M dense l x l given row-major (Mr[k*ldm + j] = M[k][j])
 hipError_t launch_right_mul(bool f64, const void* In, int64_t ldi, int64_t len, int lp, int l,
                             const void* Mr, int64_t ldm, void* Ocm, int64_t ldo, void* Orm,
@@ -72,9 +86,10 @@ hipError_t launch_rm_to_cm(bool f64, const void* X, int64_t ldx, int64_t len, in
 hipError_t launch_cm_to_rm(bool f64, const void* Xt, int64_t ldt, int64_t len, int l, void* X,
                            int64_t ldx, hipStream_t s);
 // small FP64 products: C = op(A) op(B) (lp x lp), optional transposed store
+// ident (optional): when *ident is set, A is the identity and C = op(B) is copied
 hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, int ta,
                              const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
-                             hipStream_t s);
+                             hipStream_t s, const int* ident = nullptr);
 // write L = U^T (lower) from upper U, zero elsewhere; rowsq[i] = sum_j L[i][j]^2 (or null)
 hipError_t launch_write_lower_t(const double* U, int64_t ldu, int l, double* L, int64_t ldl,
                                 double* rowsq, hipStream_t s);

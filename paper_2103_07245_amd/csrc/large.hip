@@ -237,7 +237,7 @@ __global__ void zero_dep_rows_kernel(const DepRowsP* pb, DepRowsP ps) {
   if (p.dep[p.rows] == 0) return;   // count of dependent columns of this block
   const int i = blockIdx.y;
   if (!p.dep[i]) return;
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p.cols; j += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < p.cols; j += (int64_t)p.gx * blockDim.x)
     p.R[(int64_t)i * p.ldr + j] = 0.0;
 }
 
@@ -260,7 +260,7 @@ __global__ void cast_f32_kernel(const CastP* pb, CastP ps) {
   bool past;
   const CastP p = kparams<B>(pb, ps, past);
   if (past) return;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.count; i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.count; i += (int64_t)p.gx * blockDim.x)
     p.out[i] = (float)p.in[i];
 }
 

@@ -155,6 +155,12 @@ const char* mode_name(int mode) {
   return "?";
 }
 
+// Power-of-two lift of an FP16 operand: unit-norm columns have entries of
+// about len^-1/2, lifted to about 1 (exact, undone on the product).
+float fp16_lift(bool unit_columns, int64_t xlen) {
+  return unit_columns ? std::ldexp(1.0f, (int)std::floor(0.5 * std::log2((double)xlen))) : 1.0f;
+}
+
 // Everything one factorization needs, carved from one workspace block.
 struct Ctx {
   // problem: A is m x n (lda) as stored.  The method runs on M = A, or on
@@ -184,6 +190,13 @@ struct Ctx {
          *Rfin = nullptr, *M1 = nullptr, *Qt64 = nullptr, *U = nullptr;
   void *Ra = nullptr, *Dinv = nullptr, *Ra64 = nullptr, *Dinv64 = nullptr, *Qt32 = nullptr;
   int* dep = nullptr;
+  int* ident = nullptr;   // a later sweep's factor was the identity (device flag)
+  int* far = nullptr;     // the Gram reduction's identity-test flags (lp x gram_far_cols)
+  // which operand the 16-bit buffers Xhi/Xlo hold (written by a conversion, or
+  // by the last apply of an orth() for the pass that follows it)
+  const void* conv_X = nullptr;
+  int conv_mode = 0;
+  float conv_xs = 1.0f;
   double* rowsq = nullptr;
   uint64_t ncall = 0;
   // optional outputs: R of the projection's QR (row-major, ldr_out) and the
@@ -332,6 +345,8 @@ struct Ctx {
     Dinv64 = b.take(ndv * 8);
     dep = (int*)b.take(ndep * sizeof(int));
     rowsq = (double*)b.take((size_t)lp * sizeof(double));
+    ident = (int*)b.take(sizeof(int));
+    far = (int*)b.take((size_t)lp * gram_far_cols(lp) * sizeof(int));
     gdiag = wide ? (double*)b.take((size_t)lp * sizeof(double)) : nullptr;
     if (panel_rows > 0) {
       stage[0] = b.take((size_t)panel_rows * lda * el);
@@ -550,12 +565,17 @@ pbpqlp_status stream_pass(Ctx& c, bool trans, int mode, const void* A, const voi
     float xs = 1.0f;
     if (mode == M_F16) {
       a.a_scale = c.fp16_scale;
-      // unit-norm columns have entries ~ len^-1/2: lift them to ~1 (exact power of two)
-      if (unit_columns) xs = std::ldexp(1.0f, (int)std::floor(0.5 * std::log2((double)xlen)));
+      xs = fp16_lift(unit_columns, xlen);
       a.out_scale = 1.0f / (a.a_scale * xs);
     }
-    TraceScope ts("convert", (double)xlen * c.l * (4.0 + (mode == M_BF16X3 ? 4.0 : 2.0)), 0.0, st);
-    PBQ_CHECK(launch_convert(mode, (const float*)X, ldx, xlen, c.l, c.lp32, xs, c.Xhi, c.Xlo, st));
+    // the 16-bit copy may already be there: the orth() that produced X wrote it
+    if (!(c.conv_X == X && c.conv_mode == mode && c.conv_xs == xs)) {
+      TraceScope ts("convert", (double)xlen * c.l * (4.0 + (mode == M_BF16X3 ? 4.0 : 2.0)), 0.0, st);
+      PBQ_CHECK(launch_convert(mode, (const float*)X, ldx, xlen, c.l, c.lp32, xs, c.Xhi, c.Xlo, st));
+      c.conv_X = X;
+      c.conv_mode = mode;
+      c.conv_xs = xs;
+    }
     a.X = c.Xhi;
     a.Xlo = c.Xlo;
   } else {
@@ -652,7 +672,8 @@ pbpqlp_status chol_wide(Ctx& c, bool f64, double eps, double* Rt, void* info, hi
 // with block J's apply form (dependent columns completed as in the narrow
 // path).  dst may be written in place of the block being solved.
 pbpqlp_status apply_wide(Ctx& c, bool f64, const void* src, int64_t ld, int64_t len, const double* Rt,
-                         uint64_t cseed, void* dst, void* rm, int64_t ldrm, hipStream_t st) {
+                         uint64_t cseed, void* dst, void* rm, int64_t ldrm, hipStream_t st,
+                         const Emit16& em = Emit16()) {
   const int lp = c.lp, l = c.l, nb = c.nbw();
   const size_t el = f64 ? 8 : c.el;
   for (int J = 0; J < nb; ++J) {
@@ -668,15 +689,21 @@ pbpqlp_status apply_wide(Ctx& c, bool f64, const void* src, int64_t ld, int64_t 
       srcJ = dstJ;
     }
     TraceScope ts("apply", 2.0 * len * bJ * el, (double)len * bJ * bJ, st);
+    Emit16 ej = em;
+    if (ej.mode) {
+      ej.hi = (char*)em.hi + (size_t)j0 * ld * 2;
+      ej.lo = (char*)em.lo + (size_t)j0 * ld * 2;
+    }
     PBQ_CHECK(launch_apply(f64, srcJ, ld, len, bJ, lJ, c.ra_blk(f64, J), c.dinv_blk(f64, J), c.dep_blk(J),
-                           cseed + (uint64_t)J, dstJ, ld, rm ? (char*)rm + (size_t)j0 * el : nullptr, ldrm, st));
+                           cseed + (uint64_t)J, dstJ, ld, rm ? (char*)rm + (size_t)j0 * el : nullptr, ldrm, st,
+                           -1, nullptr, ej));
   }
   return PBPQLP_OK;
 }
 
 pbpqlp_status orth_wide(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes, void* out,
                         void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm, void* info,
-                        hipStream_t st, bool small) {
+                        hipStream_t st, bool small, const Emit16& em) {
   const double eps = dep_eps(f64, c.l, len);
   const void* src = X;
   for (int ps = 0; ps < passes; ++ps) {
@@ -691,7 +718,7 @@ pbpqlp_status orth_wide(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len
     }
     pbpqlp_status s = chol_wide(c, f64, eps, Rt, info, st);
     if (s) return s;
-    s = apply_wide(c, f64, src, ld, len, Rt, cseed, dst, last ? rm : nullptr, ldrm, st);
+    s = apply_wide(c, f64, src, ld, len, Rt, cseed, dst, last ? rm : nullptr, ldrm, st, last ? em : Emit16());
     if (s) return s;
     src = dst;
   }
@@ -712,8 +739,23 @@ pbpqlp_status orth_wide(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len
 // accumulated triangular factor when non-null.
 pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int passes,
                    void* out, void* tmp, double* Rkeep, int64_t ldrk, void* rm, int64_t ldrm,
-                   void* info, hipStream_t st, bool small = false) {
-  if (c.wide) return orth_wide(c, f64, X, ld, len, passes, out, tmp, Rkeep, ldrk, rm, ldrm, info, st, small);
+                   void* info, hipStream_t st, bool small = false, int next_mode = M_F32) {
+  // the last apply also writes the 16-bit copy the next pass multiplies with
+  Emit16 em;
+  if (!f64 && next_mode >= M_BF16) {
+    em.hi = c.Xhi;
+    em.lo = c.Xlo;
+    em.mode = next_mode;
+    em.xs = next_mode == M_F16 ? fp16_lift(true, len) : 1.0f;
+  }
+  if (em.mode) {
+    c.conv_X = out;
+    c.conv_mode = em.mode;
+    c.conv_xs = em.xs;
+  } else if (c.conv_X == out) {
+    c.conv_X = nullptr;   // out is rewritten without its 16-bit copy
+  }
+  if (c.wide) return orth_wide(c, f64, X, ld, len, passes, out, tmp, Rkeep, ldrk, rm, ldrm, info, st, small, em);
   const double eps = dep_eps(f64, c.l, len);
   void* Ra = f64 ? c.Ra64 : c.Ra;
   void* Dv = f64 ? c.Dinv64 : c.Dinv;
@@ -724,18 +766,25 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     double* Rt = ps == 0 ? c.R1 : c.R2;
     const uint64_t cseed = c.seed ^ (0x9E3779B97F4A7C15ull * (++c.ncall));
     const double el = f64 ? 8.0 : (double)c.el;
+    // a later sweep whose input is already orthonormal to the rounding of its
+    // storage takes the identity factor, decided on the device: the Gram
+    // reduction flags entries off the identity, the Cholesky reads the flags,
+    // the sweep's apply and R2 R1 become copies
+    int* idf = ps > 0 ? c.ident : nullptr;
+    int* farf = ps > 0 ? c.far : nullptr;
+    const double itol = f64 ? 2e-14 : 2.0 * 5.9604644775390625e-08;
     {
       TraceScope ts(small ? "gram_ll" : "gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
-      PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, c.gram_target, st));
+      PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, c.gram_target, st, farf, c.l, itol));
     }
     {
       TraceScope ts(small ? "chol_ll" : "chol", (double)c.l * c.l * 8 * 2, (double)c.l * c.l * c.l / 3.0, st);
-      PBQ_CHECK(launch_chol(f64, c.G, c.lp, c.l, c.lp, eps, Rt, c.lp, Ra, Dv, c.dep, info, st));
+      PBQ_CHECK(launch_chol(f64, c.G, c.lp, c.l, c.lp, eps, Rt, c.lp, Ra, Dv, c.dep, info, st, nullptr, idf, farf));
     }
     {
       TraceScope ts(small ? "apply_ll" : "apply", 2.0 * len * c.l * el, (double)len * c.l * c.l, st);
       PBQ_CHECK(launch_apply(f64, src, ld, len, c.lp, c.l, Ra, Dv, c.dep, cseed, dst, ld,
-                             last ? rm : nullptr, ldrm, st));
+                             last ? rm : nullptr, ldrm, st, -1, idf, last ? em : Emit16()));
     }
     src = dst;
   }
@@ -744,7 +793,7 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     if (passes == 1)
       PBQ_CHECK(launch_copy_mat(c.R1, c.lp, c.lp, c.lp, Rkeep, ldrk, 1, st));
     else
-      PBQ_CHECK(launch_small_gemm(c.lp, c.lp, c.lp, c.R2, c.lp, 0, c.R1, c.lp, 0, Rkeep, ldrk, 0, st));
+      PBQ_CHECK(launch_small_gemm(c.lp, c.lp, c.lp, c.R2, c.lp, 0, c.R1, c.lp, 0, Rkeep, ldrk, 0, st, c.ident));
   }
   return PBPQLP_OK;
 }
@@ -790,17 +839,19 @@ pbpqlp_status run_factor(Ctx& c, const void* A, void* Q, int64_t ldq, double* L,
   s = stream_pass(c, tM, c.mode_sketch, A, c.Om, ldnM, nM, c.omega_in != nullptr, c.Y, ldmM,
                   tM ? nullptr : c.normA, st);
   if (s) return s;
-  s = orth(c, c.f64, c.Y, ldmM, mM, c.q == 0 ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
+  s = orth(c, c.f64, c.Y, ldmM, mM, c.q == 0 ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st, false,
+           c.q > 0 ? c.mode_power : c.mode_proj);
   if (s) return s;
   // S3: power iterations with re-orthonormalization after each product
   for (int i = 1; i <= c.q; ++i) {
     s = stream_pass(c, tMt, c.mode_power, A, c.Qm, ldmM, mM, true, c.Zn, ldnM, nullptr, st);
     if (s) return s;
-    s = orth(c, c.f64, c.Zn, ldnM, nM, 1, c.Pn, c.W1n, nullptr, 0, nullptr, 0, info, st);
+    s = orth(c, c.f64, c.Zn, ldnM, nM, 1, c.Pn, c.W1n, nullptr, 0, nullptr, 0, info, st, false, c.mode_power);
     if (s) return s;
     s = stream_pass(c, tM, c.mode_power, A, c.Pn, ldnM, nM, true, c.Y, ldmM, nullptr, st);
     if (s) return s;
-    s = orth(c, c.f64, c.Y, ldmM, mM, i == c.q ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st);
+    s = orth(c, c.f64, c.Y, ldmM, mM, i == c.q ? 2 : 1, c.Qm, c.W1m, nullptr, 0, nullptr, 0, info, st, false,
+             i < c.q ? c.mode_power : c.mode_proj);
     if (s) return s;
   }
   // S4: projection M^T Q (+ ||A||_F^2 when this pass is A X);  S5: = P R

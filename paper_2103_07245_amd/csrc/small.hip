@@ -46,6 +46,7 @@ struct CholShared {
   double winv[16][17];           // W_J = inverse of the apply form of R_JJ
   double pnl[2][16][kMaxL + 1];  // panel rows, double buffered: raw G_J,: in, R_J,: out
   int sflag;
+  int sflag2;
 };
 
 __device__ __forceinline__ void wave_lds_fence() {
@@ -206,8 +207,33 @@ struct CholP {
   int* dep;
   pbpqlp_info* info;
   const double* gdiag;  // dependence reference diagonal, or null (G's own)
+  int* ident;           // later sweep: set to 1 when G is the identity to the Gram
+  const int* far;       // reduction's tolerance (far: its per-row flags), else 0
   PBQ_GRID;
 };
+
+// A later CholeskyQR sweep: the Gram reduction flagged, per row and 64-column
+// block, any |G_ij - delta_ij| above the tolerance (i, j < l; NaN counts).
+// With no flag the sweep's input is already orthonormal to that tolerance:
+// the factor is the identity (the sweep's apply copies, R2 R1 copies R1), no
+// column is dependent, *ident = 1 and the caller returns; else *ident = 0 and
+// the factorization proceeds.  Nothing else is written on the identity path.
+template <typename T>
+__device__ __forceinline__ bool chol_identity(const CholP& prm, int* sflag2) {
+  const int tid = threadIdx.x, l = prm.l, lp = prm.lp;
+  const int nf = l * ((lp + 63) / 64);
+  if (tid == 0) *sflag2 = 0;
+  __syncthreads();
+  bool far = false;
+  for (int e = tid; e < nf; e += kCholThreads) far = far || prm.far[e] != 0;
+  if (far) atomicOr(sflag2, 1);
+  __syncthreads();
+  const bool id = *sflag2 == 0;
+  if (id)
+    for (int e = tid; e <= lp; e += kCholThreads) prm.dep[e] = 0;
+  if (tid == 0) *prm.ident = id ? 1 : 0;
+  return id;
+}
 
 template <typename T, bool B>
 __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, CholP ps) {
@@ -232,6 +258,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, Cho
   }
   if (tid == 0) sh.sflag = 0;
   __syncthreads();
+  if (prm.ident && chol_identity<T>(prm, &sh.sflag2)) return;
   if (tid < l && !isfinite(sh.gd[tid])) atomicOr(&sh.sflag, 1);
 
   // wave w owns tile rows RA = w and RB = 15 - w: slots 0..NA-1 hold
@@ -436,6 +463,7 @@ struct CholSharedDW {
   double wall[kDwRows][16][17];   // W_J of every panel
   double pnl[2][16][kMaxL + 1];   // panel rows, double buffered: raw G_J,: in, R_J,: out
   int sflag;
+  int sflag2;
   int bcnt;                       // B tiles done: 7 per panel, one per tile wave
 };
 
@@ -475,6 +503,7 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
     sh.bcnt = 0;
   }
   __syncthreads();
+  if (prm.ident && chol_identity<T>(prm, &sh.sflag2)) return;
   if (tid < l && !isfinite(sh.gd[tid])) atomicOr(&sh.sflag, 1);
 
   // tile wave w owns rows RA = w and RB = 13 - w: slots 0..NA-1 hold
@@ -727,9 +756,10 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
 
 hipError_t launch_chol(bool f64, const double* G, int64_t ldg, int l, int lp, double eps_dep,
                        double* Rt, int64_t ldr, void* Ra, void* Dinv, int* dep, void* info,
-                       hipStream_t s, const double* gdiag) {
+                       hipStream_t s, const double* gdiag, int* ident, const int* far) {
   if (lp > kMaxL || (lp & 15)) return hipErrorInvalidValue;
-  CholP p{G, ldg, l, lp, eps_dep, Rt, ldr, Ra, Dinv, dep, (pbpqlp_info*)info, gdiag};
+  if ((ident != nullptr) != (far != nullptr)) return hipErrorInvalidValue;
+  CholP p{G, ldg, l, lp, eps_dep, Rt, ldr, Ra, Dinv, dep, (pbpqlp_info*)info, gdiag, ident, far};
   if (lp <= 16 * kDwRows) {
     if (f64) return launch_k(chol_dw_kernel<double, false>, chol_dw_kernel<double, true>, dim3(1), dim3(kCholThreads), s, p);
     return launch_k(chol_dw_kernel<float, false>, chol_dw_kernel<float, true>, dim3(1), dim3(kCholThreads), s, p);
@@ -753,6 +783,7 @@ struct GemmP {
   double* C;
   int64_t ldc;
   int tc;
+  const int* ident;
   PBQ_GRID;
 };
 
@@ -764,6 +795,13 @@ __global__ __launch_bounds__(64) void small_gemm_kernel(const GemmP* pb, GemmP p
   const int lane = threadIdx.x, li = lane & 15, lg = lane >> 4;
   const int i0 = blockIdx.y * 16, j0 = blockIdx.x * 16;
   f64x4 acc = {0, 0, 0, 0};
+  if (p.ident && *p.ident) {   // A is the identity: C = op(B)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = i0 + acc_row<double>(lg, r);
+      acc[r] = p.tb ? p.Bm[(int64_t)(j0 + li) * p.ldb + k] : p.Bm[(int64_t)k * p.ldb + j0 + li];
+    }
+  } else
   for (int k0 = 0; k0 < p.K; k0 += 16) {
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
@@ -783,9 +821,9 @@ __global__ __launch_bounds__(64) void small_gemm_kernel(const GemmP* pb, GemmP p
 
 hipError_t launch_small_gemm(int M, int N, int K, const double* A, int64_t lda, int ta,
                              const double* B, int64_t ldb, int tb, double* C, int64_t ldc, int tc,
-                             hipStream_t s) {
+                             hipStream_t s, const int* ident) {
   if ((M | N | K) & 15) return hipErrorInvalidValue;
-  GemmP p{M, N, K, A, lda, ta, B, ldb, tb, C, ldc, tc};
+  GemmP p{M, N, K, A, lda, ta, B, ldb, tb, C, ldc, tc, ident};
   return launch_k(small_gemm_kernel<false>, small_gemm_kernel<true>, dim3((unsigned)(N / 16), (unsigned)(M / 16)),
                   dim3(64), s, p);
 }

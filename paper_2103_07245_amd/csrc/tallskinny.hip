@@ -317,6 +317,11 @@ struct GramReduceP {
   int S, np, lp;
   double* G;
   int64_t ldg;
+  // optional identity test of a later CholeskyQR sweep: block (x, row i)
+  // writes far[i gx + x] = 1 when some |G_ij - delta_ij| > tol (i, j < l)
+  int* far;
+  int l;
+  double tol;
   PBQ_GRID;
 };
 
@@ -326,8 +331,8 @@ __global__ void gram_reduce_kernel(const GramReduceP* pb, GramReduceP ps) {
   const GramReduceP p = kparams<B>(pb, ps, past);
   if (past) return;
   const int i = blockIdx.y;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= p.lp) return;
+  const int j0 = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = j0 < p.lp ? j0 : p.lp - 1;   // lanes past lp compute a valid entry, write nothing
   int bi = i >> 5, bj = j >> 5, ii = i & 31, jj = j & 31;
   if (bi > bj) {
     int t = bi; bi = bj; bj = t;
@@ -346,11 +351,17 @@ __global__ void gram_reduce_kernel(const GramReduceP* pb, GramReduceP ps) {
     s3 += src[(int64_t)(sp + 3) * stride];
   }
   for (; sp < p.S; ++sp) s0 += src[(int64_t)sp * stride];
-  p.G[(int64_t)i * p.ldg + j] = (s0 + s1) + (s2 + s3);
+  const double g = (s0 + s1) + (s2 + s3);
+  if (j0 < p.lp) p.G[(int64_t)i * p.ldg + j] = g;
+  if (p.far) {
+    const bool far = j0 < p.l && i < p.l && !(fabs(g - (i == j ? 1.0 : 0.0)) <= p.tol);
+    const uint64_t bal = __builtin_amdgcn_ballot_w64(far);
+    if (threadIdx.x == 0) p.far[(int64_t)i * p.gx + blockIdx.x] = bal != 0;
+  }
 }
 
 hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp, double* part,
-                       double* G, int64_t ldg, int target, hipStream_t s) {
+                       double* G, int64_t ldg, int target, hipStream_t s, int* far, int l, double tol) {
   const int nb = (lp + 31) / 32;
   const int np = npairs_of(nb);
   const int S = gram_splits(len, lp, target);
@@ -361,7 +372,7 @@ hipError_t launch_gram(bool f64, const void* X, int64_t ld, int64_t len, int lp,
   hipError_t e = f64 ? launch_k(gram_partial_kernel<double, false>, gram_partial_kernel<double, true>, grid, dim3(256), s, p)
                      : launch_k(gram_partial_kernel<float, false>, gram_partial_kernel<float, true>, grid, dim3(256), s, p);
   if (e != hipSuccess) return e;
-  GramReduceP r{part, S, np, lp, G, ldg};
+  GramReduceP r{part, S, np, lp, G, ldg, far, l, tol};
   return launch_k(gram_reduce_kernel<false>, gram_reduce_kernel<true>, dim3((unsigned)((lp + 63) / 64), (unsigned)lp),
                   dim3(64), s, r);
 }
