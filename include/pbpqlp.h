@@ -538,7 +538,9 @@ typedef struct {
  *   sqrt(||A||^2 - ||L'||^2) / ||A|| (exact for orthonormal factors, since
  *   Q'^T A P' = L'^T); for FP32, whose estimate carries an error of order
  *   1e-3, an estimate closer to tau than its error bound (2 sqrt(m + n) FP32
- *   units on r^2) is replaced by the explicit pbpqlp_residual pass;
+ *   units on r^2) is replaced by the explicit pbpqlp_residual pass; with any
+ *   BF16 or FP16 pass in opts, whose rounding lies far above that band, every
+ *   check is the explicit pass;
  *   if it exceeds tau (or a non-finite input was flagged) the fallback
  *   continues to q = 3 (when q_hat < 3) and returns k = k_max.
  * A plain run with q iterations costs 2 q + 2 passes; this path costs

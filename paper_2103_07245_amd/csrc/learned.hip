@@ -513,8 +513,12 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
   // FP32 factors leave sqrt(||A||^2 - ||L'||^2) with an error of order 1e-3
   // (||L'||^2 carries the products' FP32 rounding), so an FP32 answer whose
   // estimate lies within that error of tau is judged by the explicit residual
-  // pass instead (one more pass over A)
+  // pass instead (one more pass over A).  With a BF16 or FP16 pass, L' carries
+  // that pass's rounding (2^-9 or 2^-12 relative, far above the FP32 band), so
+  // every answer is judged by the explicit pass.
   const bool explicit_check = dt == PBPQLP_F32;
+  auto coarse = [](int pr) { return pr == PBPQLP_PREC_BF16 || pr == PBPQLP_PREC_FP16; };
+  const bool always_explicit = coarse(o.sketch_prec) || coarse(o.power_prec) || coarse(o.proj_prec);
 
   pbpqlp_auto_result r{};
   int cur = 0, qcur = 0, flags = 0, ndep = 0;
@@ -556,8 +560,10 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
     return PBPQLP_OK;
   };
   double hL[LP * LP];
-  // residual estimate of the leading rank-lt part of the current factorization
-  auto resid = [&](int lt, double* out, double* nl2) -> pbpqlp_status {
+  // residual estimate of the leading rank-lt part of the current factorization;
+  // `fresh`: the factorization is new since the last check (its status flags
+  // and dependent-column count are added once)
+  auto resid = [&](int lt, double* out, double* nl2, bool fresh) -> pbpqlp_status {
     PBQ_TRY(hipMemcpyAsync(hL, Lb[cur], sizeof(hL), hipMemcpyDeviceToHost, st));
     PBQ_TRY(hipMemcpyAsync(&hi, dinf, sizeof(hi), hipMemcpyDeviceToHost, st));
     PBQ_TRY(hipStreamSynchronize(st));
@@ -572,8 +578,8 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
     // explicit pass decides
     const double r2 = a2 > 0.0 ? (a2 - s2) / a2 : 0.0;
     const double bound = 2.0 * std::sqrt((double)(m + n)) * 5.9604644775390625e-8;
-    const bool decided = r2 + bound <= tau * tau || r2 - bound > tau * tau;
-    if (explicit_check && !decided) {
+    const bool decided = !always_explicit && (r2 + bound <= tau * tau || r2 - bound > tau * tau);
+    if ((explicit_check || always_explicit) && !decided) {
       pbpqlp_status s3 = pbpqlp_residual(A, lda, Qb[cur], LP, Lb[cur], LP, Pb[cur], LP, m, n, lt, dt, dres,
                                          stream);
       if (s3) return s3;
@@ -581,22 +587,27 @@ pbpqlp_status pbpqlp_factor_auto(const pbpqlp_model* md, const void* A, int64_t 
       PBQ_TRY(hipStreamSynchronize(st));
       r.passes += 1;
     }
-    flags |= hi.status_flags;
-    ndep += hi.n_dependent;
+    if (fresh) {
+      flags |= hi.status_flags;
+      ndep += hi.n_dependent;
+    }
     return PBPQLP_OK;
   };
   if ((s = advance(qh))) return s;
   int kout = kh;
   double r1 = 0.0, nl2 = 0.0;
-  if ((s = resid(kh + p, &r1, &nl2))) return s;
+  if ((s = resid(kh + p, &r1, &nl2, true))) return s;
   r.resid_first = r1;
   double rf = r1;
   const bool bad = !(r1 <= tau) || (flags & PBPQLP_FLAG_NONFINITE);
   if (bad) {
     r.fell_back = 1;
+    const int qbefore = qcur;
     if ((s = advance(3))) return s;
     kout = k_max;
-    if ((s = resid(kout + p, &rf, &nl2))) return s;
+    // the wider leading part is checked again; the factorization itself is
+    // new only if the iterations continued
+    if ((s = resid(kout + p, &rf, &nl2, qcur != qbefore))) return s;
   }
   r.q_used = qcur;
   r.k_used = kout;
