@@ -169,6 +169,82 @@ def roofline_of(tab, steps, traffic_file=TRAFFIC_FILE):
             "ms_per_step": round(dom["ms_per_step"], 4)}
 
 
+# ---------------------------------------------------------------------------
+# Summaries of rocprofv3 output (run separately; see profiles/):
+#   python bench.py --summarize-counters FETCH_DIR WRITE_DIR [MFMA_DIR]
+# reads the counter-collection CSVs of rocprofv3 --pmc runs of this bench and
+# writes profiles/traffic_c2.json (HBM bytes per launch of each streaming
+# kernel, calibrated on the 1 GiB copy the runs include) and prints a
+# markdown table; MFMA_DIR (a run with SQ_INSTS_VALU_MFMA_MOPS_* counters)
+# adds the matrix-core flops each kernel executed.
+# ---------------------------------------------------------------------------
+MODE_NAMES = {0: "f64", 1: "f32", 2: "bf16", 3: "fp16", 4: "bf16x3"}
+
+
+def trace_name(kernel):
+    """Bench trace name (k1_bf16, ...) of a streaming kernel's rocprofv3 name."""
+    import re
+    m = re.search(r"stream_k1_kernel<(\d+),", kernel)
+    if m:
+        return "k1_" + MODE_NAMES[int(m.group(1))]
+    m = re.search(r"stream_kernel<(\d+), *\d+, *(true|false),", kernel)
+    if m:
+        return ("k2_" if m.group(2) == "true" else "k1_") + MODE_NAMES[int(m.group(1))]
+    if "copyBuffer" in kernel:
+        return "copy"
+    return None
+
+
+def read_counters(d):
+    """{(trace name, counter): [values per dispatch]} from rocprofv3 CSVs under d."""
+    import csv
+    import glob
+    out = {}
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    for fn in files:
+        with open(fn) as f:
+            for row in csv.DictReader(f):
+                name = trace_name(row.get("Kernel_Name", ""))
+                if name is None:
+                    continue
+                out.setdefault((name, row["Counter_Name"]), []).append(float(row["Counter_Value"]))
+    return out
+
+
+def summarize_counters(fetch_dir, write_dir, mfma_dir=None):
+    fc, wc = read_counters(fetch_dir), read_counters(write_dir)
+    copy_bytes = 2 ** 30
+    ff = copy_bytes / (1024 * max(fc[("copy", "FETCH_SIZE")]))
+    wf = copy_bytes / (1024 * max(wc[("copy", "WRITE_SIZE")]))
+    kernels = {}
+    for (name, ctr), vals in fc.items():
+        if name == "copy" or ctr != "FETCH_SIZE":
+            continue
+        wv = wc.get((name, "WRITE_SIZE"), [0.0])
+        fb = sum(vals) / len(vals) * 1024 * ff
+        wb = sum(wv) / len(wv) * 1024 * wf
+        kernels[name] = {"fetch_bytes": fb, "write_bytes": wb, "hbm_bytes_per_launch": fb + wb,
+                         "dispatches": [len(vals), len(wv)]}
+    mfma = read_counters(mfma_dir) if mfma_dir else {}
+    for (name, ctr), vals in mfma.items():
+        if name in kernels and ctr.startswith("SQ_INSTS_VALU_MFMA_MOPS"):
+            # counted in units of 512 floating-point operations
+            kernels[name].setdefault("mfma_flops_per_launch", 0.0)
+            kernels[name]["mfma_flops_per_launch"] += sum(vals) / len(vals) * 512
+    out = {"workload": "16384x16384 fp32, l=220 (C2)", "stream_gemm_sha": _sha(STREAM_SRC),
+           "method": "rocprofv3 --pmc FETCH_SIZE, then --pmc WRITE_SIZE (KiB per dispatch), each scaled by "
+                     "the factor that makes the 1 GiB device copy read/write exactly 1 GiB",
+           "calibration": {"copy_bytes": copy_bytes, "fetch_factor": ff, "write_factor": wf},
+           "kernels": kernels}
+    json.dump(out, open(TRAFFIC_FILE, "w"), indent=1)
+    print("| kernel | HBM fetch (GB) | HBM write (GB) | HBM total (GB) | matrix-core GFLOP |")
+    print("|---|---:|---:|---:|---:|")
+    for k, v in sorted(kernels.items()):
+        mf = v.get("mfma_flops_per_launch")
+        print(f"| `{k}` | {v['fetch_bytes'] / 1e9:.4f} | {v['write_bytes'] / 1e9:.4f} | "
+              f"{v['hbm_bytes_per_launch'] / 1e9:.4f} | {mf / 1e9 if mf else float('nan'):.1f} |")
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -192,7 +268,11 @@ def main():
                     help="c2/c3: also time the factorization with A in pinned host memory")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (for counter calibration)")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="FETCH_DIR WRITE_DIR [MFMA_DIR]: summarize rocprofv3 --pmc runs of this bench")
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(*args.summarize_counters)
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
