@@ -28,6 +28,11 @@ struct StreamArgs {
 hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s);
 int stream_rows_per_block(int mode);
 int stream_kc(int mode);
+// compute units of the current device (queried once per device)
+int device_cus();
+// K1 (Y = A X) workgroups along the rows of A for `rows` rows and `splits`
+// contraction splits (the ||A||^2 partials of one launch: this times splits)
+int64_t stream_k1_grid(int mode, int64_t rows, int splits);
 
 // sketch: Omega^T (column-major lp32 x ld) in FP32 or FP64; zero padding
 hipError_t launch_omega_cm(bool f64, int64_t n, int l, int lp32, uint64_t seed, void* Ot,

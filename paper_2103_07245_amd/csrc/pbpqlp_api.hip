@@ -91,14 +91,50 @@ struct Split {
   int64_t chunk;
 };
 
-// Contraction split of one streaming pass: aim at ~256 workgroups (one
-// eight-wave block per CU), keep at least 4 stages of 64 per split.
-Split plan_split(int64_t blocks, int64_t klen, int forced) {
-  int64_t S = forced > 0 ? forced : (256 + blocks - 1) / blocks;
-  const int64_t maxS = klen / 256 > 0 ? klen / 256 : 1;
-  if (S > maxS) S = maxS;
-  if (S > 64) S = 64;
-  if (S < 1) S = 1;
+// Cost terms of one streaming pass, for plan_split.
+struct PassCost {
+  double a_bytes = 0, flops = 0, out_bytes = 0, peak = 1;
+  bool k1_even = false;   // K1 in a 16-bit mode: evens a ragged last round out without a split
+};
+
+// Contraction split of one streaming pass over `blocks` A-side workgroups
+// (one eight-wave block per CU at a time).  Among the splits that keep at
+// least 4 stages of 64 per split (and 64 at most), the one of least estimated
+// time: the pass's work (its A bytes over the HBM rate the kernels reach, or
+// its flops over the matrix-core peak, whichever bounds it) spread over the
+// ceil(T / CUs) rounds of T = blocks S workgroups, a partly busy round
+// running at the rate its CUs reach (HBM-bound passes saturate at ~90% of
+// the CUs, matrix-core bound ones scale with them), plus the S partial
+// results written and read back by the reduction and its launch.
+Split plan_split(int64_t blocks, int64_t klen, int forced, const PassCost& pc = PassCost()) {
+  const int64_t maxS = std::min<int64_t>(64, std::max<int64_t>(1, klen / 256));
+  int64_t S = 1;
+  if (forced > 0) {
+    S = std::min<int64_t>(forced, maxS);
+  } else {
+    constexpr double kBw = 6.2e12;
+    const double cus = (double)device_cus();
+    const double tm = pc.a_bytes / kBw, tc = pc.flops / pc.peak;
+    const bool mem = tm >= tc;
+    const double base = mem ? tm : tc;
+    auto rate = [&](double nb) { return std::min(1.0, mem ? nb / (0.9 * cus) : nb / cus); };
+    double best = 0.0;
+    for (int64_t s = 1; s <= maxS; ++s) {
+      const double T = (double)blocks * (double)s;
+      double t;
+      if (s == 1 && pc.k1_even && T > cus) {
+        t = base;
+      } else {
+        const double full = std::floor(T / cus), rest = T - full * cus;
+        t = full * (cus / T) * base / rate(cus) + (rest > 0 ? (rest / T) * base / rate(rest) : 0.0);
+      }
+      if (s > 1) t += 2.0 * (double)s * pc.out_bytes / kBw + 4e-6;
+      if (s == 1 || t < best) {
+        best = t;
+        S = s;
+      }
+    }
+  }
   int64_t chunk = rup((klen + S - 1) / S, 64);
   S = (klen + chunk - 1) / chunk;
   if (S < 1) S = 1;
@@ -256,12 +292,20 @@ struct Ctx {
     const int64_t rb = stream_rows_per_block(mode);
     const int64_t mr = panel_rows > 0 ? panel_rows : m;   // rows one launch sees
     const int64_t len = trans ? n : mr, klen = trans ? mr : n;
-    Split sp = plan_split((len + rb - 1) / rb, klen, forced_split);
+    // one launch covers at most kMaxL columns of the operand
+    const double w = (double)std::min(lp, kMaxL);
+    PassCost pc;
+    pc.a_bytes = (double)len * (double)klen * el;
+    pc.flops = 2.0 * (double)len * (double)klen * w * (mode == M_BF16X3 ? 3.0 : 1.0);
+    pc.out_bytes = (double)len * w * el;
+    pc.peak = mode == M_F64 ? 78.6e12 : mode == M_F32 ? 157.3e12 : 2.5e15;
+    pc.k1_even = !trans && (mode == M_BF16 || mode == M_F16);
+    Split sp = plan_split((len + rb - 1) / rb, klen, forced_split, pc);
     // the A^T X panels of a host-resident A keep every split partial until the
     // last panel: at most 64 partials in all
     if (panel_rows > 0 && trans && (int64_t)sp.S * npanels > 64) {
       const int S = (int)(64 / npanels) > 0 ? (int)(64 / npanels) : 1;
-      sp = plan_split((len + rb - 1) / rb, klen, S);
+      sp = plan_split((len + rb - 1) / rb, klen, S, pc);
     }
     return sp;
   }
@@ -295,15 +339,14 @@ struct Ctx {
     }
     if (proj) need(mode_proj, !tv);
     const int nmode = tv ? mode_proj : mode_sketch;
-    const int64_t rb = stream_rows_per_block(nmode);
-    if (panel_rows > 0) {
-      // every panel holds a whole number of row blocks but the last
-      k1_blocks = (int)(((panel_rows + rb - 1) / rb) * (npanels - 1) +
-                        ((m - panel_rows * (npanels - 1)) + rb - 1) / rb);
-    } else {
-      k1_blocks = (int)((m + rb - 1) / rb);
-    }
     k1_splits = split_for(nmode, false).S;
+    if (panel_rows > 0) {
+      // every panel but the last holds panel_rows rows
+      k1_blocks = (int)(stream_k1_grid(nmode, panel_rows, k1_splits) * (npanels - 1) +
+                        stream_k1_grid(nmode, m - panel_rows * (npanels - 1), k1_splits));
+    } else {
+      k1_blocks = (int)stream_k1_grid(nmode, m, k1_splits);
+    }
   }
 
   void carve(Bump& b, bool need16) {
@@ -510,7 +553,7 @@ pbpqlp_status host_pass(Ctx& c, bool trans, int mode, StreamArgs a, int64_t xlen
     }
     if (trans) slot += ps.S;
     PBQ_CHECK(hipEventRecord(c.ev_used[b], st));
-    nblk += (rows + rb - 1) / rb;
+    nblk += stream_k1_grid(mode, rows, ps.S);
   }
   if (trans) {
     for (int j0 = 0; j0 < c.lp32; j0 += kMaxL) {

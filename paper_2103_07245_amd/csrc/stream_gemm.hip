@@ -28,6 +28,9 @@
 // Modes: F64 (v_mfma_f64_16x16x4), F32 (v_mfma_f32_16x16x4), BF16 / FP16
 // (v_mfma_f32_16x16x32_{bf16,f16}, FP32 accumulate; A converted in
 // registers), BF16X3 (hi*hi + hi*lo + lo*hi of bfloat16 splits).
+#include <atomic>
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
@@ -153,6 +156,26 @@ __device__ __forceinline__ void store_rows(T* out, int64_t ld, int64_t col, int6
   }
 }
 
+// Rows of A that K1 block blockIdx.x (of gx) multiplies: the m rows are cut
+// into 16-row groups, block b takes groups [b N / gx, (b + 1) N / gx) of the
+// N = ceil(m / 16), i.e. its rows [16 g0, rend), and wave w sub-tile rt the
+// group g0 + rt NW + w (first row tile_r[rt]; groups past the block's end are
+// clamped away by the caller).  With gx >= ceil(m / (16 NW RT)) no block has
+// more than NW RT groups; a grid of more blocks than that evens the work of
+// the blocks out (every row block is within one group of the others).  Groups
+// go round the waves, so the two waves that share a SIMD (w, w + 4) hold
+// every fourth group and a block short of groups still keeps its SIMDs even.
+template <int NW, int RT>
+__device__ __forceinline__ void k1_rows(int64_t m, unsigned gx, int wave, int64_t& g0, int64_t& rend,
+                                        int64_t* tile_r) {
+  const int64_t ngr = (m + 15) >> 4;
+  g0 = (int64_t)blockIdx.x * ngr / gx;
+  const int64_t g1 = ((int64_t)blockIdx.x + 1) * ngr / gx;
+  rend = min(m, 16 * g1);
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) tile_r[rt] = 16 * (g0 + rt * NW + wave);
+}
+
 // Kernel arguments (by value).
 struct StreamParams {
   const void* A;
@@ -215,14 +238,17 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
   // K2 needs RT columns for its paired loads; a narrower A runs masked only
   const int nfull = (TRANS && alen < RT) ? 0 : (int)((ke - kb) / KC);
 
-  // Clamped A-side indices (always valid memory); validity kept for normA.
-  int64_t arow[RT];  // K1: row of sub-tile rt
+  // K1: this block's rows [16 g0, rend) and its sub-tiles' first rows (tile_r);
+  // clamped A-side indices (always valid memory), validity kept for normA.
+  int64_t g0 = 0, rend = alen, tile_r[RT], arow[RT];
   bool rowok[RT];
+  if constexpr (!TRANS) k1_rows<NW, RT>(p.m, p.gx, wave, g0, rend, tile_r);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    const int64_t r = a0 + 16 * rt + li;
-    rowok[rt] = r < alen;
-    arow[rt] = rowok[rt] ? r : alen - 1;
+    if constexpr (TRANS) tile_r[rt] = a0 + 16 * rt;
+    const int64_t r = tile_r[rt] + li;
+    rowok[rt] = r < rend;
+    arow[rt] = rowok[rt] ? r : rend - 1;
   }
   // K2: this lane's RT consecutive columns start at acol; its loads start at
   // acol_ld = min(acol, alen - RT) so that a pair never leaves the row, and
@@ -318,8 +344,11 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
     load_a(kb, nfull > 0);
   }
   // one stage: its X and A come from the registers, which then take the next
-  // stage; the X ring in LDS alternates between two buffers
-  auto stage = [&](int s) __attribute__((always_inline)) {
+  // stage; the X ring in LDS alternates between two buffers.  NextFull tells
+  // that stage s + 1 is full: its prefetch is then unmasked straight-line code.
+  // (A masked/unmasked choice per load inside the loop makes the compiler wait
+  // for every outstanding load before each new one.)
+  auto stage = [&](int s, auto next_full) __attribute__((always_inline)) {
     const int64_t k0 = kb + (int64_t)s * KC;
     const int buf = s & 1;
     // X(s) -> LDS
@@ -376,7 +405,10 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
         }
       }
     // prefetch stage s + 1 (its loads stay in flight across the barrier)
-    if (s + 1 < nst) {
+    if constexpr (decltype(next_full)::value) {
+      load_x(k0 + KC, true);
+      load_a(k0 + KC, true);
+    } else if (s + 1 < nst) {
       const bool full = s + 1 < nfull;
       load_x(k0 + KC, full);
       load_a(k0 + KC, full);
@@ -430,7 +462,9 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
       }
     }
   };
-  for (int s = 0; s < nst; ++s) stage(s);
+  int s = 0;
+  for (; s + 1 < nfull; ++s) stage(s, std::true_type());
+  for (; s < nst; ++s) stage(s, std::false_type());
 
   TACC* out = (TACC*)p.out + (int64_t)blockIdx.y * p.split_stride;
   const int Tst = p.lp >> 4;
@@ -440,7 +474,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void 
 #pragma unroll
       for (int ct = 0; ct < NT; ++ct)
         if (ct < Tst)
-          store_rows<TACC>(out, p.ldo, 16 * ct + li, a0 + 16 * rt, lg, p.m, acc[rt][ct], p.out_scale);
+          store_rows<TACC>(out, p.ldo, 16 * ct + li, tile_r[rt], lg, rend, acc[rt][ct], p.out_scale);
   } else {
     const int64_t j = a0 + li * RT;  // unclamped: lanes past the edge store nothing
 #pragma unroll
@@ -523,18 +557,18 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const S
   const TC* __restrict__ Xc = (const TC*)p.X;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   u32x4* const myslot = &aslot[wave * NAR * 64];
-  const int64_t a0 = ((int64_t)blockIdx.x * NW + wave) * (16 * RT);
   const int64_t kb = (int64_t)blockIdx.y * p.chunk;
   const int64_t ke = min(p.n, kb + p.chunk);
   const int nst = (int)((ke - kb + KC - 1) / KC);
   const int nfull = (int)((ke - kb) / KC);
-  int64_t arow[RT];
+  int64_t g0, rend, tile_r[RT], arow[RT];
   bool rowok[RT];
+  k1_rows<NW, RT>(p.m, p.gx, wave, g0, rend, tile_r);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
-    const int64_t r = a0 + 16 * rt + li;
-    rowok[rt] = r < p.m;
-    arow[rt] = rowok[rt] ? r : p.m - 1;
+    const int64_t r = tile_r[rt] + li;
+    rowok[rt] = r < rend;
+    arow[rt] = rowok[rt] ? r : rend - 1;
   }
   // NORM: the sketch pass also accumulates ||A||_F^2 (p.normA set)
   constexpr bool want_norm = NORM;
@@ -719,7 +753,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const S
   for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
     for (int ct = 0; ct < NT; ++ct)
-      if (ct < Tst) store_rows<TACC>(out, p.ldo, 16 * ct + li, a0 + 16 * rt, lg, p.m, acc[rt][ct], p.out_scale);
+      if (ct < Tst) store_rows<TACC>(out, p.ldo, 16 * ct + li, tile_r[rt], lg, rend, acc[rt][ct], p.out_scale);
   if (want_norm) {
     __shared__ double red[NW];
     nrm = wave_sum(nrm);
@@ -740,9 +774,9 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const S
 template <int MODE, int NT, bool TRANS>
 static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   typedef Tr<MODE> TR;
-  const int64_t len = TRANS ? a.n : a.m;
   const int span = 16 * TR::RT * TR::NW;
-  dim3 grid((unsigned)((len + span - 1) / span), (unsigned)a.splits);
+  const int64_t gx = TRANS ? (a.n + span - 1) / span : stream_k1_grid(MODE, a.m, a.splits);
+  dim3 grid((unsigned)gx, (unsigned)a.splits);
   StreamParams p;
   p.A = a.A; p.lda = a.lda; p.m = a.m; p.n = a.n;
   p.X = a.X; p.Xlo = a.Xlo; p.ldx = a.ldx; p.lp = a.lp;
@@ -806,6 +840,30 @@ int stream_rows_per_block(int mode) {
     default: return 16 * Tr<M_BF16X3>::RT * Tr<M_BF16X3>::NW;
   }
 }
+int device_cus() {
+  static std::atomic<int> cached[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  int v = cached[dev].load(std::memory_order_relaxed);
+  if (v <= 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cached[dev].store(v, std::memory_order_relaxed);
+  }
+  return v;
+}
+
+int64_t stream_k1_grid(int mode, int64_t rows, int splits) {
+  const int64_t span = stream_rows_per_block(mode);
+  const int64_t b0 = (rows + span - 1) / span;
+  const int64_t cus = device_cus();
+  // one block per CU at a time: for the HBM-bound 16-bit modes a ragged last
+  // round becomes whole rounds of smaller row blocks (the FP32 and FP64 modes
+  // are matrix-core bound, and a block's clamped sub-tiles cost them as much
+  // as full ones)
+  if (splits == 1 && b0 > cus && (mode == M_BF16 || mode == M_F16)) return (b0 + cus - 1) / cus * cus;
+  return b0;
+}
+
 int stream_kc(int mode) { return mode == M_F64 ? 16 : (mode == M_F32 ? 32 : 64); }
 
 hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s) {
