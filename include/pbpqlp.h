@@ -335,7 +335,11 @@ pbpqlp_status pbpqlp_matmul(int trans, const void* A, int64_t m, int64_t n, int6
  * row-major) = Q R with Q orthonormal (rows x l, dtype dt) and R upper
  * triangular l x l FP64 (ldr >= l, lower part written 0, diag >= 0), by
  * `passes` (1 or 2) CholeskyQR sweeps with FP64 Grams; passes = 2 gives an
- * orthonormal Q to working precision.  R may be NULL.  l <= rows, l <= 256. */
+ * orthonormal Q to working precision.  The second sweep is decided on the
+ * device: when the first sweep's Q^T Q is already within 4 u32 (FP32) or
+ * 2e-14 (FP64) of the identity in every entry, it takes the identity factor
+ * and Q and R are those of the first sweep, bit for bit.  R may be NULL.
+ * l <= rows, l <= 256. */
 pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpqlp_dtype dt,
                           int passes, void* Q, int64_t ldq, double* R, int64_t ldr,
                           pbpqlp_info* d_info, void* stream);

@@ -812,10 +812,13 @@ pbpqlp_status orth(Ctx& c, bool f64, const void* X, int64_t ld, int64_t len, int
     // a later sweep whose input is already orthonormal to the rounding of its
     // storage takes the identity factor, decided on the device: the Gram
     // reduction flags entries off the identity, the Cholesky reads the flags,
-    // the sweep's apply and R2 R1 become copies
+    // the sweep's apply and R2 R1 become copies.  FP32 data: a sweep's own
+    // FP32 substitution leaves |Q^T Q - I| at about 3 u32 for l up to 256
+    // (l-term sums), so an input within 4 u32 is as orthonormal as another
+    // sweep would make it
     int* idf = ps > 0 ? c.ident : nullptr;
     int* farf = ps > 0 ? c.far : nullptr;
-    const double itol = f64 ? 2e-14 : 2.0 * 5.9604644775390625e-08;
+    const double itol = f64 ? 2e-14 : 4.0 * 5.9604644775390625e-08;
     {
       TraceScope ts(small ? "gram_ll" : "gram", (double)len * c.l * el, (double)len * c.l * c.l, st);
       PBQ_CHECK(launch_gram(f64, src, ld, len, c.lp, c.gpart, c.G, c.lp, c.gram_target, st, farf, c.l, itol));
@@ -1556,6 +1559,8 @@ pbpqlp_status pbpqlp_orth(const void* Y, int64_t rows, int l, int64_t ldy, pbpql
     c.Ra64 = b.take((size_t)c.lp * c.lp * 8);
     c.Dinv64 = b.take((size_t)(c.lp / 16) * 256 * 8);
     c.dep = (int*)b.take((size_t)(c.lp + 1) * 4);
+    c.ident = (int*)b.take(sizeof(int));
+    c.far = (int*)b.take((size_t)c.lp * gram_far_cols(c.lp) * sizeof(int));
     void* own = b.take(sizeof(pbpqlp_info));
     if (!d_info) info = (pbpqlp_info*)own;
   };
@@ -1598,6 +1603,8 @@ pbpqlp_status pbpqlp_small_qr(const double* R, int l, int64_t ldr, double* Qt, i
     c.Ra64 = c.Ra = b.take((size_t)c.lp * c.lp * 8);
     c.Dinv64 = c.Dinv = b.take((size_t)(c.lp / 16) * 256 * 8);
     c.dep = (int*)b.take((size_t)(c.lp + 1) * 4);
+    c.ident = (int*)b.take(sizeof(int));
+    c.far = (int*)b.take((size_t)c.lp * gram_far_cols(c.lp) * sizeof(int));
     void* own = b.take(sizeof(pbpqlp_info));
     if (!d_info) info = (pbpqlp_info*)own;
   };

@@ -7,7 +7,7 @@
 //   K2  Z = A^T X    (the A^T-side power step and the projection, eq. (D))
 // A (m x n, row-major, FP32 or FP64) is read exactly once per pass and never
 // touches LDS; the l-column operand X (column-major, compute type) is staged
-// through a double-buffered LDS ring shared by the four waves and re-read from
+// through a double-buffered LDS ring shared by the block's waves and re-read from
 // L2 by every block.  Both kernels split the contraction over the grid's y
 // dimension ("split-K") so small matrices still fill 256 CUs; the partial
 // results are summed by splitk_reduce in a fixed order (deterministic).
@@ -56,7 +56,7 @@ template <> struct Tr<M_F16> {
 };
 template <> struct Tr<M_BF16X3> {
   typedef float TA; typedef __bf16 TC; typedef float TACC;
-  static constexpr int V = 8, RT = 2, XN = 2, NW = 4;
+  static constexpr int V = 8, RT = 2, XN = 2, NW = 8;
 };
 
 // Every mode moves 16 bytes of compute-type operand per lane per step
@@ -192,17 +192,19 @@ struct StreamParams {
 };
 
 // ---------------------------------------------------------------------------
-// grid (ceil(len / (16 RT NW)), S), 64 NW threads (NW waves: 8, or 4 for
-// BF16X3 whose extra operands need 512 registers per lane).  Wave w owns the
-// A-side tiles (rows for K1, columns for K2) 16 RT (NW blockIdx.x + w) .. + 16 RT.
-// Eight waves make two per SIMD (one block per CU) and share one X stage.
+// grid (ceil(len / (16 RT NW)), S), 64 NW threads (NW = 8 waves: two per
+// SIMD; BF16X3 then spills a few registers per lane, which costs less than the
+// memory latency a single wave per SIMD leaves exposed).  Wave w owns the
+// A-side tiles: for K2 the columns 16 RT (NW blockIdx.x + w) .. + 16 RT, for
+// K1 the row groups k1_rows gives it.  The eight waves (one block per CU)
+// share one X stage.
 // Full stages load A with element-aligned vector loads; only the ragged last
 // stage of a split masks its loads.  K2 with n % RT != 0 (VEC = false): the
 // lane holding the last, unpaired column loads the pair that ends there and
 // moves that column into its first slot (one select per load).
 // ---------------------------------------------------------------------------
 template <int MODE, int NT, bool TRANS, bool VEC, bool B>
-__global__ __launch_bounds__(64 * Tr<MODE>::NW, Tr<MODE>::NW == 8 ? 2 : 1) void stream_kernel(const StreamParams* pb,
+__global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const StreamParams* pb,
                                                                                        StreamParams ps) {
   bool past;
   const StreamParams p = kparams<B>(pb, ps, past);

@@ -181,6 +181,38 @@ def test_orth_dependent_columns_completed(dtype):
     assert np.abs(Qh[:, :3] - Qo[:, :3]).max() <= tol * 1e3
 
 
+@pytest.mark.parametrize("rows,l,decades,dtype", [(4096, 220, 0, torch.float32), (4096, 220, 6, torch.float32),
+                                                   (3000, 80, 0, torch.float32), (2000, 64, 0, torch.float64),
+                                                   (2000, 64, 6, torch.float64)])
+def test_orth_later_sweep_decision(rows, l, decades, dtype):
+    """A second CholeskyQR sweep whose input is already orthonormal to its
+    storage's rounding (|Q1^T Q1 - I| <= 4 u32 for FP32 data, 2e-14 for FP64)
+    takes the identity factor: two passes then return the one-pass Q and R bit
+    for bit.  Otherwise the sweep runs and improves the orthonormality."""
+    print(f"orth later sweep rows={rows} l={l} decades={decades} {dtype}", flush=True)
+    rng = synth.rng_for(rows * 7 + l + decades)
+    U = synth.haar_panel(rng, rows, l)
+    V = synth.haar_panel(rng, l, l)
+    Y = (U * np.logspace(0, -decades, l)) @ V.T
+    Yd = _dev(Y).to(dtype)
+    Q1, R1, _ = B.orth(Yd, passes=1)
+    Q2, R2, info = B.orth(Yd, passes=2)
+    q1, q2 = _host(Q1), _host(Q2)
+    e1 = np.abs(q1.T @ q1 - np.eye(l)).max()
+    e2 = np.abs(q2.T @ q2 - np.eye(l)).max()
+    tol = 2e-14 if dtype == torch.float64 else 4.0 * 2.0**-24
+    if e1 <= 0.9 * tol:
+        assert np.array_equal(q1, q2) and np.array_equal(_host(R1), _host(R2))
+    elif e1 >= 1.1 * tol:
+        assert not np.array_equal(q1, q2)
+        assert e2 < e1 and e2 <= (1e-13 if dtype == torch.float64 else 4e-7)
+    assert info.status_flags == 0
+    if decades == 0 and dtype == torch.float32:
+        # a well-conditioned FP32 input is orthonormal to the floor after one
+        # sweep: the second is skipped
+        assert e1 <= 0.9 * tol
+
+
 def test_orth_zero_matrix():
     Y = np.zeros((100, 8))
     Q, R, info = B.orth(_dev(Y), passes=2)
