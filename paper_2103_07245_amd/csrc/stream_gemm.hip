@@ -372,17 +372,19 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
         if constexpr (!TRANS) {
           g0 = an[(rt * 2 + st) * NLA];
           g1 = NLA > 1 ? an[(rt * 2 + st) * NLA + NLA - 1] : g0;
-          if (!TRANS && p.normA && rowok[rt]) {
+          if (p.normA) {
+            // rows past the edge repeat the last row: weight 0 (no lane branch)
+            const double wgt = rowok[rt] ? 1.0 : 0.0;
             if constexpr (sizeof(TA) == 8) {
               union { u32x4 v; double d[2]; } u;
               u.v = g0;
-              nrm += u.d[0] * u.d[0] + u.d[1] * u.d[1];
+              nrm += wgt * (u.d[0] * u.d[0] + u.d[1] * u.d[1]);
             } else {
 #pragma unroll
               for (int h = 0; h < NLA; ++h) {
                 const u32x4 v = an[(rt * 2 + st) * NLA + h];
                 const double x0 = u2f(v.x), x1 = u2f(v.y), x2 = u2f(v.z), x3 = u2f(v.w);
-                nrm += x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3;
+                nrm += wgt * (x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
               }
             }
           }
@@ -785,9 +787,10 @@ static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   p.out = a.out; p.ldo = a.ldo; p.split_stride = a.split_stride; p.chunk = a.chunk;
   p.normA = TRANS ? nullptr : a.normA;
   p.a_scale = a.a_scale; p.out_scale = a.out_scale;
-  // the two-stage K1 where its registers fit (measured per instantiation)
-  constexpr bool two = MODE == M_F64 || (MODE == M_BF16 && NT <= 14) || (MODE == M_F16 && NT <= 10) ||
-                       (MODE == M_F32 && NT <= 14);
+  // the two-stage K1 for the matrix-core bound FP32 and FP64 modes where its
+  // registers fit; the 16-bit modes stream faster through the general kernel
+  // (measured per instantiation)
+  constexpr bool two = MODE == M_F64 || (MODE == M_F32 && NT <= 14);
   constexpr bool two_norm = two && !(MODE == M_F32 && NT == 14);
   if constexpr (!TRANS && TR::XN == 1 && two) {
     if (vec && p.normA && two_norm)
