@@ -260,7 +260,9 @@ def main():
     ap.add_argument("--model", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                     "paper_2103_07245_amd", "weights", "qk_mlp.bin"),
                     help="c5: trained q/k network")
-    ap.add_argument("--plan", default="native", help="precision plan of the c4 batch")
+    ap.add_argument("--plan", default=None,
+                    help="precision plan: c4 batch (default mixed; the per-matrix baseline is always the "
+                         "plain FP32 method), c5 (default native)")
     ap.add_argument("--count", type=int, default=1024, help="c4 batch size")
     ap.add_argument("--skip-per-matrix", action="store_true", help="c4: skip the per-matrix timing")
     ap.add_argument("--no-tune", action="store_true", help="c4: use the built-in batch plan, not the autotuner's")
@@ -564,7 +566,10 @@ def bench_sparse(args, torch, np, synth, B, dev):
 
 
 def bench_c4(args, torch, np, synth, B, dev):
-    """Batched uneven sizes: one graph launch per batch vs one call per matrix."""
+    """Batched uneven sizes: one graph launch per batch (mixed plan by default:
+    BF16 sketch and power passes, split-BF16x3 projection) against the plain
+    FP32 method called once per matrix; the FP32 batch is timed beside it."""
+    plan = args.plan or "mixed"
     shapes = synth.config4_shapes(args.count)
     t = time.time()
     gen = torch.Generator(device=dev)
@@ -585,13 +590,13 @@ def bench_c4(args, torch, np, synth, B, dev):
     if not args.no_tune:
         # the project autotuner picks the batch's Gram plan for this shape class
         t = time.time()
-        probe_bt = B.Batch(mats, ks, ps, qs, seeds, plan=args.plan)
+        probe_bt = B.Batch(mats, ks, ps, qs, seeds, plan=plan)
         tuned = probe_bt.tune()
         probe_bt.close()
         del probe_bt
         log(f"autotuned the batch plan in {time.time() - t:.1f}s: {tuned}")
     t = time.time()
-    bt = B.Batch(mats, ks, ps, qs, seeds, plan=args.plan)
+    bt = B.Batch(mats, ks, ps, qs, seeds, plan=plan)
     torch.cuda.synchronize()
     log(f"planned the batch in {time.time() - t:.1f}s: {bt.stats()}, problem 0 plan {bt.problem_plan(0)}")
 
@@ -612,8 +617,17 @@ def bench_c4(args, torch, np, synth, B, dev):
     bt.use_graph(True)
     log(f"batched (grouped launches, no graph): {ms_direct:.3f} ms per batch")
 
-    # one pbpqlp_factor call per matrix with its own automatic plan
-    facs = [B.Factorizer(a.shape[0], a.shape[1], k, p, q, torch.float32, args.plan, dev)
+    ms_batch_fp32 = None
+    if plan != "native":
+        bt32 = B.Batch(mats, ks, ps, qs, seeds, plan="native")
+        ms_batch_fp32 = timed(bt32.run, max(1, args.steps // 2), 1)
+        bt32.close()
+        del bt32
+        log(f"batched FP32 plan (graph): {ms_batch_fp32:.3f} ms per batch")
+
+    # the plain FP32 method, one pbpqlp_factor call per matrix with its own
+    # automatic plan
+    facs = [B.Factorizer(a.shape[0], a.shape[1], k, p, q, torch.float32, "native", dev)
             for a, k, p, q in zip(mats, ks, ps, qs)]
 
     def per_matrix():
@@ -623,7 +637,7 @@ def bench_c4(args, torch, np, synth, B, dev):
     ms_single = None
     if not args.skip_per_matrix:
         ms_single = timed(per_matrix, max(1, args.steps // 4), 1)
-        log(f"per-matrix calls: {ms_single:.3f} ms per batch")
+        log(f"per-matrix calls, plain FP32: {ms_single:.3f} ms per batch")
 
     # sample against the FP64 oracle and against the per-matrix results
     from oracle import pbpqlp as oracle_pbpqlp, rel_residual
@@ -639,7 +653,7 @@ def bench_c4(args, torch, np, synth, B, dev):
         # pbpqlp_factor with the plan the batch chose reproduces it bit for bit
         split_k, gram_wg = bt.problem_plan(i)
         f1 = B.Factorizer(mats[i].shape[0], mats[i].shape[1], ks[i], ps[i], qs[i], torch.float32,
-                          args.plan, dev, split_k=split_k, gram_wg=gram_wg)
+                          plan, dev, split_k=split_k, gram_wg=gram_wg)
         same = all(torch.equal(x, y) for x, y in zip((bt.Q[i], bt.L[i], bt.P[i]), f1(mats[i], seeds[i])))
         if not same:
             log(f"problem {i}: batched and per-matrix results differ")
@@ -647,13 +661,14 @@ def bench_c4(args, torch, np, synth, B, dev):
         "metric": "PbP-QLP batched factorizations: ms per batch of 1024 uneven FP32 matrices",
         "value": round(ms_batch, 3), "unit": "ms/batch", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_batch, 3), "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.plan == "native" else "bf16",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if plan == "native" else "bf16",
         "data": "synthetic",
         "config": {"workload": f"{len(mats)} FP32 matrices m~U[256,4096] n~U[256,2048] r~U[8,64], "
-                               "sigma_i=exp(-i/r) + 1e-5 N(0,1), k=r p=8 q=1", "plan": args.plan},
-        "per_matrix_ms": round(ms_single, 3) if ms_single else None,
+                               "sigma_i=exp(-i/r) + 1e-5 N(0,1), k=r p=8 q=1", "plan": plan},
+        "per_matrix_fp32_ms": round(ms_single, 3) if ms_single else None,
+        "batched_fp32_ms": round(ms_batch_fp32, 3) if ms_batch_fp32 else None,
         "grouped_no_graph_ms": round(ms_direct, 3),
-        "speedup_vs_per_matrix": round(ms_single / ms_batch, 2) if ms_single else None,
+        "speedup_vs_per_matrix_fp32": round(ms_single / ms_batch, 2) if ms_single else None,
         "launches_per_batch": bt.stats()["launches"],
         "autotuned_plan": tuned,
         "algorithmic_gb": abytes / 1e9, "achieved_gbs": round(abytes / (ms_batch * 1e-3) / 1e9, 1),
@@ -668,6 +683,7 @@ def bench_c5(args, torch, np, synth, B, dev):
     pbpqlp_factor_auto against the plain method with q = 3 and the true
     epsilon-rank k*, both judged by tau = 1.05 r_opt(k* + p)."""
     from paper_2103_07245_amd import train_qk as T
+    plan = args.plan or "native"
     count = args.count if args.count != 1024 else 12
     size = 8192
     model = B.Model.load(args.model)
@@ -679,10 +695,10 @@ def bench_c5(args, torch, np, synth, B, dev):
         A = T.make_matrix(spec, dev).float().contiguous()
         ks = T.k_star(spec.sigma)
         tau = T.Q_SLACK * T.r_opt(spec.sigma, ks + p)
-        fplain = B.Factorizer(size, size, ks, p, 3, torch.float32, args.plan, dev)
+        fplain = B.Factorizer(size, size, ks, p, 3, torch.float32, plan, dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, _, _, res, info = B.factor_auto(model, A, p, spec.seed_omega, B.PROBE_K, tau, plan=args.plan)
+        _, _, _, res, info = B.factor_auto(model, A, p, spec.seed_omega, B.PROBE_K, tau, plan=plan)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         fplain(A, spec.seed_omega)
@@ -708,9 +724,9 @@ def bench_c5(args, torch, np, synth, B, dev):
         "metric": "learned q/k: ms per factorization of 8192x8192 FP32, learned vs plain q=3",
         "value": round(ml, 3), "unit": "ms/factorization", "n_gpus": 1, "steps": len(rows),
         "warmup": 1, "ms_per_step": round(ml, 3), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32" if args.plan == "native" else "bf16", "data": "synthetic",
+        "vs_baseline": None, "dtype": "f32" if plan == "native" else "bf16", "data": "synthetic",
         "config": {"workload": f"{len(rows)} FP32 {size}x{size} matrices, spectra step/poly/exp, "
-                               "planted rank <= 512, p=8, probe l=64", "plan": args.plan},
+                               "planted rank <= 512, p=8, probe l=64", "plan": plan},
         "plain_q3_ms": round(mp, 3), "speedup_vs_plain_q3": round(mp / ml, 3),
         "passes_learned_mean": float(np.mean([r["passes"] for r in rows])), "passes_plain": 8,
         "success_learned": ok_l, "success_plain_q3": ok_p,
