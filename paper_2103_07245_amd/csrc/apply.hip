@@ -72,40 +72,60 @@ template <int NT, int MAXT> struct ApplyPhases {
 
 template <int NT, int MAXT> inline constexpr ApplyPhases<NT, MAXT> kApplyPhases{};
 
+// Tiles of LDS a triangular operand of NT tile rows needs: all NT (NT + 1) / 2
+// upper tiles, or the MAXT of the largest phase.
+template <int NT, int MAXT>
+inline constexpr int kOpTiles = NT * (NT + 1) / 2 < MAXT ? NT * (NT + 1) / 2 : MAXT;
+
+// Staging of phase P (row blocks J0 .. J1-1 of the operand) into LDS: one
+// element of each tile per thread.
+template <typename T, int NT, int MAXT, int P>
+__device__ __forceinline__ void apply_stage(T* ops, const T* __restrict__ Ra, const T* __restrict__ Dinv, int lp,
+                                            int tid) {
+  constexpr auto& PH = kApplyPhases<NT, MAXT>;
+  constexpr int J0 = PH.j0[P], J1 = PH.j1[P];
+  const int si = tid >> 4, sc = tid & 15;
+  int t = 0;
+#pragma unroll
+  for (int J = J0; J < J1; ++J)
+#pragma unroll
+    for (int K = J; K < NT; ++K, ++t)
+      ops[t * kTile + si * 17 + sc] =
+          (K == J) ? Dinv[J * 256 + si * 16 + sc] : -Ra[(int64_t)(16 * J + si) * lp + 16 * K + sc];
+}
+
+// The products of phase P on one wave's 16 rows (the operand staged).
+template <typename T, int NT, int MAXT, int P>
+__device__ __forceinline__ void apply_compute(typename Vec4<T>::type (&y)[NT], const T* ops, int li, int lg) {
+  typedef typename Vec4<T>::type ACC;
+  constexpr auto& PH = kApplyPhases<NT, MAXT>;
+  constexpr int J0 = PH.j0[P], J1 = PH.j1[P];
+  int t = 0;
+#pragma unroll
+  for (int J = J0; J < J1; ++J) {
+    ACC q = {0, 0, 0, 0};
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) q = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], y[J][s4], q);
+    y[J] = q;
+    ++t;
+#pragma unroll
+    for (int K = J + 1; K < NT; ++K, ++t)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) y[K] = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], q[s4], y[K]);
+  }
+}
+
 // One staging phase P of the substitution (row blocks J0 .. J1-1), then the next.
 template <typename T, int NT, int MAXT, int P>
 __device__ __forceinline__ void apply_phase(typename Vec4<T>::type (&y)[NT], T* ops,
                                             const T* __restrict__ Ra, const T* __restrict__ Dinv,
                                             int lp, int tid, int li, int lg) {
-  typedef typename Vec4<T>::type ACC;
   constexpr auto& PH = kApplyPhases<NT, MAXT>;
   if constexpr (P < PH.n) {
-    constexpr int J0 = PH.j0[P], J1 = PH.j1[P];
     if constexpr (P > 0) lds_barrier();  // every wave is done with the previous phase
-    const int si = tid >> 4, sc = tid & 15;  // staging: one element of each tile per thread
-    {
-      int t = 0;
-#pragma unroll
-      for (int J = J0; J < J1; ++J)
-#pragma unroll
-        for (int K = J; K < NT; ++K, ++t)
-          ops[t * kTile + si * 17 + sc] =
-              (K == J) ? Dinv[J * 256 + si * 16 + sc] : -Ra[(int64_t)(16 * J + si) * lp + 16 * K + sc];
-    }
+    apply_stage<T, NT, MAXT, P>(ops, Ra, Dinv, lp, tid);
     lds_barrier();
-    int t = 0;
-#pragma unroll
-    for (int J = J0; J < J1; ++J) {
-      ACC q = {0, 0, 0, 0};
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) q = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], y[J][s4], q);
-      y[J] = q;
-      ++t;
-#pragma unroll
-      for (int K = J + 1; K < NT; ++K, ++t)
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) y[K] = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], q[s4], y[K]);
-    }
+    apply_compute<T, NT, MAXT, P>(y, ops, li, lg);
     apply_phase<T, NT, MAXT, P + 1>(y, ops, Ra, Dinv, lp, tid, li, lg);
   }
 }
@@ -132,6 +152,7 @@ struct ApplyP {
   void* lo;
   int emode;
   float xs;
+  int rtiles;     // 64-row tiles per block (1 unless the operand is staged in one phase)
   PBQ_GRID;
 };
 
@@ -166,29 +187,46 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps)
   typedef typename Vec4<T>::type ACC;
   constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
   static_assert(MAXT >= NT, "a phase must hold one full row block");
-  __shared__ T ops[MAXT * kTile];
+  // LDS for the operand's upper tiles, or for one phase of them: narrow
+  // operands leave room for several blocks per CU
+  __shared__ T ops[kOpTiles<NT, MAXT> * kTile];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int64_t arow = ((int64_t)blockIdx.x * 4 + wave) * 16 + li;
-  const bool in = arow < len;
-  ACC y[NT];
-#pragma unroll
-  for (int K = 0; K < NT; ++K)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      y[K][r] = in ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
   // the identity factor of a later sweep leaves Y as it is (block-uniform test)
-  if (!(prm.ident && *prm.ident)) apply_phase<T, NT, MAXT, 0>(y, ops, Ra, Dinv, lp, tid, li, lg);
+  const bool ident = prm.ident && *prm.ident;
+  // an operand staged in one phase serves every row tile of the block
+  constexpr bool single = kApplyPhases<NT, MAXT>.n == 1;
+  const int rtiles = single ? prm.rtiles : 1;
+  if (single && !ident) {
+    apply_stage<T, NT, MAXT, 0>(ops, Ra, Dinv, lp, tid);
+    lds_barrier();
+  }
+  for (int rt = 0; rt < rtiles; ++rt) {
+    const int64_t arow = (((int64_t)blockIdx.x * rtiles + rt) * 4 + wave) * 16 + li;
+    const bool in = arow < len;
+    ACC y[NT];
 #pragma unroll
-  for (int J = 0; J < NT; ++J)
+    for (int K = 0; K < NT; ++K)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int c = 16 * J + acc_row<T>(lg, r);
-      if (Qcm && arow < prm.wq) {
-        Qcm[(int64_t)c * ldq + arow] = y[J][r];
-        if (prm.emode) store16<T>(prm, (int64_t)c * ldq + arow, y[J][r]);
-      }
-      if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[J][r];
+      for (int r = 0; r < 4; ++r)
+        y[K][r] = in ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
+    if (!ident) {
+      if constexpr (single)
+        apply_compute<T, NT, MAXT, 0>(y, ops, li, lg);
+      else
+        apply_phase<T, NT, MAXT, 0>(y, ops, Ra, Dinv, lp, tid, li, lg);
     }
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * J + acc_row<T>(lg, r);
+        if (Qcm && arow < prm.wq) {
+          Qcm[(int64_t)c * ldq + arow] = y[J][r];
+          if (prm.emode) store16<T>(prm, (int64_t)c * ldq + arow, y[J][r]);
+        }
+        if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[J][r];
+      }
+  }
 }
 
 // Short tall matrices (the l x l stages, len <= 256 rows): one block per
@@ -263,7 +301,7 @@ __global__ __launch_bounds__(256) void apply_cols_kernel(const ApplyP* pb, Apply
   constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
   constexpr int NS = (NT + 3) / 4;
   static_assert(MAXT >= NT, "a phase must hold one full row block");
-  __shared__ T ops[MAXT * kTile];
+  __shared__ T ops[kOpTiles<NT, MAXT> * kTile];
   __shared__ T qb[2][16 * 17];
   const int tid = threadIdx.x, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -325,7 +363,7 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const RightMulP* pb, Rig
   T* __restrict__ Orm = (T*)prm.Orm;
   typedef typename Vec4<T>::type ACC;
   constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
-  constexpr int RPP = MAXT / NT;  // row blocks of M per phase
+  constexpr int RPP = MAXT / NT < NT ? MAXT / NT : NT;  // row blocks of M per phase
   static_assert(RPP >= 1, "a phase must hold one row block");
   __shared__ T ops[RPP * NT * kTile];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
@@ -386,14 +424,24 @@ static hipError_t apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, 
   if (e != hipSuccess) return e;
   if (wq < 0) wq = ldq;
   const int64_t rows = Qcm ? (wq > len ? wq : len) : len;
-  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr, wq, ident, em.hi, em.lo, em.mode, em.xs};
+  ApplyP p{Y, ldy, len, l, lp, Ra, Dinv, Qcm, ldq, Qrm, ldqr, wq, ident, em.hi, em.lo, em.mode, em.xs, 1};
   if constexpr (sizeof(T) == 8) {
     if (rows <= 256)  // the FP64 l x l stages: four waves per row panel
       return launch_k(apply_cols_kernel<T, NT, false>, apply_cols_kernel<T, NT, true>,
                       dim3((unsigned)((rows + 15) / 16)), dim3(256), s, p);
   }
-  return launch_k(apply_kernel<T, NT, false>, apply_kernel<T, NT, true>, dim3((unsigned)((rows + 63) / 64)),
-                  dim3(256), s, p);
+  // Several 64-row tiles per block share one staging of the operand: in a
+  // batch (the problems fill the chip together) and where the row tiles make
+  // more than two rounds of the CUs.
+  const int64_t tiles = (rows + 63) / 64;
+  constexpr int MAXT = kOpLdsBytes / (kTile * (int)sizeof(T));
+  if (kApplyPhases<NT, MAXT>.n == 1) {
+    const int64_t cus = device_cus();
+    const int64_t want = current_recorder() ? 4 : tiles / (2 * cus);
+    p.rtiles = (int)(want < 1 ? 1 : (want > 4 ? 4 : want));
+  }
+  return launch_k(apply_kernel<T, NT, false>, apply_kernel<T, NT, true>,
+                  dim3((unsigned)((tiles + p.rtiles - 1) / p.rtiles)), dim3(256), s, p);
 }
 
 template <typename T, int NT>
