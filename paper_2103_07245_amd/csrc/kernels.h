@@ -26,8 +26,8 @@ struct StreamArgs {
 };
 
 hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s);
-int stream_rows_per_block(int mode);
-int stream_kc(int mode);
+// rows (A X) or columns (A^T X) of A one block of a streaming pass covers
+int stream_span(int mode, bool trans);
 // compute units of the current device (queried once per device)
 int device_cus();
 // K1 (Y = A X) workgroups along the rows of A for `rows` rows and `splits`

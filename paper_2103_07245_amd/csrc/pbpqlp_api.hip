@@ -289,7 +289,7 @@ struct Ctx {
   int64_t ldnM() const { return tv ? ldm : ldn; }
   // Split plan of a pass in compute mode `mode` (grid blocks depend on it).
   Split split_for(int mode, bool trans) const {
-    const int64_t rb = stream_rows_per_block(mode);
+    const int64_t rb = stream_span(mode, trans);
     const int64_t mr = panel_rows > 0 ? panel_rows : m;   // rows one launch sees
     const int64_t len = trans ? n : mr, klen = trans ? mr : n;
     // one launch covers at most kMaxL columns of the operand
@@ -480,7 +480,7 @@ StreamArgs slice_args(const Ctx& c, const StreamArgs& a, int mode, int j0) {
 pbpqlp_status host_pass(Ctx& c, bool trans, int mode, StreamArgs a, int64_t xlen, void* out,
                         int64_t ldo, double* normA, hipStream_t st) {
   const Split sp = c.split_for(mode, trans);
-  const int64_t rb = stream_rows_per_block(mode);
+  const int64_t rb = stream_span(mode, trans);
   const int64_t olen = trans ? c.n : c.m;
   const double xb = (mode >= M_BF16) ? 2.0 : (double)c.el;
   int64_t slot = 0;

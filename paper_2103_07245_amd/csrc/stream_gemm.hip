@@ -41,28 +41,35 @@ template <int MODE> struct Tr;
 template <> struct Tr<M_F64> {
   typedef double TA; typedef double TC; typedef double TACC;
   static constexpr int V = 2, RT = 1, XN = 1, NW = 8;
+  static constexpr int RT1 = 1, NS1 = 2;
 };
 template <> struct Tr<M_F32> {
   typedef float TA; typedef float TC; typedef float TACC;
   static constexpr int V = 4, RT = 2, XN = 1, NW = 8;
+  static constexpr int RT1 = 2, NS1 = 2;
 };
 template <> struct Tr<M_BF16> {
   typedef float TA; typedef __bf16 TC; typedef float TACC;
   static constexpr int V = 8, RT = 2, XN = 1, NW = 8;
+  static constexpr int RT1 = 2, NS1 = 2;
 };
 template <> struct Tr<M_F16> {
   typedef float TA; typedef _Float16 TC; typedef float TACC;
   static constexpr int V = 8, RT = 2, XN = 1, NW = 8;
+  static constexpr int RT1 = 2, NS1 = 2;
 };
 template <> struct Tr<M_BF16X3> {
   typedef float TA; typedef __bf16 TC; typedef float TACC;
   static constexpr int V = 8, RT = 2, XN = 2, NW = 8;
+  static constexpr int RT1 = 2, NS1 = 2;
 };
 
 // Every mode moves 16 bytes of compute-type operand per lane per step
-// (KS = 4 V contraction indices) and two steps per stage: 128 bytes per X
-// column per stage.
-constexpr int kPitch = 128 + 16;  // LDS bytes per X column, padded against bank conflicts
+// (KS = 4 V contraction indices); a stage is NS steps (two for A^T X and the
+// two-stage K1, Tr::NS1 for the general K1), 64 NS bytes per X column.
+// RT: 16-row (K1) or paired-column (K2) sub-tiles per wave; the general K1
+// takes Tr::RT1.
+constexpr int kPitch = 128 + 16;  // LDS bytes per X column of a two-step stage, padded against bank conflicts
 constexpr int kGroup = 4;         // X column tiles per scheduling group
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
@@ -214,18 +221,24 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
   typedef typename TR::TC TC;
   typedef typename TR::TACC TACC;
   typedef typename AccOf<TACC>::type ACC;
-  constexpr int V = TR::V, KS = 4 * V, KC = 2 * KS, RT = TR::RT, XN = TR::XN;
+  constexpr int V = TR::V, KS = 4 * V, XN = TR::XN;
+  constexpr int RT = TRANS ? TR::RT : TR::RT1;      // sub-tiles per wave
+  constexpr int NS = TRANS ? 2 : TR::NS1;           // steps per stage
+  constexpr int KC = NS * KS;                       // contraction indices per stage
+  constexpr int PITCH = 64 * NS + 16;               // LDS bytes per X column, padded against bank conflicts
+  constexpr int CPC = 4 * NS;                       // 16-byte X chunks per column per stage
   constexpr int NBUF = 2;                           // X ring depth in LDS
   constexpr int NW = TR::NW, NTH = 64 * NW;
-  constexpr int XCH = (NT * 128 + NTH - 1) / NTH;   // 16-byte X chunks per thread per stage
+  constexpr int NCH = NT * 16 * CPC;                // 16-byte X chunks per stage
+  constexpr int XCH = (NCH + NTH - 1) / NTH;        // per thread
   constexpr int EA = 16 / (int)sizeof(TA);          // A elements per 16-byte load (K1)
   constexpr int NLA = (V * (int)sizeof(TA)) / 16;   // 16-byte A loads per lane per step (K1)
-  constexpr int NAR = TRANS ? 2 * V : 2 * RT * NLA; // A registers-loads per lane per stage
+  constexpr int NAR = TRANS ? NS * V : NS * RT * NLA; // A registers-loads per lane per stage
   static_assert(NT % 2 == 0, "NT must be even");
-  // a chunk index q < NT * 128 is valid; only the last j can overflow
-  auto xch_ok = [&](int j, int q) { return j < XCH - 1 || (NT * 128) % NTH == 0 || q < NT * 128; };
-  static_assert(RT * sizeof(TA) == 8, "K2 loads 8 bytes of A per row per lane");
-  __shared__ __attribute__((aligned(16))) char xs[NBUF][XN][NT * 16 * kPitch];
+  // a chunk index q < NCH is valid; only the last j can overflow
+  auto xch_ok = [&](int j, int q) { return j < XCH - 1 || NCH % NTH == 0 || q < NCH; };
+  static_assert(!TRANS || RT * sizeof(TA) == 8, "K2 loads 8 bytes of A per row per lane");
+  __shared__ __attribute__((aligned(16))) char xs[NBUF][XN][NT * 16 * PITCH];
 
   const TA* __restrict__ A = (const TA*)p.A;
   const TC* __restrict__ Xc = (const TC*)p.X;
@@ -281,7 +294,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
     for (int j = 0; j < XCH; ++j) {
       const int q = tid + NTH * j;
       if (!xch_ok(j, q)) continue;
-      const int c = q >> 3, part = q & 7;
+      const int c = q / CPC, part = q % CPC;
       constexpr int EX = 16 / (int)sizeof(TC);
       const int64_t k = k0 + part * EX;
       const int64_t off = (int64_t)c * p.ldx + k;
@@ -304,12 +317,12 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int st = 0; st < 2; ++st)
+        for (int st = 0; st < NS; ++st)
 #pragma unroll
           for (int h = 0; h < NLA; ++h) {
             const int64_t k = k0 + st * KS + lg * V + h * EA;
             const TA* src = A + arow[rt] * p.lda + k;
-            u32x4& d = an[(rt * 2 + st) * NLA + h];
+            u32x4& d = an[(rt * NS + st) * NLA + h];
             if (full) {
               d = *(const u32x4_e*)src;
             } else {
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
           }
     } else {
 #pragma unroll
-      for (int st = 0; st < 2; ++st)
+      for (int st = 0; st < NS; ++st)
 #pragma unroll
         for (int e = 0; e < V; ++e) {
           const int64_t i = k0 + st * KS + lg * V + e;
@@ -358,20 +371,20 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
     for (int j = 0; j < XCH; ++j) {
       const int q = tid + NTH * j;
       if (!xch_ok(j, q)) continue;
-      const int c = q >> 3, part = q & 7;
+      const int c = q / CPC, part = q % CPC;
 #pragma unroll
-      for (int x = 0; x < XN; ++x) st16(&xs[buf][x][c * kPitch + part * 16], xn[x][j]);
+      for (int x = 0; x < XN; ++x) st16(&xs[buf][x][c * PITCH + part * 16], xn[x][j]);
     }
     // A(s) -> compute-type fragments afr[rt][st] (hi and, for BF16X3, lo)
-    u32x4 ahi[RT][2], alo[RT][2];
+    u32x4 ahi[RT][NS], alo[RT][NS];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-      for (int st = 0; st < 2; ++st) {
+      for (int st = 0; st < NS; ++st) {
         u32x4 g0, g1;  // the V A values of this lane for (rt, st), as raw TA bits
         if constexpr (!TRANS) {
-          g0 = an[(rt * 2 + st) * NLA];
-          g1 = NLA > 1 ? an[(rt * 2 + st) * NLA + NLA - 1] : g0;
+          g0 = an[(rt * NS + st) * NLA];
+          g1 = NLA > 1 ? an[(rt * NS + st) * NLA + NLA - 1] : g0;
           if (p.normA) {
             // rows past the edge repeat the last row: weight 0 (no lane branch)
             const double wgt = rowok[rt] ? 1.0 : 0.0;
@@ -382,7 +395,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
             } else {
 #pragma unroll
               for (int h = 0; h < NLA; ++h) {
-                const u32x4 v = an[(rt * 2 + st) * NLA + h];
+                const u32x4 v = an[(rt * NS + st) * NLA + h];
                 const double x0 = u2f(v.x), x1 = u2f(v.y), x2 = u2f(v.z), x3 = u2f(v.w);
                 nrm += wgt * (x0 * x0 + x1 * x1 + x2 * x2 + x3 * x3);
               }
@@ -422,17 +435,17 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
       // split-BF16x3: six products per X fragment pair; the pair of the next
       // column tile is read before the products of this one are issued
       auto frag = [&](int t, u32x4& h, u32x4& l) __attribute__((always_inline)) {
-        const int boff = (16 * (t % NT) + li) * kPitch + (t / NT) * 64 + lg * 16;
+        const int boff = (16 * (t % NT) + li) * PITCH + (t / NT) * 64 + lg * 16;
         h = *(const u32x4*)&xs[buf][0][boff];
         l = *(const u32x4*)&xs[buf][1][boff];
       };
       u32x4 fh, fl;
       frag(0, fh, fl);
 #pragma unroll
-      for (int t = 0; t < 2 * NT; ++t) {
+      for (int t = 0; t < NS * NT; ++t) {
         const int st = t / NT, ct = t % NT;
         u32x4 nh = fh, nl = fl;
-        if (t + 1 < 2 * NT) frag(t + 1, nh, nl);
+        if (t + 1 < NS * NT) frag(t + 1, nh, nl);
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
@@ -447,13 +460,13 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
       }
     } else {
 #pragma unroll
-      for (int st = 0; st < 2; ++st) {
+      for (int st = 0; st < NS; ++st) {
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
           // keep at most kGroup X fragments in flight: the scheduler would
           // otherwise hoist every LDS read of the step and spill accumulators
           if (ct % kGroup == 0 && (ct > 0 || st > 0)) __builtin_amdgcn_sched_barrier(0);
-          const int boff = (16 * ct + li) * kPitch + st * 64 + lg * 16;
+          const int boff = (16 * ct + li) * PITCH + st * 64 + lg * 16;
           const u32x4 xhi = *(const u32x4*)&xs[buf][0][boff];
 #pragma unroll
           for (int rt = 0; rt < RT; ++rt) {
@@ -545,6 +558,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const S
   typedef typename AccOf<TACC>::type ACC;
   constexpr int V = TR::V, KS = 4 * V, KC = 2 * KS, RT = TR::RT;
   static_assert(TR::XN == 1, "split-BF16x3 keeps the general kernel");
+  static_assert(TR::RT1 == TR::RT && TR::NS1 == 2, "the two-stage K1 keeps two-step stages of RT sub-tiles");
   constexpr int NW = TR::NW, NTH = 64 * NW;
   constexpr int XCH = (NT * 128 + NTH - 1) / NTH;
   constexpr int EA = 16 / (int)sizeof(TA);
@@ -778,7 +792,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const S
 template <int MODE, int NT, bool TRANS>
 static hipError_t launch_nt(const StreamArgs& a, bool vec, hipStream_t s) {
   typedef Tr<MODE> TR;
-  const int span = 16 * TR::RT * TR::NW;
+  const int span = stream_span(MODE, TRANS);
   const int64_t gx = TRANS ? (a.n + span - 1) / span : stream_k1_grid(MODE, a.m, a.splits);
   dim3 grid((unsigned)gx, (unsigned)a.splits);
   StreamParams p;
@@ -836,13 +850,17 @@ static hipError_t dispatch_dir(bool trans, const StreamArgs& a, hipStream_t s) {
   return trans ? dispatch_nt<MODE, true>(a, vec, s) : dispatch_nt<MODE, false>(a, vec, s);
 }
 
-int stream_rows_per_block(int mode) {
+template <int MODE> static int span_of(bool trans) {
+  typedef Tr<MODE> TR;
+  return 16 * (trans ? TR::RT : TR::RT1) * TR::NW;
+}
+int stream_span(int mode, bool trans) {
   switch (mode) {
-    case M_F64: return 16 * Tr<M_F64>::RT * Tr<M_F64>::NW;
-    case M_F32: return 16 * Tr<M_F32>::RT * Tr<M_F32>::NW;
-    case M_BF16: return 16 * Tr<M_BF16>::RT * Tr<M_BF16>::NW;
-    case M_F16: return 16 * Tr<M_F16>::RT * Tr<M_F16>::NW;
-    default: return 16 * Tr<M_BF16X3>::RT * Tr<M_BF16X3>::NW;
+    case M_F64: return span_of<M_F64>(trans);
+    case M_F32: return span_of<M_F32>(trans);
+    case M_BF16: return span_of<M_BF16>(trans);
+    case M_F16: return span_of<M_F16>(trans);
+    default: return span_of<M_BF16X3>(trans);
   }
 }
 int device_cus() {
@@ -858,7 +876,7 @@ int device_cus() {
 }
 
 int64_t stream_k1_grid(int mode, int64_t rows, int splits) {
-  const int64_t span = stream_rows_per_block(mode);
+  const int64_t span = stream_span(mode, false);
   const int64_t b0 = (rows + span - 1) / span;
   const int64_t cus = device_cus();
   // one block per CU at a time: for the HBM-bound 16-bit modes a ragged last
@@ -869,7 +887,6 @@ int64_t stream_k1_grid(int mode, int64_t rows, int splits) {
   return b0;
 }
 
-int stream_kc(int mode) { return mode == M_F64 ? 16 : (mode == M_F32 ? 32 : 64); }
 
 hipError_t launch_stream(bool trans, int mode, const StreamArgs& a, hipStream_t s) {
   if (a.lp32 < 32 || a.lp32 > 256 || a.lp32 % 32 != 0 || a.lp > a.lp32) return hipErrorInvalidValue;

@@ -64,8 +64,11 @@ def _ref_product(A, X, trans, prec, a_scale=1.0):
     return a16 @ x16
 
 
+# (70001, 130, 64): one contraction split over 274 row blocks, which the
+# 16-bit A X spreads over two whole rounds of the CUs (512 blocks of about
+# 137 rows, the last row group partial)
 SHAPES = [(1000, 777, 25), (129, 70, 7), (70, 129, 16), (3000, 520, 33), (515, 300, 220),
-          (256, 256, 256), (40, 33, 1)]
+          (256, 256, 256), (40, 33, 1), (70001, 130, 64)]
 
 
 @pytest.mark.parametrize("m,n,l", SHAPES)
@@ -140,9 +143,11 @@ def _signed_qr(Y):
     return householder_qr(Y)
 
 
+# (140000, 64): more than two rounds of 64-row tiles, so each apply block
+# takes four of them under one staging of the factor
 @pytest.mark.parametrize("rows,l,dtype", [(1000, 25, torch.float64), (5000, 80, torch.float32),
                                           (300, 220, torch.float64), (777, 33, torch.float32),
-                                          (64, 64, torch.float64)])
+                                          (64, 64, torch.float64), (140000, 64, torch.float32)])
 def test_orth_matches_householder(rows, l, dtype):
     print(f"orth rows={rows} l={l} {dtype}", flush=True)
     rng = synth.rng_for(rows + l)
