@@ -134,8 +134,9 @@ hipError_t launch_csr_transpose(bool f64, const int64_t* rowptr, const int32_t* 
 hipError_t launch_sumsq(bool f64, const void* vals, int64_t nnz, int nparts, double* part, hipStream_t s);
 // out (column-major, ldo, padding 0) = M X[:, c0:c0+w] for CSR M (rows x cols)
 // and row-major X (ldx), balanced by nonzeros; Yrm (rows x ldy) and part
-// (2 spmm_chunks(nnz) x ldy) are scratch
+// (spmm_part_rows(nnz) x ldy) are scratch
 int64_t spmm_chunks(int64_t nnz);
+int64_t spmm_part_rows(int64_t nnz);
 hipError_t launch_spmm(bool f64, const int64_t* rowptr, const int32_t* idx, const void* vals, int64_t rows,
                        int64_t cols, int64_t nnz, const void* X, int64_t ldx, int c0, int w, void* Yrm,
                        int64_t ldy, void* part, void* out, int64_t ldo, hipStream_t s);

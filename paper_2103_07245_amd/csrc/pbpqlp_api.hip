@@ -402,7 +402,7 @@ struct Ctx {
       tscratch = b.take(csr_transpose_scratch_bytes(nnz, n));
       Xrm = b.take((size_t)(m > n ? m : n) * lp32 * el);
       Yrm = b.take((size_t)(m > n ? m : n) * ldyr() * el);
-      spart = b.take((size_t)2 * (spmm_chunks(nnz) > 0 ? spmm_chunks(nnz) : 1) * ldyr() * el);
+      spart = b.take((size_t)spmm_part_rows(nnz) * ldyr() * el);
     }
   }
 };

@@ -14,6 +14,7 @@
 namespace pbq {
 
 constexpr int64_t kSpmmChunk = 256;   // nonzeros per wave of the balanced product
+constexpr int64_t kFixGroup = 64;     // chunks per head sum of the rows cut by chunk boundaries
 
 // ---------------------------------------------------------------------------
 // CSR of A^T by a stable LSD radix sort of the column indices (8 bits per
@@ -445,7 +446,7 @@ struct SpmmP {
   int c0, w;
   void* Y;          // row-major rows x ldy, zero before the call
   int64_t ldy;
-  void* part;       // T x 2 x ldy partial rows
+  void* part;       // T x 2 x ldy partial rows, then ceil(T / kFixGroup) x ldy head sums
   int64_t C, T;
   PBQ_GRID;
 };
@@ -539,9 +540,53 @@ __global__ __launch_bounds__(256) void spmm_kernel(const SpmmP* pb, SpmmP ps) {
   flush();
 }
 
-// The rows cut by chunk boundaries: the wave of boundary t (t = 1 .. T - 1)
-// sums the partials of the row holding entry t C when that row starts in
-// chunk t - 1 (so each cut row is summed once), in chunk order.
+// The rows cut by chunk boundaries.  A cut row r starts in chunk t0 (its
+// partial there is slot 0 of t0 when r begins the chunk, else slot 1) and
+// continues through chunks t0 + 1 .. t1 (slot 0 of each).  Its sum runs in a
+// fixed order: the first partial, the continuation chunks before the first
+// group start (a multiple of kFixGroup), then the head sums of the groups
+// that start inside the row, each the sum in chunk order of the row's
+// continuation chunks in that group (spmm_head_kernel).  A row of a million
+// nonzeros is then a few hundred additions instead of thousands.
+//
+// spmm_head_kernel: the wave of group j sums slot 0 of the chunks
+// jG .. min(jG + G - 1, t1) when chunk jG continues a row that started earlier.
+template <typename T, bool B>
+__global__ __launch_bounds__(256) void spmm_head_kernel(const SpmmP* pb, SpmmP ps) {
+  bool past;
+  const SpmmP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t NG = (p.T + kFixGroup - 1) / kFixGroup;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= NG || j == 0) return;
+  const int64_t u0 = j * kFixGroup, b = u0 * p.C;
+  const int64_t r = row_of(p.rowptr, p.rows, p.nnz, b);
+  const int64_t rs = rp(p.rowptr, r, p.nnz), re = rp(p.rowptr, r + 1, p.nnz);
+  if (!(rs < b && re > b)) return;
+  int64_t u1 = (re - 1) / p.C;
+  if (u1 > u0 + kFixGroup - 1) u1 = u0 + kFixGroup - 1;
+  if (u1 > p.T - 1) u1 = p.T - 1;
+  const T* part = (const T*)p.part;
+  T s[4] = {T(0), T(0), T(0), T(0)};
+  for (int64_t u = u0; u <= u1; ++u) {
+    const T* pu = part + (u * 2) * p.ldy;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = lane + 64 * q;
+      if (c < p.w) s[q] += pu[c];
+    }
+  }
+  T* h = (T*)p.part + (2 * p.T + j) * p.ldy;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = lane + 64 * q;
+    if (c < p.w) h[c] = s[q];
+  }
+}
+
+// The wave of boundary t (t = 1 .. T - 1) sums the row holding entry t C when
+// that row starts in chunk t - 1 (so each cut row is summed once).
 template <typename T, bool B>
 __global__ __launch_bounds__(256) void spmm_fix_kernel(const SpmmP* pb, SpmmP ps) {
   bool past;
@@ -555,7 +600,9 @@ __global__ __launch_bounds__(256) void spmm_fix_kernel(const SpmmP* pb, SpmmP ps
   const int64_t rs = rp(p.rowptr, r, p.nnz);
   int64_t re = rp(p.rowptr, r + 1, p.nnz);
   if (!(rs < b && rs >= b - p.C && re > b)) return;
-  const int64_t t0 = t - 1, t1 = (re - 1) / p.C;
+  const int64_t t0 = t - 1;
+  int64_t t1 = (re - 1) / p.C;
+  if (t1 > p.T - 1) t1 = p.T - 1;
   const T* part = (const T*)p.part;
   T s[4];
   const T* first = part + (t0 * 2 + (rs == t0 * p.C ? 0 : 1)) * p.ldy;
@@ -564,13 +611,29 @@ __global__ __launch_bounds__(256) void spmm_fix_kernel(const SpmmP* pb, SpmmP ps
     const int c = lane + 64 * q;
     s[q] = c < p.w ? first[c] : T(0);
   }
-  for (int64_t u = t0 + 1; u <= t1 && u < p.T; ++u) {
-    const T* pu = part + (u * 2) * p.ldy;
+  auto add_chunks = [&](int64_t ua, int64_t ub) {   // slot 0 of chunks ua .. ub - 1, in order
+    for (int64_t u = ua; u < ub; ++u) {
+      const T* pu = part + (u * 2) * p.ldy;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = lane + 64 * q;
-      if (c < p.w) s[q] += pu[c];
+      for (int q = 0; q < 4; ++q) {
+        const int c = lane + 64 * q;
+        if (c < p.w) s[q] += pu[c];
+      }
     }
+  };
+  const int64_t ga = (t0 + kFixGroup) / kFixGroup, gb = t1 / kFixGroup;  // groups starting in t0 + 1 .. t1
+  if (ga <= gb) {
+    add_chunks(t0 + 1, ga * kFixGroup);
+    for (int64_t j = ga; j <= gb; ++j) {
+      const T* h = part + (2 * p.T + j) * p.ldy;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = lane + 64 * q;
+        if (c < p.w) s[q] += h[c];
+      }
+    }
+  } else {
+    add_chunks(t0 + 1, t1 + 1);
   }
   T* Y = (T*)p.Y + r * p.ldy;
 #pragma unroll
@@ -588,6 +651,10 @@ hipError_t launch_sumsq(bool f64, const void* vals, int64_t nnz, int nparts, dou
 }
 
 int64_t spmm_chunks(int64_t nnz) { return (nnz + kSpmmChunk - 1) / kSpmmChunk; }
+int64_t spmm_part_rows(int64_t nnz) {
+  const int64_t T = spmm_chunks(nnz) > 0 ? spmm_chunks(nnz) : 1;
+  return 2 * T + (T + kFixGroup - 1) / kFixGroup;
+}
 
 hipError_t launch_spmm(bool f64, const int64_t* rowptr, const int32_t* idx, const void* vals, int64_t rows,
                        int64_t cols, int64_t nnz, const void* X, int64_t ldx, int c0, int w, void* Yrm,
@@ -604,6 +671,13 @@ hipError_t launch_spmm(bool f64, const int64_t* rowptr, const int32_t* idx, cons
             : launch_k(spmm_kernel<float, false>, spmm_kernel<float, true>, grid, dim3(256), s, p);
     if (e != hipSuccess) return e;
     if (T > 1) {
+      const int64_t NG = (T + kFixGroup - 1) / kFixGroup;
+      if (NG > 1) {
+        const dim3 gh((unsigned)((NG + 3) / 4));
+        e = f64 ? launch_k(spmm_head_kernel<double, false>, spmm_head_kernel<double, true>, gh, dim3(256), s, p)
+                : launch_k(spmm_head_kernel<float, false>, spmm_head_kernel<float, true>, gh, dim3(256), s, p);
+        if (e != hipSuccess) return e;
+      }
       const dim3 gf((unsigned)((T - 1 + 3) / 4));
       e = f64 ? launch_k(spmm_fix_kernel<double, false>, spmm_fix_kernel<double, true>, gf, dim3(256), s, p)
               : launch_k(spmm_fix_kernel<float, false>, spmm_fix_kernel<float, true>, gf, dim3(256), s, p);
