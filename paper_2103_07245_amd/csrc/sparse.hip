@@ -80,6 +80,7 @@ struct RowCheckP {
   const int64_t* rowptr;
   int64_t m, nnz;
   int* bad;
+  int* rpbad;   // the transpose's own record of invalid row pointers
   PBQ_GRID;
 };
 
@@ -93,7 +94,10 @@ __global__ void rowptr_check_kernel(const RowCheckP* pb, RowCheckP ps) {
   const int64_t v = p.rowptr[i];
   bool badv = v < 0 || v > p.nnz || (i == 0 && v != 0) || (i == p.m && v != p.nnz);
   if (i < p.m && p.rowptr[i + 1] < v) badv = true;
-  if (badv) atomicOr(p.bad, PBPQLP_FLAG_BADINPUT);
+  if (badv) {
+    atomicOr(p.bad, PBPQLP_FLAG_BADINPUT);
+    atomicOr(p.rpbad, 1);
+  }
 }
 
 struct RsP {
@@ -278,12 +282,38 @@ hipError_t launch_scan(const int32_t* in, const int64_t* in64, int64_t n, int64_
   return launch_k(scan_total_kernel<false>, scan_total_kernel<true>, dim3(1), dim3(64), s, tp);
 }
 
+// Row of every entry of A: thread r writes r over its row's entries.  Run
+// only when the row pointers passed their check (then they rise from 0 to nnz
+// and the threads write nnz entries in all); with invalid row pointers the
+// finish kernel searches them per entry instead.
+struct RowIdP {
+  const int64_t* rowptr;
+  int64_t m;
+  const int* rpbad;
+  int32_t* rowid;
+  PBQ_GRID;
+};
+
+template <bool B>
+__global__ void rowid_kernel(const RowIdP* pb, RowIdP ps) {
+  bool past;
+  const RowIdP p = kparams<B>(pb, ps, past);
+  if (past) return;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= p.m) return;
+  if (__hip_atomic_load(p.rpbad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
+  const int64_t e1 = p.rowptr[r + 1];
+  for (int64_t e = p.rowptr[r]; e < e1; ++e) p.rowid[e] = (int32_t)r;
+}
+
 // Column counts of the valid entries (from the sorted keys: the last entry of
 // each run of equal keys knows its count) and the entries of A^T.
 struct FinishP {
   const int32_t* key;   // sorted
   const int32_t* perm;
+  const int32_t* rowid; // row of each entry of A (rowid_kernel)
   const int64_t* rowptr;
+  const int* rpbad;     // set: row pointers invalid, rowid not written
   const void* vals;
   int64_t m, n, nnz;
   int32_t* colcnt;
@@ -302,13 +332,19 @@ __global__ void csr_finish_kernel(const FinishP* pb, FinishP ps) {
   const int k = p.key[i];
   if (k >= p.n) return;   // invalid entries sort last and are left out
   const int64_t e = p.perm[i];
-  // row of entry e: the last r with rowptr[r] <= e
-  int64_t lo = 0, hi = p.m - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (p.rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+  int64_t r;
+  if (!__hip_atomic_load(p.rpbad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    r = p.rowid[e];
+  } else {
+    // row of entry e: the last r with rowptr[r] <= e
+    int64_t lo = 0, hi = p.m - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (p.rowptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    r = lo;
   }
-  p.idx_t[i] = (int32_t)lo;
+  p.idx_t[i] = (int32_t)r;
   ((T*)p.vals_t)[i] = ((const T*)p.vals)[e];
   if (i + 1 == p.nnz || p.key[i + 1] != k) {
     // the run of key k ends here; it started after the previous key's run
@@ -329,6 +365,7 @@ size_t csr_transpose_scratch_bytes(int64_t nnz, int64_t n) {
   take((size_t)256 * T * sizeof(int32_t));          // H
   take(((size_t)256 * T + 1) * sizeof(int64_t));    // its scan
   take((size_t)n * sizeof(int32_t));                // column counts
+  take(sizeof(int32_t));                            // invalid row pointers
   const int64_t big = 256 * T > n ? 256 * T : n;
   take(scan_scratch_elems(big) * sizeof(int64_t));
   return b + 256;
@@ -347,10 +384,13 @@ hipError_t launch_csr_transpose(bool f64, const int64_t* rowptr, const int32_t* 
   int32_t* H = (int32_t*)take((size_t)256 * T * 4);
   int64_t* Hs = (int64_t*)take(((size_t)256 * T + 1) * 8);
   int32_t* colcnt = (int32_t*)take((size_t)n * 4);
+  int* rpbad = (int*)take(4);
   int64_t* ss = (int64_t*)sp;
   hipError_t e;
   {
-    RowCheckP rc{rowptr, m, nnz, bad};
+    e = launch_fill_zero(rpbad, 4, s);
+    if (e != hipSuccess) return e;
+    RowCheckP rc{rowptr, m, nnz, bad, rpbad};
     e = launch_k(rowptr_check_kernel<false>, rowptr_check_kernel<true>, dim3((unsigned)((m + 1 + 255) / 256)),
                  dim3(256), s, rc);
     if (e != hipSuccess) return e;
@@ -378,7 +418,11 @@ hipError_t launch_csr_transpose(bool f64, const int64_t* rowptr, const int32_t* 
     }
     e = launch_fill_zero(colcnt, (size_t)n * 4, s);
     if (e != hipSuccess) return e;
-    FinishP fp{kin, pin, rowptr, vals, m, n, nnz, colcnt, idx_t, vals_t};
+    // the last pass's input keys are free: the row of every entry goes there
+    RowIdP ri{rowptr, m, rpbad, kout};
+    e = launch_k(rowid_kernel<false>, rowid_kernel<true>, dim3((unsigned)((m + 255) / 256)), dim3(256), s, ri);
+    if (e != hipSuccess) return e;
+    FinishP fp{kin, pin, kout, rowptr, rpbad, vals, m, n, nnz, colcnt, idx_t, vals_t};
     e = f64 ? launch_k(csr_finish_kernel<double, false>, csr_finish_kernel<double, true>,
                        dim3((unsigned)((nnz + 255) / 256)), dim3(256), s, fp)
             : launch_k(csr_finish_kernel<float, false>, csr_finish_kernel<float, true>,
