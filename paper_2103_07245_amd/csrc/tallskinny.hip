@@ -279,10 +279,12 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
     for (int e = 0; e < VV; ++e) {
       const double x0 = (double)cur[0][e], x1 = (double)cur[1][e];
       const double y0 = (double)cur[2][e], y1 = (double)cur[3][e];
+      // tiles wholly in the padding columns (lp < 32 nb) stay zero: skipped
+      // (block-uniform tests, lp is a multiple of 16)
       a00 = mma_f64(x0, y0, a00);
-      a01 = mma_f64(x0, y1, a01);
-      if (!dg) a10 = mma_f64(x1, y0, a10);
-      a11 = mma_f64(x1, y1, a11);
+      if (okJ1) a01 = mma_f64(x0, y1, a01);
+      if (!dg && okI1) a10 = mma_f64(x1, y0, a10);
+      if (okI1 && okJ1) a11 = mma_f64(x1, y1, a11);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)
