@@ -78,7 +78,7 @@ typedef struct {
                                heuristic), -1 = the built-in heuristic, > 0 forced */
   int gram_workgroups;      /* workgroups each Gram aims at (contraction splits x
                                column-block pairs): 0 = automatic (cached plan,
-                               else 512; in a batch a count-based default), > 0 forced */
+                               else 256; in a batch a count-based default), > 0 forced */
   double fp16_scale_a;      /* power of two applied to A in FP16 passes (0 -> 1)  */
   void* workspace;          /* device memory owned by the caller, or NULL: then the
                                library allocates stream-ordered and frees it after */

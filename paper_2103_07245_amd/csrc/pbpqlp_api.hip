@@ -211,7 +211,7 @@ struct Ctx {
   int mode_sketch = 0, mode_power = 0, mode_proj = 0;
   float fp16_scale = 1.0f;
   int forced_split = 0;
-  int gram_target = 512;   // Gram workgroups to aim at (fewer per problem in a batch)
+  int gram_target = 256;   // Gram workgroups to aim at (fewer per problem in a batch)
   uint64_t seed = 0;
   const void* omega_in = nullptr;  // caller's sketch matrix (row-major n x l), or generated
   int64_t ldo_in = 0;

@@ -314,11 +314,17 @@ __global__ __launch_bounds__(kCholThreads) void chol_kernel(const CholP* pb, Cho
   // G_IK -= R_JI^T R_JK for slot j (panel J in pnl[J & 1])
   auto update = [&](int j, int J, int I, int K) {
     double(*pn)[kMaxL + 1] = sh.pnl[J & 1];
+    // all eight operands requested before the first product
+    double xa[4], xb[4];
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
       const int kk = acc_row<double>(lg, s4);
-      t[j] = mma_f64(-pn[kk][16 * I + li], pn[kk][16 * K + li], t[j]);
+      xa[s4] = pn[kk][16 * I + li];
+      xb[s4] = pn[kk][16 * K + li];
     }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) t[j] = mma_f64(-xa[s4], xb[s4], t[j]);
   };
 
   if (w == 0) step_a(0, 0, 16);  // panel 0 belongs to wave 0 (RA = 0)
@@ -695,11 +701,18 @@ __global__ __launch_bounds__(kCholThreads) void chol_dw_kernel(const CholP* pb, 
       for (int j = 0; j < NS; ++j) {
         const int I = tile_i(j), K = tile_k(j);
         if (I > J1 && K < Tn) {
+          // all eight operands are requested before the first product (left
+          // to itself the scheduler waits out one LDS read per product)
+          double xa[4], xb[4];
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4) {
             const int kk = acc_row<double>(lg, s4);
-            t[j] = mma_f64(-pn[kk][16 * I + li], pn[kk][16 * K + li], t[j]);
+            xa[s4] = pn[kk][16 * I + li];
+            xb[s4] = pn[kk][16 * K + li];
           }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) t[j] = mma_f64(-xa[s4], xb[s4], t[j]);
         }
         if (j % 2 == 1) __builtin_amdgcn_sched_barrier(0);
       }

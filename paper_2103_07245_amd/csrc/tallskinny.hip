@@ -206,6 +206,9 @@ int gram_splits(int64_t len, int lp, int target) {
   const int np = npairs_of(nb);
   int64_t S = (target + np - 1) / np;            // aim at ~target workgroups
   const int64_t maxS = (len + 255) / 256;        // at least 256 rows per split
+  // a multiple of 8 (to the nearest) lets the kernel keep each row range on one XCD
+  const int64_t S8 = S < 8 ? 8 : (S + 4) / 8 * 8;
+  if (S8 <= maxS) S = S8;
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
   return (int)S;
@@ -235,13 +238,25 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
   const int lp = prm.lp;
   constexpr int VV = 16 / sizeof(T);
   constexpr int STEP = 4 * VV;  // contraction indices per slice (four lane groups)
-  const int p = blockIdx.x;
+  // block -> (pair p, row range sp).  Workgroups are dealt to the eight XCDs
+  // round-robin by linear id; when the split count is a multiple of 8 the np
+  // blocks of one row range go to the same XCD, whose L2 then serves their
+  // repeated reads of those rows (each column block is read by nb blocks).
+  int p = blockIdx.x, sp = blockIdx.y;
+  if constexpr (!B) {
+    if ((prm.gy & 7) == 0) {
+      const int L = blockIdx.x + prm.gx * blockIdx.y;
+      const int slot = L >> 3;
+      p = slot % prm.gx;
+      sp = (L & 7) + 8 * (slot / prm.gx);
+    }
+  }
   int bj = 0;
   while ((bj + 1) * (bj + 2) / 2 <= p) ++bj;
   const int bi = p - bj * (bj + 1) / 2;
   const bool dg = bi == bj;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
-  const int64_t kb = (int64_t)blockIdx.y * prm.kchunk, ke = min(len, kb + prm.kchunk);
+  const int64_t kb = (int64_t)sp * prm.kchunk, ke = min(len, kb + prm.kchunk);
   const int r0 = 32 * bi + li, r1 = r0 + 16, c0 = 32 * bj + li, c1 = c0 + 16;
   const T* pI0 = X + (int64_t)r0 * ld;
   const T* pI1 = X + (int64_t)r1 * ld;
@@ -260,8 +275,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
     }
   };
   f64x4 a00 = {0, 0, 0, 0}, a01 = a00, a10 = a00, a11 = a00;
-  // slices in flight: the current one and the next two of this wave
-  T cur[4][VV], nx[4][VV], nn[4][VV];
+  // masked loads (any iteration)
   auto load4 = [&](int64_t at, T (*dst)[VV]) __attribute__((always_inline)) {
     const int64_t k = at + lg * VV;
     ld_slice(pI0, okI0, k, dst[0]);
@@ -269,16 +283,31 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
     ld_slice(pJ0, okJ0, k, dst[2]);
     ld_slice(pJ1, okJ1, k, dst[3]);
   };
-  // wave-uniform trip count: lanes past the end load zeros
-  int64_t base = kb + (int64_t)wave * STEP;
-  if (base < ke) load4(base, cur);
-  if (base + 4 * STEP < ke) load4(base + 4 * STEP, nx);
-  for (; base < ke; base += 4 * STEP) {
-    if (base + 8 * STEP < ke) load4(base + 8 * STEP, nn);
+  // unconditional loads of an iteration that lies wholly in [kb, ke); a
+  // padding column block (r1 or c1 >= lp, uniform) reads its partner column,
+  // whose products are skipped
+  const T* qI1 = okI1 ? pI1 : pI0;
+  const T* qJ1 = okJ1 ? pJ1 : pJ0;
+  auto load4f = [&](int64_t at, T (*dst)[VV]) __attribute__((always_inline)) {
+    const int64_t k = at + lg * VV;
+    union { u32x4 v; T e[VV]; } u0, u1, u2, u3;
+    u0.v = ld16(pI0 + k);
+    u1.v = ld16(qI1 + k);
+    u2.v = ld16(pJ0 + k);
+    u3.v = ld16(qJ1 + k);
 #pragma unroll
     for (int e = 0; e < VV; ++e) {
-      const double x0 = (double)cur[0][e], x1 = (double)cur[1][e];
-      const double y0 = (double)cur[2][e], y1 = (double)cur[3][e];
+      dst[0][e] = u0.e[e];
+      dst[1][e] = u1.e[e];
+      dst[2][e] = u2.e[e];
+      dst[3][e] = u3.e[e];
+    }
+  };
+  auto compute = [&](const T (*c)[VV]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int e = 0; e < VV; ++e) {
+      const double x0 = (double)c[0][e], x1 = (double)c[1][e];
+      const double y0 = (double)c[2][e], y1 = (double)c[3][e];
       // tiles wholly in the padding columns (lp < 32 nb) stay zero: skipped
       // (block-uniform tests, lp is a multiple of 16)
       a00 = mma_f64(x0, y0, a00);
@@ -286,12 +315,44 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
       if (!dg && okI1) a10 = mma_f64(x1, y0, a10);
       if (okI1 && okJ1) a11 = mma_f64(x1, y1, a11);
     }
+  };
+  // Wave-uniform iterations i = 0 .. nit-1 over the slices starting at
+  // b0 + 4 STEP i; the first nfull lie wholly in [kb, ke).  Full iterations
+  // run with unconditional loads two iterations ahead in three rotating
+  // buffers (no masked load in the loop, so the wait before each iteration's
+  // products covers only its own loads); the rest run with masked loads.
+  const int64_t b0 = kb + (int64_t)wave * STEP;
+  const int nit = b0 < ke ? (int)((ke - b0 + 4 * STEP - 1) / (4 * STEP)) : 0;
+  const int nfull = b0 + STEP <= ke ? (int)((ke - b0 - STEP) / (4 * STEP)) + 1 : 0;
+  auto at = [&](int i) { return b0 + (int64_t)i * 4 * STEP; };
+  T B0[4][VV], B1[4][VV], B2[4][VV];
+  int it = 0;
+  if (nfull >= 5) {
+    load4f(at(0), B0);
+    load4f(at(1), B1);
+    do {
+      load4f(at(it + 2), B2);
+      compute(B0);
+      load4f(at(it + 3), B0);
+      compute(B1);
+      load4f(at(it + 4), B1);
+      compute(B2);
+      it += 3;
+    } while (it + 4 < nfull);
+  } else {
+    if (nit > 0) load4(at(0), B0);
+    if (nit > 1) load4(at(1), B1);
+  }
+  // the remaining iterations: B0 holds iteration it, B1 iteration it + 1
+  for (; it < nit; ++it) {
+    if (it + 2 < nit) load4(at(it + 2), B2);
+    compute(B0);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int e = 0; e < VV; ++e) {
-        cur[q][e] = nx[q][e];
-        nx[q][e] = nn[q][e];
+        B0[q][e] = B1[q][e];
+        B1[q][e] = B2[q][e];
       }
   }
   // sum the four waves' blocks in LDS (fixed order), write the 32x32 partial
@@ -306,7 +367,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
     red[wave][dg ? (16 + li) * 32 + row : (16 + row) * 32 + li] = dg ? a01[r] : a10[r];
   }
   __syncthreads();
-  double* out = prm.part + ((int64_t)blockIdx.y * prm.gx + p) * 1024;
+  double* out = prm.part + ((int64_t)sp * prm.gx + p) * 1024;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int e = tid + 256 * q;

@@ -137,7 +137,7 @@ pbpqlp_status pbpqlp_tune_factor(const void* A, int64_t m, int64_t n, int64_t ld
   base.workspace = nullptr;
   base.workspace_bytes = 0;
   const int splits[] = {0, 1, 2, 4, 8, 16};
-  const int grams[] = {0, 64, 256, 1024};
+  const int grams[] = {0, 64, 512, 1024};
   TunePlan best;
   best.ms = -1.0;
   pbpqlp_status s = PBPQLP_OK;
@@ -145,9 +145,9 @@ pbpqlp_status pbpqlp_tune_factor(const void* A, int64_t m, int64_t n, int64_t ld
     for (int gw : grams) {
       pbpqlp_opts o = base;
       // a trial plan is explicit: 0 would read the cache being filled; the
-      // heuristic split is marked by -1 and the default Gram target is 512
+      // heuristic split is marked by -1 and the default Gram target is 256
       o.split_k = sk;
-      o.gram_workgroups = gw == 0 ? 512 : gw;
+      o.gram_workgroups = gw == 0 ? 256 : gw;
       if (sk == 0) o.split_k = -1;
       double ms = 0.0;
       s = time_runs([&]() {
