@@ -100,18 +100,53 @@ __device__ __forceinline__ void apply_compute(typename Vec4<T>::type (&y)[NT], c
   typedef typename Vec4<T>::type ACC;
   constexpr auto& PH = kApplyPhases<NT, MAXT>;
   constexpr int J0 = PH.j0[P], J1 = PH.j1[P];
-  int t = 0;
+  if constexpr (NT >= (sizeof(T) == 8 ? 8 : 7)) {
+    // One wave per SIMD at these widths: the four operand values of tile
+    // t + 1 are read from LDS before the products of tile t (left to itself
+    // the scheduler waited out one LDS read per pair of products).  Narrower
+    // operands run several waves per SIMD, which hide that latency, and the
+    // extra operand registers would cost one of them.
+    int nt = 0;
 #pragma unroll
-  for (int J = J0; J < J1; ++J) {
-    ACC q = {0, 0, 0, 0};
+    for (int J = J0; J < J1; ++J) nt += NT - J;
+    T a[2][4];
+    auto fetch = [&](int tt) __attribute__((always_inline)) {
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) q = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], y[J][s4], q);
-    y[J] = q;
-    ++t;
+      for (int s4 = 0; s4 < 4; ++s4) a[tt & 1][s4] = ops[tt * kTile + acc_row<T>(lg, s4) * 17 + li];
+    };
+    fetch(0);
+    int t = 0;
 #pragma unroll
-    for (int K = J + 1; K < NT; ++K, ++t)
+    for (int J = J0; J < J1; ++J) {
+      if (t + 1 < nt) fetch(t + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      ACC q = {0, 0, 0, 0};
 #pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) y[K] = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], q[s4], y[K]);
+      for (int s4 = 0; s4 < 4; ++s4) q = mma_native(a[t & 1][s4], y[J][s4], q);
+      y[J] = q;
+      ++t;
+#pragma unroll
+      for (int K = J + 1; K < NT; ++K, ++t) {
+        if (t + 1 < nt) fetch(t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) y[K] = mma_native(a[t & 1][s4], q[s4], y[K]);
+      }
+    }
+  } else {
+    int t = 0;
+#pragma unroll
+    for (int J = J0; J < J1; ++J) {
+      ACC q = {0, 0, 0, 0};
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) q = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], y[J][s4], q);
+      y[J] = q;
+      ++t;
+#pragma unroll
+      for (int K = J + 1; K < NT; ++K, ++t)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) y[K] = mma_native(ops[t * kTile + acc_row<T>(lg, s4) * 17 + li], q[s4], y[K]);
+    }
   }
 }
 
@@ -389,15 +424,36 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const RightMulP* pb, Rig
       __builtin_amdgcn_sched_barrier(0);  // at most one row block of loads in flight
     }
     lds_barrier();
+    if constexpr (NT >= (sizeof(T) == 8 ? 8 : 7) && (sizeof(T) == 8 || NT < 16)) {
+      // one wave per SIMD: tile t + 1's operands are read before tile t's
+      // products (as in apply_compute; FP32 at 16 tiles already spills)
+      const int I1 = I0 + RPP < NT ? I0 + RPP : NT;
+      const int nt = (I1 - I0) * NT;
+      T a[2][4];
+      auto fetch = [&](int tt) __attribute__((always_inline)) {
 #pragma unroll
-    for (int I = I0; I < I0 + RPP && I < NT; ++I) {
+        for (int s4 = 0; s4 < 4; ++s4) a[tt & 1][s4] = ops[tt * kTile + acc_row<T>(lg, s4) * 17 + li];
+      };
+      fetch(0);
 #pragma unroll
-      for (int J = 0; J < NT; ++J)
+      for (int t = 0; t < nt; ++t) {
+        if (t + 1 < nt) fetch(t + 1);
+        __builtin_amdgcn_sched_barrier(0);
+        const int I = I0 + t / NT, J = t % NT;
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-          acc[J] = mma_native(ops[((I - I0) * NT + J) * kTile + acc_row<T>(lg, s4) * 17 + li], x[I][s4], acc[J]);
-      // bound the LDS operands in flight to one row block
-      __builtin_amdgcn_sched_barrier(0);
+        for (int s4 = 0; s4 < 4; ++s4) acc[J] = mma_native(a[t & 1][s4], x[I][s4], acc[J]);
+      }
+    } else {
+#pragma unroll
+      for (int I = I0; I < I0 + RPP && I < NT; ++I) {
+#pragma unroll
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4)
+            acc[J] = mma_native(ops[((I - I0) * NT + J) * kTile + acc_row<T>(lg, s4) * 17 + li], x[I][s4], acc[J]);
+        // bound the LDS operands in flight to one row block
+        __builtin_amdgcn_sched_barrier(0);
+      }
     }
   }
 #pragma unroll
