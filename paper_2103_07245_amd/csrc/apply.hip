@@ -235,15 +235,9 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps)
     apply_stage<T, NT, MAXT, 0>(ops, Ra, Dinv, lp, tid);
     lds_barrier();
   }
-  for (int rt = 0; rt < rtiles; ++rt) {
+  auto finish = [&](int rt, ACC (&y)[NT]) __attribute__((always_inline)) {
     const int64_t arow = (((int64_t)blockIdx.x * rtiles + rt) * 4 + wave) * 16 + li;
     const bool in = arow < len;
-    ACC y[NT];
-#pragma unroll
-    for (int K = 0; K < NT; ++K)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        y[K][r] = in ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
     if (!ident) {
       if constexpr (single)
         apply_compute<T, NT, MAXT, 0>(y, ops, li, lg);
@@ -261,6 +255,46 @@ __global__ __launch_bounds__(256) void apply_kernel(const ApplyP* pb, ApplyP ps)
         }
         if (Qrm && in && c < l) Qrm[arow * ldqr + c] = y[J][r];
       }
+  };
+  if constexpr (single && NT * sizeof(T) <= 32) {
+    // Narrow operands, several row tiles per block: the next tile's rows are
+    // requested before the current tile's products.  The loads take no
+    // branch (rows past len read row len - 1, whose values are replaced by
+    // zeros), so the wait before a tile's products covers only its own loads.
+    auto load_tile = [&](int rt, ACC (&dst)[NT]) __attribute__((always_inline)) {
+      const int64_t arow = (((int64_t)blockIdx.x * rtiles + rt) * 4 + wave) * 16 + li;
+      const bool in = arow < len;
+      const int64_t rc = in ? arow : len - 1;
+#pragma unroll
+      for (int K = 0; K < NT; ++K)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const T v = Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + rc];
+          dst[K][r] = in ? v : T(0);
+        }
+    };
+    ACC ya[NT], yb[NT];
+    load_tile(0, ya);
+    for (int rt = 0; rt < rtiles; rt += 2) {
+      load_tile(rt + 1 < rtiles ? rt + 1 : rt, yb);
+      finish(rt, ya);
+      if (rt + 1 < rtiles) {
+        load_tile(rt + 2 < rtiles ? rt + 2 : rt + 1, ya);
+        finish(rt + 1, yb);
+      }
+    }
+  } else {
+    for (int rt = 0; rt < rtiles; ++rt) {
+      const int64_t arow = (((int64_t)blockIdx.x * rtiles + rt) * 4 + wave) * 16 + li;
+      const bool in = arow < len;
+      ACC y[NT];
+#pragma unroll
+      for (int K = 0; K < NT; ++K)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          y[K][r] = in ? Y[(int64_t)(16 * K + acc_row<T>(lg, r)) * ldy + arow] : T(0);
+      finish(rt, y);
+    }
   }
 }
 
@@ -474,6 +508,7 @@ static hipError_t apply_launch(const void* Y, int64_t ldy, int64_t len, int lp, 
                                const void* Dinv, const int* dep, uint64_t seed, void* Qcm, int64_t ldq,
                                void* Qrm, int64_t ldqr, hipStream_t s, int64_t wq, const int* ident,
                                const Emit16& em) {
+  if (len < 1) return hipErrorInvalidValue;  // the row-tile loads assume a first row
   CompleteP c{(void*)Y, ldy, len, l, lp, dep, seed};
   hipError_t e = launch_k(complete_kernel<T, false>, complete_kernel<T, true>, dim3((unsigned)((len + 255) / 256)),
                           dim3(256), s, c);

@@ -206,9 +206,12 @@ int gram_splits(int64_t len, int lp, int target) {
   const int np = npairs_of(nb);
   int64_t S = (target + np - 1) / np;            // aim at ~target workgroups
   const int64_t maxS = (len + 255) / 256;        // at least 256 rows per split
-  // a multiple of 8 (to the nearest) lets the kernel keep each row range on one XCD
-  const int64_t S8 = S < 8 ? 8 : (S + 4) / 8 * 8;
-  if (S8 <= maxS) S = S8;
+  // from 8 splits up, a multiple of 8 (to the nearest) lets the kernel keep
+  // each row range on one XCD
+  if (S >= 8) {
+    const int64_t S8 = (S + 4) / 8 * 8;
+    if (S8 <= maxS) S = S8;
+  }
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
   return (int)S;
@@ -317,17 +320,20 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const GramP* pb, Gram
     }
   };
   // Wave-uniform iterations i = 0 .. nit-1 over the slices starting at
-  // b0 + 4 STEP i; the first nfull lie wholly in [kb, ke).  Full iterations
-  // run with unconditional loads two iterations ahead in three rotating
-  // buffers (no masked load in the loop, so the wait before each iteration's
-  // products covers only its own loads); the rest run with masked loads.
+  // b0 + 4 STEP i; the first nfull lie wholly in [kb, ke).  For FP32, full
+  // iterations run with unconditional loads two iterations ahead in three
+  // rotating buffers (no masked load in the loop, so the wait before each
+  // iteration's products covers only its own loads); the rest run with
+  // masked loads.  FP64 keeps the masked loop throughout: on the wide
+  // L2-bound Grams (thousands of block pairs) the deeper effective prefetch
+  // made it slower (l = 7500: 14.6 -> 19.0 ms per launch).
   const int64_t b0 = kb + (int64_t)wave * STEP;
   const int nit = b0 < ke ? (int)((ke - b0 + 4 * STEP - 1) / (4 * STEP)) : 0;
   const int nfull = b0 + STEP <= ke ? (int)((ke - b0 - STEP) / (4 * STEP)) + 1 : 0;
   auto at = [&](int i) { return b0 + (int64_t)i * 4 * STEP; };
   T B0[4][VV], B1[4][VV], B2[4][VV];
   int it = 0;
-  if (nfull >= 5) {
+  if (sizeof(T) == 4 && nfull >= 5) {
     load4f(at(0), B0);
     load4f(at(1), B1);
     do {
