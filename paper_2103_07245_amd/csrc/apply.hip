@@ -77,6 +77,38 @@ template <int NT, int MAXT> inline constexpr ApplyPhases<NT, MAXT> kApplyPhases{
 template <int NT, int MAXT>
 inline constexpr int kOpTiles = NT * (NT + 1) / 2 < MAXT ? NT * (NT + 1) / 2 : MAXT;
 
+// Row-major output of one wave's 16 rows (lane li: row arow; columns < l).
+// An FP32 accumulator register r of lane group g holds column 4 g + r of the
+// tile, so a lane's four registers are four consecutive columns of its row:
+// one 16-byte store where the row is 16-byte aligned and the four columns
+// are live, else one store per element.
+template <typename T, int NT>
+__device__ __forceinline__ void store_rows(T* __restrict__ O, int64_t ldo, int64_t arow, bool in, int l, int lg,
+                                           const typename Vec4<T>::type (&v)[NT]) {
+  if constexpr (sizeof(T) == 4) {
+    const bool vec = (ldo & 3) == 0 && ((uintptr_t)O & 15) == 0;  // uniform
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+      const int c0 = 16 * J + 4 * lg;
+      if (vec && in && c0 + 3 < l) {
+        *(typename Vec4<T>::type*)(O + arow * ldo + c0) = v[J];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (in && c0 + r < l) O[arow * ldo + c0 + r] = v[J][r];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int J = 0; J < NT; ++J)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 16 * J + acc_row<T>(lg, r);
+        if (in && c < l) O[arow * ldo + c] = v[J][r];
+      }
+  }
+}
+
 // Staging of phase P (row blocks J0 .. J1-1 of the operand) into LDS: one
 // element of each tile per thread.
 template <typename T, int NT, int MAXT, int P>
@@ -496,8 +528,8 @@ __global__ __launch_bounds__(256) void right_mul_kernel(const RightMulP* pb, Rig
     for (int r = 0; r < 4; ++r) {
       const int c = 16 * J + acc_row<T>(lg, r);
       if (Ocm && arow < ldo) Ocm[(int64_t)c * ldo + arow] = acc[J][r];
-      if (Orm && in && c < l) Orm[arow * ldor + c] = acc[J][r];
     }
+  if (Orm) store_rows<T, NT>(Orm, ldor, arow, in, l, lg, acc);
 }
 
 // ---------------------------------------------------------------------------
