@@ -163,7 +163,7 @@ __device__ __forceinline__ void store_rows(T* out, int64_t ld, int64_t col, int6
   }
 }
 
-// Rows of A that K1 block blockIdx.x (of gx) multiplies: the m rows are cut
+// Rows of A that K1 block b (of gx) multiplies: the m rows are cut
 // into 16-row groups, block b takes groups [b N / gx, (b + 1) N / gx) of the
 // N = ceil(m / 16), i.e. its rows [16 g0, rend), and wave w sub-tile rt the
 // group g0 + rt NW + w (first row tile_r[rt]; groups past the block's end are
@@ -173,11 +173,11 @@ __device__ __forceinline__ void store_rows(T* out, int64_t ld, int64_t col, int6
 // go round the waves, so the two waves that share a SIMD (w, w + 4) hold
 // every fourth group and a block short of groups still keeps its SIMDs even.
 template <int NW, int RT>
-__device__ __forceinline__ void k1_rows(int64_t m, unsigned gx, int wave, int64_t& g0, int64_t& rend,
+__device__ __forceinline__ void k1_rows(int64_t m, unsigned b, unsigned gx, int wave, int64_t& g0, int64_t& rend,
                                         int64_t* tile_r) {
   const int64_t ngr = (m + 15) >> 4;
-  g0 = (int64_t)blockIdx.x * ngr / gx;
-  const int64_t g1 = ((int64_t)blockIdx.x + 1) * ngr / gx;
+  g0 = (int64_t)b * ngr / gx;
+  const int64_t g1 = ((int64_t)b + 1) * ngr / gx;
   rend = min(m, 16 * g1);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) tile_r[rt] = 16 * (g0 + rt * NW + wave);
@@ -216,6 +216,21 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
   bool past;
   const StreamParams p = kparams<B>(pb, ps, past);
   if (past) return;
+  // Block order (single launches): workgroups are dealt to the eight XCDs
+  // round-robin by linear id.  With a grid of a multiple of 8 blocks, XCD x
+  // takes the x-th eighth of them in split-major order, so it reads the rows
+  // of the l-column operand of one or two splits, which then stay in its L2
+  // instead of every XCD fetching every split's rows.
+  unsigned bx = blockIdx.x, by = blockIdx.y;
+  if constexpr (!B) {
+    const unsigned N = p.gx * p.gy;
+    if ((N & 7) == 0) {
+      const unsigned L = blockIdx.x + p.gx * blockIdx.y;
+      const unsigned g = (L & 7) * (N >> 3) + (L >> 3);
+      bx = g % p.gx;
+      by = g / p.gx;
+    }
+  }
   typedef Tr<MODE> TR;
   typedef typename TR::TA TA;
   typedef typename TR::TC TC;
@@ -245,9 +260,9 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
   const TC* __restrict__ Xl = (const TC*)p.Xlo;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lg = lane >> 4;
   // A-side position of this lane: K1 a row of A per (rt), K2 RT columns.
-  const int64_t a0 = ((int64_t)blockIdx.x * NW + wave) * (16 * RT);
+  const int64_t a0 = ((int64_t)bx * NW + wave) * (16 * RT);
   const int64_t alen = TRANS ? p.n : p.m;           // extent of the A-side dimension
-  const int64_t kb = (int64_t)blockIdx.y * p.chunk;
+  const int64_t kb = (int64_t)by * p.chunk;
   const int64_t ke = min(TRANS ? p.m : p.n, kb + p.chunk);
   const int nst = (int)((ke - kb + KC - 1) / KC);
   // K2 needs RT columns for its paired loads; a narrower A runs masked only
@@ -257,7 +272,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
   // clamped A-side indices (always valid memory), validity kept for normA.
   int64_t g0 = 0, rend = alen, tile_r[RT], arow[RT];
   bool rowok[RT];
-  if constexpr (!TRANS) k1_rows<NW, RT>(p.m, p.gx, wave, g0, rend, tile_r);
+  if constexpr (!TRANS) k1_rows<NW, RT>(p.m, bx, p.gx, wave, g0, rend, tile_r);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     if constexpr (TRANS) tile_r[rt] = a0 + 16 * rt;
@@ -483,7 +498,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
   for (; s + 1 < nfull; ++s) stage(s, std::true_type());
   for (; s < nst; ++s) stage(s, std::false_type());
 
-  TACC* out = (TACC*)p.out + (int64_t)blockIdx.y * p.split_stride;
+  TACC* out = (TACC*)p.out + (int64_t)by * p.split_stride;
   const int Tst = p.lp >> 4;
   if constexpr (!TRANS) {
 #pragma unroll
@@ -523,7 +538,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_kernel(const Stre
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < NW; ++w) t += red[w];
-      p.normA[blockIdx.y * p.gx + blockIdx.x] = t;
+      p.normA[by * p.gx + bx] = t;
     }
   }
 }
@@ -581,7 +596,7 @@ __global__ __launch_bounds__(64 * Tr<MODE>::NW, 2) void stream_k1_kernel(const S
   const int nfull = (int)((ke - kb) / KC);
   int64_t g0, rend, tile_r[RT], arow[RT];
   bool rowok[RT];
-  k1_rows<NW, RT>(p.m, p.gx, wave, g0, rend, tile_r);
+  k1_rows<NW, RT>(p.m, blockIdx.x, p.gx, wave, g0, rend, tile_r);
 #pragma unroll
   for (int rt = 0; rt < RT; ++rt) {
     const int64_t r = tile_r[rt] + li;
